@@ -1,0 +1,88 @@
+"""The five workloads: sizes, field parameters, step limits and stops.
+
+Values follow the workload descriptions of this project; entries marked
+"chosen" fill parameters those descriptions leave open.  Lengths are in Mpc,
+energies in eV, fields in nG.  A workload with ``n_realisations > 0`` is a
+batch of independent field realisations, each with its own B_rms, particle
+count and observer radius.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+
+def mass_number(z: int) -> int:
+    """Mass number used for a charge number: A = 1 for protons, else A = 2Z.
+
+    The mass number is carried through the state but does not enter the
+    dynamics at these energies (beta = 1 to better than 1e-13).
+    """
+    z = abs(int(z))
+    return 1 if z == 1 else 2 * z
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    index: int
+    n_particles: int
+    charges: tuple
+    e_min: float
+    e_max: float
+    grid_n: int
+    spacing: float
+    l_min: float
+    l_max: float
+    b_rms: float
+    grid_dtype: str          # storage dtype of the device grid: f64 | f32 | f16 | bf16
+    tol: float
+    h_min: float
+    h_max: float
+    obs_radius: float        # <= 0: no observer sphere
+    max_length: float        # math.inf: no length limit
+    charge_rule: str = "uniform"
+    n_realisations: int = 0
+    b_rms_range: tuple = (0.0, 0.0)
+    count_range: tuple = (0, 0)
+    radius_range: tuple = (0.0, 0.0)
+    checkpoint_every: int = 0
+
+    @property
+    def box(self) -> float:
+        return self.grid_n * self.spacing
+
+
+MIXED = (1, 2, 7, 26)
+
+CONFIGS = (
+    # 1,000 protons at 1 EeV in a 32^3 FP64 grid; stop at 50 Mpc of path.
+    Workload("small_fp64_32cube", 0, 1000, (1,), 1e18, 1e18, 32, 0.1, 0.2, 1.6, 1.0, "f64",
+             1e-4, 0.01, 1.0, 0.0, 50.0),
+    # 1e6 mixed nuclei, 256^3 FP32 grid; stop at r = 20 Mpc or 1 Gpc of path.
+    Workload("production_256cube", 1, 1_000_000, MIXED, 1e18, 1e20, 256, 0.05, 0.1, 5.0, 1.0, "f32",
+             1e-4, 0.001, 1.0, 20.0, 1000.0),
+    # 64 realisations of 64^3 FP32 grids; spacing, band, tol, step limits and L_max chosen.
+    Workload("batched_64x64cube", 2, 0, MIXED, 1e17, 1e20, 64, 0.05, 0.1, 1.6, 1.0, "f32",
+             1e-4, 0.001, 1.0, 0.0, 1000.0, n_realisations=64, b_rms_range=(0.1, 10.0),
+             count_range=(100, 100_000), radius_range=(1.0, 50.0)),
+    # 4e6 mixed nuclei, 1024^3 grid stored FP16/BF16 (or FP32); tol, step limits and L_max chosen.
+    Workload("precision_1024cube", 3, 4_000_000, MIXED, 1e18, 1e20, 1024, 0.01, 0.02, 2.0, 1.0, "f16",
+             1e-4, 0.001, 1.0, 10.0, 1000.0),
+    # 1e5 protons and iron, 128^3 FP32 grid; band, tol, step limits and L_max chosen.
+    Workload("adjoint_128cube", 4, 100_000, (1, 26), 1e18, 1e19, 128, 0.05, 0.1, 3.2, 1.0, "f32",
+             1e-4, 0.001, 1.0, 10.0, 1000.0, charge_rule="alternate", checkpoint_every=64),
+)
+
+
+def get_config(key) -> Workload:
+    """Look a workload up by index or by name."""
+    if isinstance(key, int):
+        return CONFIGS[key]
+    for w in CONFIGS:
+        if w.name == key:
+            return w
+    raise KeyError(key)
+
+
+assert all(math.isfinite(w.max_length) for w in CONFIGS)

@@ -1,0 +1,614 @@
+/*
+ * crp_oracle.c -- plain FP64 CPU reference for charged-particle propagation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline of the benchmark may load this library.  It shares no code,
+ * header, table or constant with the GPU library: every coefficient and
+ * constant below is written here from its published definition.
+ *
+ * What it computes (paper: "Cosmic ray propagation with CRPropa 3"):
+ *   - the 3D mode, in which charged nuclei are deflected by a magnetic field
+ *     (section 2), sampled on a regular periodic vector grid (section 3.2);
+ *   - one particle at a time, advanced by steps whose length is the lowest
+ *     bid among all participants (section 3.1, bidding system): the error
+ *     controlled integrator, the step limits, the distance to the observer
+ *     sphere and the remaining trajectory length;
+ *   - the step is the largest one that keeps the user's accuracy (section 3.1);
+ *   - no energy losses, as for galactic propagation (section 3.3);
+ *   - propagation ends when it is "completed or aborted" (section 3.1) at an
+ *     observer sphere or at a maximum trajectory length.
+ *
+ * The paper names no integrator, interpolation, error norm or controller.
+ * The readings taken (all listed with their reasons in the design notes):
+ *   - equation of motion in path length s: dx/ds = u, du/ds = kappa u x B(x),
+ *     kappa = Z*K/E, K = c * 1e-13 T/nG * 1 Mpc (positions in Mpc, B in nG,
+ *     E in eV; beta = 1, the mass number does not enter);
+ *   - Cash-Karp embedded Runge-Kutta 5(4) (Cash & Karp 1990, ACM TOMS 16:201),
+ *     propagating the 5th-order solution;
+ *   - trilinear interpolation on the periodic grid, x then y then z;
+ *   - error = max(|delta_u|, |delta_x|/h) / tol; accept when <= 1 or h <= h_min;
+ *   - step controller with safety 0.9, growth <= 5, shrink >= 0.1, exponents
+ *     -1/5 (grow) and -1/4 (shrink) (Numerical Recipes section 16.2; Hairer,
+ *     Norsett & Wanner II.4);
+ *   - event location of the sphere crossing by the Illinois variant of
+ *     regula falsi (Dowell & Jarratt 1971) on the Cash-Karp step map, keeping
+ *     the bracket end outside the sphere as the crossing point.
+ *
+ * Arithmetic is IEEE FP64, round to nearest even, compiled with
+ * -ffp-contract=off; fused multiply-adds appear only where fma() is written.
+ * The fifth root in the controller is a fixed Newton iteration rather than
+ * pow(), so that the result does not depend on a math library.
+ *
+ * Parity pins: see the oracle tests (closed-form helix, straight line,
+ * affine-field interpolation, order conditions, brute-force integration,
+ * invariants, stop semantics).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- physical constants ------------------------------------------------ */
+/* K = c * 1e-13 * Mpc_in_m, with c = 299792458 m/s and
+ * 1 Mpc = 1e6 * (648000/pi) * 149597870700 m (IAU 2012/2015 definitions).
+ * kappa * B = 1/r_gyro for B in nG, E in eV, r in Mpc. */
+static const double K_LORENTZ = 9.250628667507923e17;
+/* Seconds per Mpc of path at the speed of light: Mpc_in_m / c. */
+static const double MPC_OVER_C = 102927125054339.0;
+
+/* ---- Cash-Karp 5(4) tableau ------------------------------------------- */
+static const double CK_A[6][5] = {
+    {0.0, 0.0, 0.0, 0.0, 0.0},
+    {1.0 / 5.0, 0.0, 0.0, 0.0, 0.0},
+    {3.0 / 40.0, 9.0 / 40.0, 0.0, 0.0, 0.0},
+    {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0.0, 0.0},
+    {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0.0},
+    {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0},
+};
+static const double CK_C[6] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 3.0 / 5.0, 1.0, 7.0 / 8.0};
+/* fifth-order weights */
+static const double CK_B5[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0, 512.0 / 1771.0};
+/* fourth-order weights */
+static const double CK_B4[6] = {2825.0 / 27648.0, 0.0, 18575.0 / 48384.0, 13525.0 / 55296.0,
+                                277.0 / 14336.0, 1.0 / 4.0};
+/* error weights b5 - b4, each the rounded exact rational difference */
+static const double CK_E[6] = {-277.0 / 64512.0, 0.0, 6925.0 / 370944.0, -6925.0 / 202752.0,
+                               -277.0 / 14336.0, 277.0 / 7084.0};
+
+/* 2^(-j/5), j = 0..4, rounded to nearest FP64 (checked against mpmath). */
+static const double TWO_POW_NEG_FIFTHS[5] = {
+    0x1.0000000000000p+0, 0x1.bdb8cdadbe120p-1, 0x1.8406003b2ae5cp-1,
+    0x1.51cb453b9536cp-1, 0x1.2611186bae675p-1};
+
+/* status codes of a particle */
+enum { ST_ACTIVE = 0, ST_ARRIVED = 1, ST_MAX_LENGTH = 2, ST_MAX_STEPS = 3,
+       ST_NONFINITE = 4, ST_CANCELLED = 5, ST_BAD_INPUT = 6 };
+
+/* ---- the periodic vector grid ----------------------------------------- */
+typedef struct {
+    int64_t n[3];
+    double origin[3];
+    double inv_spacing;      /* 1.0 / spacing, one FP64 division */
+    const double *v64;       /* [n0][n1][n2][3], nG; exactly one of v64/v32 set */
+    const float *v32;
+} grid_t;
+
+static double grid_value(const grid_t *g, int64_t i, int64_t j, int64_t k, int c)
+{
+    int64_t idx = ((i * g->n[1] + j) * g->n[2] + k) * 3 + c;
+    return g->v64 ? g->v64[idx] : (double)g->v32[idx];
+}
+
+static int64_t pmod(int64_t a, int64_t n)
+{
+    int64_t r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+/* linear interpolation a + t (b - a), one fused multiply-add */
+static double lerp(double a, double b, double t) { return fma(t, b - a, a); }
+
+/* Trilinear interpolation of the periodic grid at X (Mpc) -> B (nG).
+ * Cell index i0 = floor(f), f = (X - origin) / spacing (as a product with the
+ * reciprocal), fraction t = f - floor(f); corners i0 and i0 + 1, wrapped.
+ * Interpolate along x first, then y, then z. */
+static void field_at(const grid_t *g, const double X[3], double B[3])
+{
+    int64_t i0[3], i1[3];
+    double t[3];
+    for (int a = 0; a < 3; ++a) {
+        double f = (X[a] - g->origin[a]) * g->inv_spacing;
+        if (!(fabs(f) < 4.0e15)) {          /* NaN or absurd position */
+            B[0] = B[1] = B[2] = NAN;
+            return;
+        }
+        double fl = floor(f);
+        t[a] = f - fl;
+        i0[a] = pmod((int64_t)fl, g->n[a]);
+        i1[a] = pmod(i0[a] + 1, g->n[a]);
+    }
+    for (int c = 0; c < 3; ++c) {
+        double v000 = grid_value(g, i0[0], i0[1], i0[2], c);
+        double v100 = grid_value(g, i1[0], i0[1], i0[2], c);
+        double v010 = grid_value(g, i0[0], i1[1], i0[2], c);
+        double v110 = grid_value(g, i1[0], i1[1], i0[2], c);
+        double v001 = grid_value(g, i0[0], i0[1], i1[2], c);
+        double v101 = grid_value(g, i1[0], i0[1], i1[2], c);
+        double v011 = grid_value(g, i0[0], i1[1], i1[2], c);
+        double v111 = grid_value(g, i1[0], i1[1], i1[2], c);
+        double c00 = lerp(v000, v100, t[0]);
+        double c10 = lerp(v010, v110, t[0]);
+        double c01 = lerp(v001, v101, t[0]);
+        double c11 = lerp(v011, v111, t[0]);
+        double c0 = lerp(c00, c10, t[1]);
+        double c1 = lerp(c01, c11, t[1]);
+        B[c] = lerp(c0, c1, t[2]);
+    }
+}
+
+/* Right-hand side of the Lorentz-force system in path length:
+ * y = (x, u) -> (u, kappa * u x B(x)). */
+static void rhs(const grid_t *g, double kappa, const double Y[6], double k[6])
+{
+    double B[3];
+    field_at(g, Y, B);
+    k[0] = Y[3];
+    k[1] = Y[4];
+    k[2] = Y[5];
+    double cx = Y[4] * B[2] - Y[5] * B[1];
+    double cy = Y[5] * B[0] - Y[3] * B[2];
+    double cz = Y[3] * B[1] - Y[4] * B[0];
+    k[3] = kappa * cx;
+    k[4] = kappa * cy;
+    k[5] = kappa * cz;
+}
+
+/* One Cash-Karp evaluation of step h from y: the fifth-order solution y5
+ * and the embedded error vector delta = h * sum_i (b5_i - b4_i) k_i.
+ * Stage sums run over j in increasing order with fma, starting from zero. */
+static void ck_eval(const grid_t *g, double kappa, const double y[6], double h,
+                    double y5[6], double delta[6])
+{
+    double k[6][6];
+    for (int i = 0; i < 6; ++i) {
+        double Y[6];
+        for (int c = 0; c < 6; ++c) {
+            if (i == 0) {
+                Y[c] = y[c];
+                continue;
+            }
+            double acc = 0.0;
+            for (int j = 0; j < i; ++j)
+                acc = fma(CK_A[i][j], k[j][c], acc);
+            Y[c] = fma(h, acc, y[c]);
+        }
+        rhs(g, kappa, Y, k[i]);
+    }
+    for (int c = 0; c < 6; ++c) {
+        double a5 = 0.0, ae = 0.0;
+        for (int i = 0; i < 6; ++i) {
+            a5 = fma(CK_B5[i], k[i][c], a5);
+            ae = fma(CK_E[i], k[i][c], ae);
+        }
+        y5[c] = fma(h, a5, y[c]);
+        delta[c] = h * ae;
+    }
+}
+
+static double norm3(const double v[3]) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+/* err^(-1/5) for finite err > 0 without pow(): err = m 2^e with m in [0.5, 1),
+ * e = 5q + j (floor division, j in 0..4); r -> m^(-1/5) by exactly six Newton
+ * steps r <- r (6 - m r^5) / 5 on r^-5 - m = 0 from r = 1 (monotone from
+ * below); result r * 2^(-j/5) * 2^(-q). */
+static double inv_fifth_root(double err)
+{
+    int e;
+    double m = frexp(err, &e);
+    int q = e >= 0 ? e / 5 : -((-e + 4) / 5);
+    int j = e - 5 * q;
+    double r = 1.0;
+    for (int it = 0; it < 6; ++it) {
+        double r2 = r * r;
+        double r5 = (r2 * r2) * r;
+        r = r * (6.0 - m * r5) * 0.2;
+    }
+    return ldexp(r * TWO_POW_NEG_FIFTHS[j], -q);
+}
+
+/* ---- propagation parameters ------------------------------------------- */
+typedef struct {
+    double tol, h_min, h_max;
+    double center[3];
+    double radius;        /* <= 0: no observer sphere */
+    double l_max;         /* +inf: no length limit */
+    int64_t max_steps;    /* accepted steps allowed in this call; 0 = no limit */
+} params_t;
+
+static double sphere_g(const params_t *p, const double x[3])
+{
+    double d0 = x[0] - p->center[0], d1 = x[1] - p->center[1], d2 = x[2] - p->center[2];
+    return (d0 * d0 + d1 * d1 + d2 * d2) - p->radius * p->radius;
+}
+
+static int all_finite(const double *v, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(v[i]))
+            return 0;
+    return 1;
+}
+
+/* Per-particle outcome counters summed by the caller. */
+typedef struct {
+    int64_t evals;        /* Cash-Karp evaluations (6 field lookups each) */
+    int64_t accepted, rejected, event_evals, floor_hits;
+} counts_t;
+
+/* Optional tape of accepted step sizes (for the adjoint); NULL = none. */
+typedef struct {
+    double *h;            /* accepted step sizes, in order */
+    int64_t cap, len;
+    double s_event;       /* event step s* (0 if no event) */
+    int event;            /* 1 if the run ended by sphere crossing */
+    int length_bound;     /* 1 if the last accepted step was the length bid */
+} tape_t;
+
+/* Propagate one particle in place.  State y = (x, u); L = path length;
+ * *h_next = controller bid carried between calls (0 = fresh start). */
+static int propagate_one(const grid_t *g, const params_t *p, double y[6], double energy,
+                         int32_t charge, double *L, double *h_next, int64_t *n_acc,
+                         int64_t *n_rej, counts_t *cnt, tape_t *tape)
+{
+    const int sphere = p->radius > 0.0;
+    const int lmax_on = isfinite(p->l_max);
+    const double R2 = p->radius * p->radius;
+
+    if (!(energy > 0.0) || !isfinite(energy) || !all_finite(y, 6) || !isfinite(*L) ||
+        !(*h_next >= 0.0) || !isfinite(*h_next))
+        return ST_BAD_INPUT;
+
+    double hctrl;
+    if (*h_next == 0.0) {                  /* fresh start: unit direction, first bid h_max */
+        double n2 = y[3] * y[3] + y[4] * y[4] + y[5] * y[5];
+        if (!(n2 > 0.0))
+            return ST_BAD_INPUT;
+        double nrm = sqrt(n2);
+        y[3] = y[3] / nrm;
+        y[4] = y[4] / nrm;
+        y[5] = y[5] / nrm;
+        hctrl = p->h_max;
+    } else {
+        hctrl = *h_next;
+    }
+    if (sphere && sphere_g(p, y) >= 0.0)
+        return ST_ARRIVED;
+    if (lmax_on && *L >= p->l_max)
+        return ST_MAX_LENGTH;
+
+    const double kappa = ((double)charge * K_LORENTZ) / energy;
+    int64_t steps_this_call = 0;
+
+    for (;;) {
+        /* bids: controller, h_max, sphere distance (all floored by h_min),
+         * then the remaining length (not floored) */
+        double h = hctrl;
+        if (h > p->h_max) h = p->h_max;
+        if (sphere) {
+            double d0 = y[0] - p->center[0], d1 = y[1] - p->center[1], d2 = y[2] - p->center[2];
+            double dist = p->radius - sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            if (dist < h) h = dist;
+        }
+        if (h < p->h_min) h = p->h_min;
+        int binding = 0;
+        if (lmax_on) {
+            double rem = p->l_max - *L;
+            if (rem <= h) {
+                h = rem;
+                binding = 1;
+            }
+        }
+
+        /* attempts until accepted */
+        double y5[6], delta[6], err;
+        for (;;) {
+            ck_eval(g, kappa, y, h, y5, delta);
+            cnt->evals++;
+            double eu = norm3(delta + 3);
+            double exh = norm3(delta) / h;
+            if (!isfinite(eu) || !isfinite(exh)) {
+                *h_next = hctrl;
+                return ST_NONFINITE;
+            }
+            double em = eu > exh ? eu : exh;
+            err = em / p->tol;
+            if (err > 1.0 && h > p->h_min) {
+                double fac = 0.9 * (1.0 / sqrt(sqrt(err)));
+                if (fac < 0.1) fac = 0.1;
+                h = h * fac;
+                if (h < p->h_min) h = p->h_min;
+                binding = 0;
+                (*n_rej)++;
+                cnt->rejected++;
+                continue;
+            }
+            break;
+        }
+
+        /* accepted: next controller bid */
+        int floor_hit = err > 1.0;
+        double gfac;
+        if (floor_hit) {
+            gfac = 1.0;
+            cnt->floor_hits++;
+        } else if (err == 0.0) {
+            gfac = 5.0;
+        } else {
+            gfac = 0.9 * inv_fifth_root(err);
+            if (gfac > 5.0) gfac = 5.0;
+        }
+        hctrl = h * gfac;
+        if (hctrl < p->h_min) hctrl = p->h_min;
+        if (hctrl > p->h_max) hctrl = p->h_max;
+
+        double un2 = y5[3] * y5[3] + y5[4] * y5[4] + y5[5] * y5[5];
+        double un = sqrt(un2);
+        double ynew[6] = {y5[0], y5[1], y5[2], y5[3] / un, y5[4] / un, y5[5] / un};
+        double Lnew = binding ? p->l_max : *L + h;
+        (*n_acc)++;
+        cnt->accepted++;
+        steps_this_call++;
+        if (tape && tape->h) {
+            if (tape->len < tape->cap) tape->h[tape->len] = h;
+            tape->len++;
+            tape->length_bound = binding;
+        }
+
+        /* stops, in order: sphere crossing, length, step budget */
+        if (sphere && sphere_g(p, ynew) >= 0.0) {
+            double lo = 0.0, glo = sphere_g(p, y), hi = h, ghi = sphere_g(p, ynew);
+            int side = 0;
+            for (int it = 0; it < 30; ++it) {
+                /* converged when the outside end is on the sphere to 1e-14 R^2,
+                 * or the bracket is below 1e-15 h; s* is always the outside end */
+                if (ghi <= 1e-14 * R2 || (hi - lo) <= 1e-15 * h)
+                    break;
+                double s = (lo * ghi - hi * glo) / (ghi - glo);
+                double ys[6], ds[6];
+                ck_eval(g, kappa, y, s, ys, ds);
+                cnt->evals++;
+                cnt->event_evals++;
+                double gs = sphere_g(p, ys);
+                if (!isfinite(gs)) {
+                    *h_next = hctrl;
+                    return ST_NONFINITE;
+                }
+                if (gs >= 0.0) {
+                    hi = s;
+                    ghi = gs;
+                    if (side == 1) glo = glo * 0.5;
+                    side = 1;
+                } else {
+                    lo = s;
+                    glo = gs;
+                    if (side == -1) ghi = ghi * 0.5;
+                    side = -1;
+                }
+            }
+            if (hi != h) {
+                double ys[6], ds[6];
+                ck_eval(g, kappa, y, hi, ys, ds);
+                cnt->evals++;
+                cnt->event_evals++;
+                double sn = sqrt(ys[3] * ys[3] + ys[4] * ys[4] + ys[5] * ys[5]);
+                ynew[0] = ys[0];
+                ynew[1] = ys[1];
+                ynew[2] = ys[2];
+                ynew[3] = ys[3] / sn;
+                ynew[4] = ys[4] / sn;
+                ynew[5] = ys[5] / sn;
+                Lnew = *L + hi;
+            }
+            memcpy(y, ynew, sizeof ynew);
+            *L = Lnew;
+            *h_next = hctrl;
+            if (tape) {
+                tape->event = 1;
+                tape->s_event = hi;
+            }
+            return ST_ARRIVED;
+        }
+        memcpy(y, ynew, sizeof ynew);
+        *L = Lnew;
+        if (lmax_on && *L >= p->l_max) {
+            *h_next = hctrl;
+            return ST_MAX_LENGTH;
+        }
+        if (p->max_steps > 0 && steps_this_call >= p->max_steps) {
+            *h_next = hctrl;
+            return ST_MAX_STEPS;
+        }
+    }
+}
+
+/* ======================= exported C interface ============================ */
+
+static int make_grid(grid_t *g, const void *data, int dtype, int64_t n0, int64_t n1, int64_t n2,
+                     const double origin[3], double spacing)
+{
+    if (!data || n0 < 2 || n1 < 2 || n2 < 2 || !(spacing > 0.0) || (dtype != 0 && dtype != 1))
+        return -1;
+    g->n[0] = n0;
+    g->n[1] = n1;
+    g->n[2] = n2;
+    for (int a = 0; a < 3; ++a)
+        g->origin[a] = origin ? origin[a] : 0.0;
+    g->inv_spacing = 1.0 / spacing;
+    g->v64 = dtype == 0 ? (const double *)data : NULL;
+    g->v32 = dtype == 1 ? (const float *)data : NULL;
+    return 0;
+}
+
+/* Constants and tableau, for the pins. out: [K, Mpc/c, A(36), c(6), b5(6), b4(6), e(6), T(5)] */
+void oracle_constants(double *out)
+{
+    out[0] = K_LORENTZ;
+    out[1] = MPC_OVER_C;
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j)
+            out[2 + 6 * i + j] = j < 5 ? CK_A[i][j] : 0.0;
+    for (int i = 0; i < 6; ++i) {
+        out[38 + i] = CK_C[i];
+        out[44 + i] = CK_B5[i];
+        out[50 + i] = CK_B4[i];
+        out[56 + i] = CK_E[i];
+    }
+    for (int j = 0; j < 5; ++j)
+        out[62 + j] = TWO_POW_NEG_FIFTHS[j];
+}
+
+double oracle_inv_fifth_root(double err) { return inv_fifth_root(err); }
+
+/* Field at n points X[n][3] -> B[n][3]. Returns 0 or -1 on bad arguments. */
+int oracle_field_at(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2,
+                    const double *origin, double spacing, const double *X, double *B, int64_t n)
+{
+    grid_t g;
+    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing))
+        return -1;
+    for (int64_t i = 0; i < n; ++i)
+        field_at(&g, X + 3 * i, B + 3 * i);
+    return 0;
+}
+
+/* One Cash-Karp evaluation (no control): y[6], h -> y5[6], delta[6]. */
+int oracle_ck_eval(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2,
+                   const double *origin, double spacing, double kappa, const double *y, double h,
+                   double *y5, double *delta)
+{
+    grid_t g;
+    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing))
+        return -1;
+    ck_eval(&g, kappa, y, h, y5, delta);
+    return 0;
+}
+
+/* Fixed-step integration (no controller, no normalisation): nsteps of size h. */
+int oracle_fixed_steps(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2,
+                       const double *origin, double spacing, double kappa, double *y, double h,
+                       int64_t nsteps)
+{
+    grid_t g;
+    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing))
+        return -1;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        double y5[6], d[6];
+        ck_eval(&g, kappa, y, h, y5, d);
+        memcpy(y, y5, sizeof y5);
+    }
+    return 0;
+}
+
+/* Propagate n particles in place.  prm: [tol, h_min, h_max, cx, cy, cz, R, l_max].
+ * Arrays of length n (pos/dir are n x 3).  counters (may be NULL): 5 int64 summed
+ * [evals, accepted, rejected, event_evals, floor_hits].  Returns 0 or -1. */
+int oracle_propagate(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2,
+                     const double *origin, double spacing, const double *prm, int64_t max_steps,
+                     int64_t n, double *pos, double *dir, const double *energy,
+                     const int32_t *charge, double *length, double *h_next, int32_t *status,
+                     int64_t *n_acc, int64_t *n_rej, int64_t *counters, int nthreads)
+{
+    grid_t g;
+    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing) || n < 0 || !prm)
+        return -1;
+    params_t p;
+    p.tol = prm[0];
+    p.h_min = prm[1];
+    p.h_max = prm[2];
+    p.center[0] = prm[3];
+    p.center[1] = prm[4];
+    p.center[2] = prm[5];
+    p.radius = prm[6];
+    p.l_max = prm[7];
+    p.max_steps = max_steps;
+    if (!(p.tol > 0.0) || !(p.h_min > 0.0) || !(p.h_max >= p.h_min) || isnan(p.l_max) ||
+        !(p.l_max > 0.0) || (!isfinite(p.l_max) && max_steps <= 0))
+        return -1;
+    int64_t c_evals = 0, c_acc = 0, c_rej = 0, c_ev = 0, c_fl = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads) \
+    reduction(+ : c_evals, c_acc, c_rej, c_ev, c_fl)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        if (status[i] != ST_ACTIVE)
+            continue;
+        double y[6] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2],
+                       dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
+        counts_t cnt = {0, 0, 0, 0, 0};
+        double L = length[i], hn = h_next[i];
+        int st = propagate_one(&g, &p, y, energy[i], charge[i], &L, &hn, &n_acc[i], &n_rej[i],
+                               &cnt, NULL);
+        status[i] = st;
+        if (st != ST_BAD_INPUT) {
+            for (int c = 0; c < 3; ++c) {
+                pos[3 * i + c] = y[c];
+                dir[3 * i + c] = y[3 + c];
+            }
+            length[i] = L;
+            h_next[i] = hn;
+        }
+        c_evals += cnt.evals;
+        c_acc += cnt.accepted;
+        c_rej += cnt.rejected;
+        c_ev += cnt.event_evals;
+        c_fl += cnt.floor_hits;
+    }
+    if (counters) {
+        counters[0] += c_evals;
+        counters[1] += c_acc;
+        counters[2] += c_rej;
+        counters[3] += c_ev;
+        counters[4] += c_fl;
+    }
+    return 0;
+}
+
+/* Propagate one particle recording the accepted step sizes (for the adjoint
+ * and for tests).  h_tape has capacity cap; returns the number of accepted
+ * steps (may exceed cap, then the tape is truncated) or -1.  info[0] = status,
+ * info[1] = event flag, info[2] = s* of the event, info[3] = length-bound flag. */
+int64_t oracle_propagate_taped(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2,
+                               const double *origin, double spacing, const double *prm,
+                               double *y, double energy, int32_t charge, double *length,
+                               double *h_next, double *h_tape, int64_t cap, double *info)
+{
+    grid_t g;
+    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing))
+        return -1;
+    params_t p;
+    p.tol = prm[0];
+    p.h_min = prm[1];
+    p.h_max = prm[2];
+    p.center[0] = prm[3];
+    p.center[1] = prm[4];
+    p.center[2] = prm[5];
+    p.radius = prm[6];
+    p.l_max = prm[7];
+    p.max_steps = 0;
+    if (!isfinite(p.l_max))
+        return -1;
+    tape_t tape = {h_tape, cap, 0, 0.0, 0, 0};
+    counts_t cnt = {0, 0, 0, 0, 0};
+    int64_t na = 0, nr = 0;
+    int st = propagate_one(&g, &p, y, energy, charge, length, h_next, &na, &nr, &cnt, &tape);
+    info[0] = st;
+    info[1] = tape.event;
+    info[2] = tape.s_event;
+    info[3] = tape.length_bound;
+    return tape.len;
+}
