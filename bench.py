@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the propagation hot path on one MI355X.
+
+Workload (default): 1e6 nuclei (Z uniform in {1, 2, 7, 26}, E log-uniform in
+1e18..1e20 eV, isotropic from the origin) in a 256^3 FP32 Kolmogorov grid
+(spacing 50 kpc, l_min 100 kpc, l_max 5 Mpc, B_rms 1 nG), tolerance 1e-4,
+steps 1 kpc .. 1 Mpc, stop at the r = 20 Mpc sphere or at 1 Gpc of path.
+A step of the benchmark propagates every particle until it stops.
+
+Prints one JSON line: particle-steps/s (accepted Cash-Karp steps per second of
+the whole job), the gather roofline of the propagation kernel (algorithmic
+bytes of the field lookups per launch / average launch time, against the HBM
+peak), and the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s + gather GB/s vs roofline; adjoint/forward time; err vs FP64"
+HBM_PEAK_GBPS = 8000.0
+BYTES_PER_VALUE = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+KERNEL_SOURCES = ["crp_device.h", "propagate_fp64.hip", "crp_internal.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1410_5323_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, layout: str, evals_per_launch: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_propagate_fp64_{workload}_{layout}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(B, w, P, sample: int):
+    import numpy as np
+
+    from oracle import oracle as O
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = min(cores, int(omp)) if omp and omp.isdigit() else cores
+    sel = slice(0, sample)
+    g = O.Grid(B, w.spacing)
+    prm = O.params_array(w.tol, w.h_min, w.h_max, radius=w.obs_radius, l_max=w.max_length)
+    t0 = time.perf_counter()
+    r = O.propagate(g, prm, P["pos"][sel], P["dir"][sel], P["energy"][sel], P["charge"][sel], nthreads=threads)
+    dt = time.perf_counter() - t0
+    acc = int(np.sum(r["n_acc"]))
+    return {"value": acc / dt, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sample} particles of the same seeded list ({acc} accepted steps, "
+                      f"{r['counters']['evals']} evaluations, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="production_256cube")
+    ap.add_argument("--n", type=int, default=None, help="particle count (default: the workload's)")
+    ap.add_argument("--layout", default="linear", choices=["linear", "cell8"])
+    ap.add_argument("--block-size", type=int, default=256)
+    ap.add_argument("--blocks-per-cu", type=int, default=4)
+    ap.add_argument("--refill-threshold", type=int, default=1)
+    ap.add_argument("--no-order", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=200000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the path shards "
+              "particles across GPUs by design but no multi-GPU run is part of it.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import crp_inputs as ci
+    from paper_1410_5323_amd import crp
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU available", file=sys.stderr)
+        sys.exit(1)
+    crp.lib()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    w = ci.get_config(args.workload)
+    fs, ps, _ = ci.config_seeds(w.index)
+    n = w.n_particles if args.n is None else args.n
+    gdt = {"f64": np.float64}.get(w.grid_dtype, np.float32)
+    t0 = time.perf_counter()
+    B = ci.kolmogorov_field(w.grid_n, w.spacing, w.l_min, w.l_max, w.b_rms, fs, dtype=gdt)
+    P = ci.isotropic_particles(n, w.e_min, w.e_max, w.charges, ps, charge_rule=w.charge_rule)
+    log(f"bench: inputs generated in {time.perf_counter() - t0:.1f} s ({w.name}, n={n})")
+
+    dtype = w.grid_dtype if w.grid_dtype in ("f64", "f32") else "f32"
+    field = crp.make_field(B, w.spacing, dtype=dtype, layout=args.layout)
+    prm = crp.make_params(w.tol, w.h_min, w.h_max, obs_radius=w.obs_radius, l_max=w.max_length)
+    pristine = crp.particles_to_device(P["pos"], P["dir"], P["energy"], P["charge"], mass=P["mass"])
+    state = crp.clone_particles(pristine)
+    ws = torch.empty(crp.crp_workspace_bytes(n, 1, 1), dtype=torch.uint8, device=dev)
+    counters = torch.zeros(crp.NCOUNTERS, dtype=torch.int64, device=dev)
+    tuning = crp.make_tuning(args.block_size, args.blocks_per_cu, args.refill_threshold,
+                             0 if args.no_order else 1)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        for k, v in pristine.items():
+            if v is not None:
+                state[k].copy_(v, non_blocking=True)
+        if ev is not None:
+            ev[0].record(stream)
+        crp.crp_propagate([field], [prm], state, tuning=tuning, counters=counters, workspace=ws)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"bench: warmup {i + 1}/{args.warmup} done")
+    counters.zero_()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(events[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    launch_ms = [a.elapsed_time(b) for a, b in events]
+    c = counters.cpu().numpy().astype(np.int64)
+    log(f"bench: {args.steps} timed steps in {elapsed:.3f} s; launch ms {['%.1f' % x for x in launch_ms]}")
+
+    accepted = int(c[1])
+    evals = int(c[0])
+    steps_per_s = accepted / elapsed
+    avg_launch_s = float(np.mean(launch_ms)) / 1e3
+    bpv = BYTES_PER_VALUE[dtype]
+    bytes_per_eval = 6 * 8 * 3 * bpv
+    evals_per_launch = evals / args.steps
+    achieved = bytes_per_eval * evals_per_launch / avg_launch_s / 1e9
+    traffic = measured_traffic(w.name, args.layout, evals_per_launch)
+    host = crp.particles_to_host(state)
+    statuses = {k: int(np.sum(host["status"] == v)) for k, v in crp.STATUS.items() if np.any(host["status"] == v)}
+
+    result = {
+        "metric": METRIC,
+        "value": steps_per_s,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "particles": n, "grid": f"{w.grid_n}^3 {dtype}",
+                   "grid_spacing_mpc": w.spacing, "layout": args.layout, "tol": w.tol,
+                   "h_min_mpc": w.h_min, "h_max_mpc": w.h_max, "obs_radius_mpc": w.obs_radius,
+                   "l_max_mpc": w.max_length, "precision": "fp64",
+                   "tuning": {"block_size": args.block_size, "blocks_per_cu": args.blocks_per_cu,
+                              "refill_threshold": args.refill_threshold, "order_by_rigidity": not args.no_order}},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": None if traffic is None else traffic},
+        "detail": {"accepted_steps_per_launch": accepted / args.steps,
+                   "evaluations_per_launch": evals_per_launch,
+                   "rejected_per_launch": int(c[2]) / args.steps,
+                   "event_evaluations_per_launch": int(c[3]) / args.steps,
+                   "floor_hits_per_launch": int(c[4]) / args.steps,
+                   "evaluations_per_s": evals / elapsed,
+                   "avg_launch_ms": avg_launch_s * 1e3,
+                   "algorithmic_bytes_per_evaluation": bytes_per_eval,
+                   "statuses": statuses,
+                   "kernel_source_sha": kernel_source_hash()},
+    }
+    if not args.no_cpu_baseline:
+        log(f"bench: timing the CPU oracle on the first {args.cpu_sample} particles")
+        result["cpu_baseline"] = cpu_baseline(B, w, P, min(args.cpu_sample, n))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,182 @@
+/*
+ * crp.h -- C ABI of the MI355X (gfx950) charged-particle propagation library.
+ *
+ * The library advances many independent charged nuclei through a magnetic
+ * field sampled on a regular periodic grid, the 3D mode of "Cosmic ray
+ * propagation with CRPropa 3" (sections 2 and 3.2).  Each particle carries
+ * position, direction, energy, charge and mass (section 3.1: the particle is
+ * the single interface between modules).  Each step is an error-controlled
+ * Cash-Karp Runge-Kutta step of the Lorentz force with trilinear field
+ * interpolation at every stage; its length is the lowest bid among the
+ * controller, the step limits, the distance to the observer sphere and the
+ * remaining trajectory length (section 3.1, bidding system).  Propagation
+ * ends at the observer sphere, at the length limit or when aborted
+ * (section 3.1: "completed or aborted").  Energy is not changed (no losses,
+ * as in section 3.3).  A negative charge with reversed direction propagates
+ * backwards (section 3.3, backtracking).
+ *
+ * Conventions
+ *   - [dev] marks device pointers; every buffer is owned by the caller (for
+ *     example allocated through PyTorch).  The library never allocates device
+ *     memory and keeps no global state other than a thread-local error string.
+ *   - All work is enqueued on the caller's stream and is asynchronous; the
+ *     call returns after enqueueing.  No call throws across the ABI.
+ *   - Units: positions and lengths in Mpc, energies in eV, fields in nG,
+ *     times in seconds.  Status values are the CRP_ST_* codes below.
+ *   - Argument errors are reported synchronously, before anything is
+ *     enqueued, as CRP_ERR_INVALID; a failing HIP call as CRP_ERR_DEVICE.
+ *     Problems of one particle only go into its status.
+ */
+#ifndef CRP_H
+#define CRP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CRP_OK = 0,
+    CRP_ERR_INVALID = -1,      /* bad argument; nothing was enqueued */
+    CRP_ERR_DEVICE = -2,       /* a HIP runtime call failed */
+    CRP_ERR_UNSUPPORTED = -3,  /* valid but not supported combination */
+    CRP_ERR_WORKSPACE = -4     /* workspace missing or too small */
+} crp_status;
+
+typedef enum { CRP_F64 = 0, CRP_F32 = 1, CRP_F16 = 2, CRP_BF16 = 3 } crp_dtype;
+
+/* Device storage layout of a field grid.
+ * LINEAR: nodes [i][j][k][3] with one duplicated wrap node on every axis,
+ *         (n0+1)(n1+1)(n2+1)*3 values; the 8 corners of a cell never wrap.
+ * CELL8:  one record per cell holding its 8 corner vectors (24 values padded
+ *         to 32), n0*n1*n2*32 values; a cell lookup reads one record. */
+typedef enum { CRP_LAYOUT_LINEAR = 0, CRP_LAYOUT_CELL8 = 1 } crp_layout;
+
+/* Arithmetic of the propagation kernel.
+ * FP64: every stage in FP64 (the parity path).
+ * MIXED_F64ACC: FP32 stages, position / length / time accumulated in FP64.
+ * MIXED_DFACC: FP32 stages, position / length accumulated as double-float. */
+typedef enum { CRP_PREC_FP64 = 0, CRP_PREC_MIXED_F64ACC = 1, CRP_PREC_MIXED_DFACC = 2 } crp_precision;
+
+/* Particle status (per particle, in crp_particles.status). Only ACTIVE particles
+ * are propagated; set MAX_STEPS or CANCELLED back to ACTIVE to resume. */
+enum {
+    CRP_ST_ACTIVE = 0,      /* still propagating */
+    CRP_ST_ARRIVED = 1,     /* crossed the observer sphere (event located) */
+    CRP_ST_MAX_LENGTH = 2,  /* trajectory length reached l_max exactly */
+    CRP_ST_MAX_STEPS = 3,   /* accepted-step budget of this call used up */
+    CRP_ST_NONFINITE = 4,   /* the error estimate or the event function was not finite */
+    CRP_ST_CANCELLED = 5,   /* stopped by the cancel flag */
+    CRP_ST_BAD_INPUT = 6    /* E <= 0, zero or non-finite direction or position, bad h_next */
+};
+
+/* One periodic vector grid (section 3.2: regular grids; section 4: a vector
+ * grid with a random Kolmogorov realisation).  Node (i,j,k) sits at
+ * origin + spacing*(i,j,k); the field repeats with period n*spacing. */
+typedef struct {
+    int32_t n[3];          /* nodes per axis, each >= 2 */
+    int32_t dtype;         /* crp_dtype of the stored values */
+    int32_t layout;        /* crp_layout */
+    int32_t reserved;
+    double origin[3];      /* Mpc */
+    double spacing;        /* Mpc, > 0 */
+    double value_scale;    /* nG per stored unit (1 for F64/F32 grids) */
+    void *data;            /* [dev] crp_field_bytes(this) bytes, written by crp_field_upload */
+} crp_field;
+
+/* Bidding and stopping parameters of one particle group (section 3.1). */
+typedef struct {
+    double tol;            /* accuracy: error norm per step <= tol, > 0 */
+    double h_min, h_max;   /* step limits in Mpc, 0 < h_min <= h_max */
+    double obs_center[3];  /* observer sphere centre, Mpc */
+    double obs_radius;     /* Mpc; <= 0 disables the sphere */
+    double l_max;          /* length limit, Mpc, > 0; +inf disables it (then max_steps > 0) */
+    int64_t max_steps;     /* accepted steps allowed per particle in one call; 0 = no limit */
+    int32_t field_index;   /* which entry of the fields array this group uses */
+    int32_t reserved;
+} crp_params;
+
+/* Structure-of-arrays particle state; every pointer is [dev] with n entries
+ * (may be NULL when n = 0).  In/out arrays are updated in place. */
+typedef struct {
+    double *x, *y, *z;        /* in/out position, Mpc */
+    double *ux, *uy, *uz;     /* in/out direction; normalised on a fresh start */
+    double *energy;           /* in, eV (unchanged) */
+    int32_t *charge;          /* in, signed charge number Z (negative: backtracking) */
+    int32_t *mass;            /* in, mass number A (carried, does not enter at beta = 1); may be NULL */
+    double *length;           /* in/out trajectory length, Mpc */
+    double *h_next;           /* in/out controller bid; 0 = fresh start */
+    double *time;             /* out, length * Mpc / c in seconds; may be NULL */
+    int32_t *status;          /* in/out CRP_ST_* */
+    int32_t *param_index;     /* in, index into params; NULL = all use params[0] */
+    int64_t *n_accepted;      /* in/out accepted steps (cumulative) */
+    int64_t *n_rejected;      /* in/out rejected attempts (cumulative) */
+} crp_particles;
+
+/* Launch configuration; NULL selects the defaults. */
+typedef struct {
+    int32_t block_size;       /* threads per block: 64, 128 or 256 (default 256) */
+    int32_t blocks_per_cu;    /* persistent blocks per compute unit (default 4); 0 = one lane per particle */
+    int32_t refill_threshold; /* refill a wavefront when at least this many lanes are idle (default 1) */
+    int32_t order_by_rigidity;/* 1: hand out low-rigidity particles first (longest first); default 1 */
+} crp_tuning;
+
+/* Counters accumulated by crp_propagate into an optional [dev] int64 array. */
+enum {
+    CRP_CNT_EVALS = 0,        /* Cash-Karp evaluations (each 6 field lookups) */
+    CRP_CNT_ACCEPTED = 1,
+    CRP_CNT_REJECTED = 2,
+    CRP_CNT_EVENT_EVALS = 3,  /* evaluations spent locating sphere crossings */
+    CRP_CNT_FLOOR_HITS = 4,   /* steps accepted at h_min with error above tolerance */
+    CRP_CNT_PARTICLES = 5,    /* particles taken from the queue */
+    CRP_NCOUNTERS = 8
+};
+
+/* Bytes of device storage for a field in its dtype and layout; 0 if the
+ * descriptor is invalid. */
+size_t crp_field_bytes(const crp_field *f);
+
+/* Fill f->data from src: [dev] C-order [n0][n1][n2][3] values in nG, of
+ * src_dtype F64 or F32 (the grid of section 3.2 as produced by a field
+ * generator).  Values are divided by f->value_scale and rounded to nearest
+ * even into f->dtype, then written in f->layout.  src and f->data must not
+ * overlap.  Stream s (hipStream_t, may be NULL for the default stream). */
+crp_status crp_field_upload(const crp_field *f, const void *src, int32_t src_dtype, void *stream);
+
+/* Device workspace needed by crp_propagate for n particles and the given
+ * table sizes (field and parameter descriptors, work queue, ordering keys). */
+size_t crp_workspace_bytes(int64_t n, int32_t n_fields, int32_t n_params);
+
+/* Propagate n particles in place (sections 2, 3.1, 3.2): each ACTIVE particle
+ * is stepped until it arrives at its observer sphere, reaches l_max, uses up
+ * max_steps, or fails.  fields[n_fields] and params[n_params] are host
+ * arrays; every field of one call must share dtype and layout.  precision is
+ * a crp_precision.  counters: optional [dev] int64[CRP_NCOUNTERS],
+ * accumulated (caller zeroes).  workspace: [dev], crp_workspace_bytes long,
+ * 256-byte aligned; its contents are scratch.  Calls that share a workspace
+ * must be ordered on one stream. */
+crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_params *params,
+                         int32_t n_params, const crp_particles *p, int64_t n, int32_t precision,
+                         const crp_tuning *tuning, int64_t *counters, void *workspace,
+                         size_t workspace_bytes, void *stream);
+
+/* Device arithmetic conformance: apply operation op to n inputs in[] ([dev]
+ * FP64) writing out[] ([dev] FP64).  op: 0 sqrt, 1 reciprocal (1/x), 2 fma(x, y,
+ * z) on triples (n triples, in has 3n values), 3 floor, 4 the controller's
+ * fifth root x^(-1/5), 5 the controller's shrink factor 1/sqrt(sqrt(x)).  Used
+ * to check that the device rounds exactly like the host. */
+crp_status crp_selftest_arith(const double *in, double *out, int64_t n, int32_t op, void *stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *crp_last_error(void);
+
+/* Library version string. */
+const char *crp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRP_H */

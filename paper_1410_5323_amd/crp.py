@@ -1,0 +1,260 @@
+"""ctypes binding of libcrp (include/crp.h): argument marshalling only.
+
+Every step of the propagation runs in the library's HIP kernels; this module
+only allocates device memory through PyTorch, fills the C descriptors and
+calls the entry points of the same names on the current torch stream.  If the
+library is missing or fails to load, every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcrp.so")
+
+CRP_OK, CRP_ERR_INVALID, CRP_ERR_DEVICE, CRP_ERR_UNSUPPORTED, CRP_ERR_WORKSPACE = 0, -1, -2, -3, -4
+CRP_F64, CRP_F32, CRP_F16, CRP_BF16 = 0, 1, 2, 3
+CRP_LAYOUT_LINEAR, CRP_LAYOUT_CELL8 = 0, 1
+CRP_PREC_FP64, CRP_PREC_MIXED_F64ACC, CRP_PREC_MIXED_DFACC = 0, 1, 2
+STATUS = {"ACTIVE": 0, "ARRIVED": 1, "MAX_LENGTH": 2, "MAX_STEPS": 3, "NONFINITE": 4,
+          "CANCELLED": 5, "BAD_INPUT": 6}
+COUNTERS = ["evals", "accepted", "rejected", "event_evals", "floor_hits", "particles"]
+NCOUNTERS = 8
+DTYPES = {"f64": CRP_F64, "f32": CRP_F32, "f16": CRP_F16, "bf16": CRP_BF16}
+LAYOUTS = {"linear": CRP_LAYOUT_LINEAR, "cell8": CRP_LAYOUT_CELL8}
+
+
+class CRPError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"libcrp status {status}: {message}")
+        self.status = status
+
+
+class crp_field(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("dtype", C.c_int32), ("layout", C.c_int32),
+                ("reserved", C.c_int32), ("origin", C.c_double * 3), ("spacing", C.c_double),
+                ("value_scale", C.c_double), ("data", C.c_void_p)]
+
+
+class crp_params(C.Structure):
+    _fields_ = [("tol", C.c_double), ("h_min", C.c_double), ("h_max", C.c_double),
+                ("obs_center", C.c_double * 3), ("obs_radius", C.c_double), ("l_max", C.c_double),
+                ("max_steps", C.c_int64), ("field_index", C.c_int32), ("reserved", C.c_int32)]
+
+
+_PARTICLE_FIELDS = ["x", "y", "z", "ux", "uy", "uz", "energy", "charge", "mass", "length",
+                    "h_next", "time", "status", "param_index", "n_accepted", "n_rejected"]
+
+
+class crp_particles(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in _PARTICLE_FIELDS]
+
+
+class crp_tuning(C.Structure):
+    _fields_ = [("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("refill_threshold", C.c_int32), ("order_by_rigidity", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcrp.so from the package directory (raises if absent)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libcrp.so not built at {LIB_PATH}; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        L.crp_field_bytes.argtypes = [C.POINTER(crp_field)]
+        L.crp_field_bytes.restype = C.c_size_t
+        L.crp_field_upload.argtypes = [C.POINTER(crp_field), C.c_void_p, C.c_int32, C.c_void_p]
+        L.crp_workspace_bytes.argtypes = [C.c_int64, C.c_int32, C.c_int32]
+        L.crp_workspace_bytes.restype = C.c_size_t
+        L.crp_propagate.argtypes = [C.POINTER(crp_field), C.c_int32, C.POINTER(crp_params), C.c_int32,
+                                    C.POINTER(crp_particles), C.c_int64, C.c_int32,
+                                    C.POINTER(crp_tuning), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.crp_selftest_arith.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+        L.crp_last_error.restype = C.c_char_p
+        L.crp_version.restype = C.c_char_p
+        for f in (L.crp_field_upload, L.crp_propagate, L.crp_selftest_arith):
+            f.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != CRP_OK:
+        raise CRPError(status, lib().crp_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------- entry points
+
+def crp_version() -> str:
+    return lib().crp_version().decode()
+
+
+def crp_last_error() -> str:
+    return lib().crp_last_error().decode()
+
+
+def crp_field_bytes(desc: crp_field) -> int:
+    return int(lib().crp_field_bytes(C.byref(desc)))
+
+
+def crp_workspace_bytes(n: int, n_fields: int = 1, n_params: int = 1) -> int:
+    return int(lib().crp_workspace_bytes(int(n), int(n_fields), int(n_params)))
+
+
+def crp_field_upload(desc: crp_field, src, stream=None):
+    """src: CUDA tensor float64/float32 of shape (n0, n1, n2, 3), nG."""
+    torch = _torch()
+    if src.dtype == torch.float64:
+        sd = CRP_F64
+    elif src.dtype == torch.float32:
+        sd = CRP_F32
+    else:
+        raise TypeError("source grid must be float64 or float32")
+    if not src.is_contiguous() or not src.is_cuda:
+        raise ValueError("source grid must be a contiguous device tensor")
+    if tuple(src.shape) != (desc.n[0], desc.n[1], desc.n[2], 3):
+        raise ValueError(f"source shape {tuple(src.shape)} does not match the descriptor")
+    _check(lib().crp_field_upload(C.byref(desc), _ptr(src), sd, _stream_handle(stream)))
+
+
+def crp_propagate(fields, params, particles: dict, precision=CRP_PREC_FP64, tuning=None,
+                  counters=None, workspace=None, stream=None):
+    """Propagate in place.  fields: list of Field; params: list of crp_params;
+    particles: dict of device tensors keyed as in crp_particles."""
+    torch = _torch()
+    nf, np_ = len(fields), len(params)
+    farr = (crp_field * nf)(*[f.desc for f in fields])
+    parr = (crp_params * np_)(*params)
+    n = int(particles["energy"].numel())
+    ps = crp_particles(**{k: (particles[k].data_ptr() if particles.get(k) is not None else None)
+                          for k in _PARTICLE_FIELDS})
+    need = crp_workspace_bytes(n, nf, np_)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=particles["energy"].device)
+    tun = C.byref(tuning) if tuning is not None else None
+    _check(lib().crp_propagate(farr, nf, parr, np_, C.byref(ps), n, int(precision), tun,
+                               _ptr(counters), _ptr(workspace), workspace.numel(),
+                               _stream_handle(stream)))
+    return particles
+
+
+def crp_selftest_arith(inp, out, op: int, stream=None):
+    n = out.numel()
+    _check(lib().crp_selftest_arith(_ptr(inp), _ptr(out), n, int(op), _stream_handle(stream)))
+
+
+# ------------------------------------------------------------- conveniences
+
+@dataclass
+class Field:
+    """A device field grid: descriptor plus the torch tensor that owns its storage."""
+    desc: crp_field
+    storage: object
+
+    @property
+    def nbytes(self) -> int:
+        return crp_field_bytes(self.desc)
+
+
+def make_field(values, spacing: float, origin=(0.0, 0.0, 0.0), dtype="f32", layout="linear",
+               value_scale: float = 1.0, device="cuda", stream=None) -> Field:
+    """Upload an (n0, n1, n2, 3) grid in nG (numpy or torch; float64/float32)."""
+    torch = _torch()
+    src = values if isinstance(values, torch.Tensor) else torch.from_numpy(values)
+    src = src.to(device=device).contiguous()
+    d = crp_field()
+    d.n[0], d.n[1], d.n[2] = (int(s) for s in src.shape[:3])
+    d.dtype = DTYPES[dtype]
+    d.layout = LAYOUTS[layout]
+    d.origin[0], d.origin[1], d.origin[2] = (float(o) for o in origin)
+    d.spacing = float(spacing)
+    d.value_scale = float(value_scale)
+    nb = crp_field_bytes(d)
+    if nb == 0:
+        raise CRPError(CRP_ERR_INVALID, crp_last_error())
+    storage = torch.empty(nb, dtype=torch.uint8, device=device)
+    d.data = storage.data_ptr()
+    crp_field_upload(d, src, stream=stream)
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return Field(d, storage)
+
+
+def make_params(tol, h_min, h_max, obs_radius=0.0, l_max=math.inf, obs_center=(0.0, 0.0, 0.0),
+                max_steps=0, field_index=0) -> crp_params:
+    p = crp_params()
+    p.tol, p.h_min, p.h_max = float(tol), float(h_min), float(h_max)
+    for i in range(3):
+        p.obs_center[i] = float(obs_center[i])
+    p.obs_radius = float(obs_radius)
+    p.l_max = float(l_max)
+    p.max_steps = int(max_steps)
+    p.field_index = int(field_index)
+    return p
+
+
+def make_tuning(block_size=256, blocks_per_cu=4, refill_threshold=1, order_by_rigidity=1) -> crp_tuning:
+    return crp_tuning(block_size, blocks_per_cu, refill_threshold, order_by_rigidity)
+
+
+def particles_to_device(pos, dir, energy, charge, mass=None, param_index=None, device="cuda",
+                        with_time=True) -> dict:
+    """Copy host particle arrays into the SoA device tensors of crp_particles (fresh start)."""
+    torch = _torch()
+    import numpy as np
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    dir = np.asarray(dir, dtype=np.float64).reshape(-1, 3)
+    n = pos.shape[0]
+
+    def d64(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+
+    def i32(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(device)
+
+    p = {"x": d64(pos[:, 0]), "y": d64(pos[:, 1]), "z": d64(pos[:, 2]),
+         "ux": d64(dir[:, 0]), "uy": d64(dir[:, 1]), "uz": d64(dir[:, 2]),
+         "energy": d64(energy), "charge": i32(charge),
+         "mass": i32(mass) if mass is not None else None,
+         "length": torch.zeros(n, dtype=torch.float64, device=device),
+         "h_next": torch.zeros(n, dtype=torch.float64, device=device),
+         "time": torch.zeros(n, dtype=torch.float64, device=device) if with_time else None,
+         "status": torch.zeros(n, dtype=torch.int32, device=device),
+         "param_index": i32(param_index) if param_index is not None else None,
+         "n_accepted": torch.zeros(n, dtype=torch.int64, device=device),
+         "n_rejected": torch.zeros(n, dtype=torch.int64, device=device)}
+    return p
+
+
+def particles_to_host(p: dict) -> dict:
+    """Gather device particle state into numpy arrays (pos/dir as (n, 3))."""
+    import numpy as np
+    out = {k: v.cpu().numpy() for k, v in p.items() if v is not None}
+    out["pos"] = np.stack([out.pop("x"), out.pop("y"), out.pop("z")], axis=1)
+    out["dir"] = np.stack([out.pop("ux"), out.pop("uy"), out.pop("uz")], axis=1)
+    return out
+
+
+def clone_particles(p: dict) -> dict:
+    return {k: (v.clone() if v is not None else None) for k, v in p.items()}

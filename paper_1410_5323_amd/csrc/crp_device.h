@@ -1,0 +1,233 @@
+// crp_device.h -- device arithmetic of the FP64 propagation path (gfx950).
+//
+// Everything here is written for the GPU library alone.  The arithmetic
+// follows one fixed contract so that the result of every particle is
+// reproducible bit for bit:
+//   * IEEE FP64, round to nearest even, compiled with -ffp-contract=off; a
+//     fused multiply-add only where fma() is written;
+//   * sqrt and division are the correctly rounded device sequences;
+//   * the controller's fifth root is a fixed Newton iteration, not pow().
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "crp_internal.h"
+
+namespace crp {
+namespace dev {
+
+// Lorentz-force constant: kappa = Z*K/E gives kappa*B = 1/r_gyro with B in nG,
+// E in eV and lengths in Mpc; K = c * 1e-13 T/nG * 1 Mpc, c = 299792458 m/s,
+// 1 Mpc = 1e6 * 648000/pi au, au = 149597870700 m.
+constexpr double K_LORENTZ = 9.250628667507923e17;
+// Seconds of light travel per Mpc.
+constexpr double SEC_PER_MPC = 102927125054339.0;
+
+// Cash-Karp 5(4) tableau (Cash & Karp 1990), each entry the FP64 rounding of
+// its rational value.  Fifth-order weights B5*, error weights E* = b5 - b4.
+constexpr double A21 = 1.0 / 5.0;
+constexpr double A31 = 3.0 / 40.0, A32 = 9.0 / 40.0;
+constexpr double A41 = 3.0 / 10.0, A42 = -9.0 / 10.0, A43 = 6.0 / 5.0;
+constexpr double A51 = -11.0 / 54.0, A52 = 5.0 / 2.0, A53 = -70.0 / 27.0, A54 = 35.0 / 27.0;
+constexpr double A61 = 1631.0 / 55296.0, A62 = 175.0 / 512.0, A63 = 575.0 / 13824.0,
+                 A64 = 44275.0 / 110592.0, A65 = 253.0 / 4096.0;
+constexpr double B51 = 37.0 / 378.0, B53 = 250.0 / 621.0, B54 = 125.0 / 594.0, B56 = 512.0 / 1771.0;
+constexpr double E1 = -277.0 / 64512.0, E3 = 6925.0 / 370944.0, E4 = -6925.0 / 202752.0,
+                 E5 = -277.0 / 14336.0, E6 = 277.0 / 7084.0;
+
+// 2^(-j/5), j = 0..4, nearest FP64.
+__device__ __forceinline__ double two_pow_neg_fifth(int j) {
+    switch (j) {
+        case 0: return 0x1.0000000000000p+0;
+        case 1: return 0x1.bdb8cdadbe120p-1;
+        case 2: return 0x1.8406003b2ae5cp-1;
+        case 3: return 0x1.51cb453b9536cp-1;
+        default: return 0x1.2611186bae675p-1;
+    }
+}
+
+// x^(-1/5) for finite x > 0: x = m 2^e, m in [0.5, 1); e = 5q + j with j in
+// 0..4; six Newton steps r <- r (6 - m r^5) / 5 from r = 1 give m^(-1/5)
+// (monotone from below); the result is r * 2^(-j/5) * 2^(-q).
+__device__ __forceinline__ double inv_fifth_root(double x) {
+    int e;
+    double m = frexp(x, &e);
+    int q = e >= 0 ? e / 5 : -((-e + 4) / 5);
+    int j = e - 5 * q;
+    double r = 1.0;
+#pragma unroll
+    for (int it = 0; it < 6; ++it) {
+        double r2 = r * r;
+        double r5 = (r2 * r2) * r;
+        r = r * (6.0 - m * r5) * 0.2;
+    }
+    return ldexp(r * two_pow_neg_fifth(j), -q);
+}
+
+__device__ __forceinline__ double lerp(double a, double b, double t) { return fma(t, b - a, a); }
+
+template <class T> __device__ __forceinline__ double to_f64(T v);
+template <> __device__ __forceinline__ double to_f64<double>(double v) { return v; }
+template <> __device__ __forceinline__ double to_f64<float>(float v) { return (double)v; }
+template <> __device__ __forceinline__ double to_f64<__half>(__half v) { return (double)__half2float(v); }
+template <> __device__ __forceinline__ double to_f64<__hip_bfloat16>(__hip_bfloat16 v) {
+    return (double)__bfloat162float(v);
+}
+
+// Cell index and fraction along one axis: f = (X - o) * inv_spacing,
+// i = floor(f) wrapped into [0, n), t = f - floor(f).
+__device__ __forceinline__ int cell_axis(double X, double o, double inv, int n, int pow2, double &t) {
+    double f = (X - o) * inv;
+    double fl = floor(f);
+    t = f - fl;
+    int i = (int)fl;
+    if (pow2) return i & (n - 1);
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// Trilinear interpolation of the 8 corner vectors v[dz][dy][dx][c]: along x,
+// then y, then z, each a + t (b - a) with one fma.
+__device__ __forceinline__ void trilinear(const double (&v)[2][2][2][3], double tx, double ty, double tz,
+                                          double B[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double c00 = lerp(v[0][0][0][c], v[0][0][1][c], tx);
+        double c10 = lerp(v[0][1][0][c], v[0][1][1][c], tx);
+        double c01 = lerp(v[1][0][0][c], v[1][0][1][c], tx);
+        double c11 = lerp(v[1][1][0][c], v[1][1][1][c], tx);
+        double c0 = lerp(c00, c10, ty);
+        double c1 = lerp(c01, c11, ty);
+        B[c] = lerp(c0, c1, tz);
+    }
+}
+
+// Field lookup at X (Mpc) -> B (nG) for the LINEAR (wrap-padded) layout:
+// corner (dx,dy,dz) of cell (i,j,k) is node (i+dx, j+dy, k+dz) of the padded
+// grid, so no corner needs a wrap.
+template <class T>
+__device__ __forceinline__ void lookup_linear(const FieldDev &F, const double X[3], double B[3]) {
+    double tx, ty, tz;
+    int i = cell_axis(X[0], F.origin[0], F.inv_spacing, F.n[0], F.pow2, tx);
+    int j = cell_axis(X[1], F.origin[1], F.inv_spacing, F.n[1], F.pow2, ty);
+    int k = cell_axis(X[2], F.origin[2], F.inv_spacing, F.n[2], F.pow2, tz);
+    const T *p = static_cast<const T *>(F.data) +
+                 3u * ((uint32_t)i * F.sx + (uint32_t)j * F.sy + (uint32_t)k);
+    double v[2][2][2][3];
+#pragma unroll
+    for (int dx = 0; dx < 2; ++dx)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            const T *q = p + 3u * ((uint32_t)dx * F.sx + (uint32_t)dy * F.sy);
+#pragma unroll
+            for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[dz][dy][dx][c] = to_f64<T>(q[3 * dz + c]);
+        }
+    trilinear(v, tx, ty, tz, B);
+    if (F.value_scale != 1.0) {
+        B[0] = B[0] * F.value_scale;
+        B[1] = B[1] * F.value_scale;
+        B[2] = B[2] * F.value_scale;
+    }
+}
+
+// Field lookup for the CELL8 layout: one record of 32 values per cell, the
+// 8 corner vectors in the order (dz, dy, dx, component), 24 used.
+template <class T>
+__device__ __forceinline__ void lookup_cell8(const FieldDev &F, const double X[3], double B[3]) {
+    double tx, ty, tz;
+    int i = cell_axis(X[0], F.origin[0], F.inv_spacing, F.n[0], F.pow2, tx);
+    int j = cell_axis(X[1], F.origin[1], F.inv_spacing, F.n[1], F.pow2, ty);
+    int k = cell_axis(X[2], F.origin[2], F.inv_spacing, F.n[2], F.pow2, tz);
+    const T *p = static_cast<const T *>(F.data) +
+                 32ull * (uint64_t)((uint32_t)i * F.cx + (uint32_t)j * F.cy + (uint32_t)k);
+    double v[2][2][2][3];
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[dz][dy][dx][c] = to_f64<T>(p[((dz * 2 + dy) * 2 + dx) * 3 + c]);
+    trilinear(v, tx, ty, tz, B);
+    if (F.value_scale != 1.0) {
+        B[0] = B[0] * F.value_scale;
+        B[1] = B[1] * F.value_scale;
+        B[2] = B[2] * F.value_scale;
+    }
+}
+
+template <class T, int LAYOUT>
+__device__ __forceinline__ void lookup(const FieldDev &F, const double X[3], double B[3]) {
+    if (LAYOUT == CRP_LAYOUT_CELL8)
+        lookup_cell8<T>(F, X, B);
+    else
+        lookup_linear<T>(F, X, B);
+}
+
+// Right-hand side in path length: k = (U, kappa * U x B(X)) for Y = (X, U).
+template <class T, int LAYOUT>
+__device__ __forceinline__ void rhs(const FieldDev &F, double kap, const double Y[6], double k[6]) {
+    double B[3];
+    lookup<T, LAYOUT>(F, Y, B);
+    k[0] = Y[3];
+    k[1] = Y[4];
+    k[2] = Y[5];
+    double cx = Y[4] * B[2] - Y[5] * B[1];
+    double cy = Y[5] * B[0] - Y[3] * B[2];
+    double cz = Y[3] * B[1] - Y[4] * B[0];
+    k[3] = kap * cx;
+    k[4] = kap * cy;
+    k[5] = kap * cz;
+}
+
+__device__ __forceinline__ double norm3(double a, double b, double c) { return sqrt(a * a + b * b + c * c); }
+
+// One Cash-Karp evaluation of step h from y: fifth-order solution y5 and the
+// norms of the embedded error vector delta = h * sum_i e_i k_i split into
+// position (ex) and direction (eu) parts.  Stage sums accumulate over j in
+// increasing order with fma starting from zero; terms with a zero weight are
+// omitted (they only add a signed zero).
+template <class T, int LAYOUT>
+__device__ __forceinline__ void ck_eval(const FieldDev &F, double kap, const double y[6], double h,
+                                        double y5[6], double &ex, double &eu) {
+    double k1[6], k2[6], k3[6], k4[6], k5[6], k6[6], Y[6];
+    rhs<T, LAYOUT>(F, kap, y, k1);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) Y[c] = fma(h, fma(A21, k1[c], 0.0), y[c]);
+    rhs<T, LAYOUT>(F, kap, Y, k2);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) Y[c] = fma(h, fma(A32, k2[c], fma(A31, k1[c], 0.0)), y[c]);
+    rhs<T, LAYOUT>(F, kap, Y, k3);
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        Y[c] = fma(h, fma(A43, k3[c], fma(A42, k2[c], fma(A41, k1[c], 0.0))), y[c]);
+    rhs<T, LAYOUT>(F, kap, Y, k4);
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        Y[c] = fma(h, fma(A54, k4[c], fma(A53, k3[c], fma(A52, k2[c], fma(A51, k1[c], 0.0)))), y[c]);
+    rhs<T, LAYOUT>(F, kap, Y, k5);
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        Y[c] = fma(h, fma(A65, k5[c], fma(A64, k4[c], fma(A63, k3[c], fma(A62, k2[c], fma(A61, k1[c], 0.0))))),
+                   y[c]);
+    rhs<T, LAYOUT>(F, kap, Y, k6);
+    double d[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        double a5 = fma(B56, k6[c], fma(B54, k4[c], fma(B53, k3[c], fma(B51, k1[c], 0.0))));
+        double ae = fma(E6, k6[c], fma(E5, k5[c], fma(E4, k4[c], fma(E3, k3[c], fma(E1, k1[c], 0.0)))));
+        y5[c] = fma(h, a5, y[c]);
+        d[c] = h * ae;
+    }
+    ex = norm3(d[0], d[1], d[2]);
+    eu = norm3(d[3], d[4], d[5]);
+}
+
+}  // namespace dev
+}  // namespace crp

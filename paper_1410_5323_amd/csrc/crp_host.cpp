@@ -1,0 +1,288 @@
+// crp_host.cpp -- host side of the C ABI declared in include/crp.h.
+//
+// Validates every argument before anything is enqueued, packs the device
+// descriptors, and enqueues the kernels on the caller's stream.  Nothing here
+// allocates device memory or blocks on the device.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "crp_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+crp_status fail(crp_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+crp_status fail(crp_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+crp_status ok() {
+    g_last_error.clear();
+    return CRP_OK;
+}
+
+crp_status device_error(hipError_t e, const char *what) {
+    return fail(CRP_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_pow2(int32_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+size_t dtype_size(int32_t d) {
+    switch (d) {
+        case CRP_F64: return 8;
+        case CRP_F32: return 4;
+        case CRP_F16: return 2;
+        case CRP_BF16: return 2;
+        default: return 0;
+    }
+}
+
+// Checks one field descriptor; data may be NULL only when !need_data.
+crp_status check_field(const crp_field *f, bool need_data, const char *what) {
+    if (!f) return fail(CRP_ERR_INVALID, "%s: null field descriptor", what);
+    for (int a = 0; a < 3; ++a) {
+        if (f->n[a] < 2 || f->n[a] > (1 << 20))
+            return fail(CRP_ERR_INVALID, "%s: n[%d] = %d out of range [2, 2^20]", what, a, f->n[a]);
+        if (!std::isfinite(f->origin[a])) return fail(CRP_ERR_INVALID, "%s: origin not finite", what);
+    }
+    if (!(f->spacing > 0.0) || !std::isfinite(f->spacing))
+        return fail(CRP_ERR_INVALID, "%s: spacing must be finite and > 0", what);
+    if (!(f->value_scale > 0.0) || !std::isfinite(f->value_scale))
+        return fail(CRP_ERR_INVALID, "%s: value_scale must be finite and > 0", what);
+    if (dtype_size(f->dtype) == 0) return fail(CRP_ERR_INVALID, "%s: unknown dtype %d", what, f->dtype);
+    if (f->layout != CRP_LAYOUT_LINEAR && f->layout != CRP_LAYOUT_CELL8)
+        return fail(CRP_ERR_INVALID, "%s: unknown layout %d", what, f->layout);
+    uint64_t n0 = f->n[0], n1 = f->n[1], n2 = f->n[2];
+    if (f->layout == CRP_LAYOUT_LINEAR && 3ull * (n0 + 1) * (n1 + 1) * (n2 + 1) >= (1ull << 32))
+        return fail(CRP_ERR_UNSUPPORTED, "%s: LINEAR layout limited to 2^32 stored values", what);
+    if (f->layout == CRP_LAYOUT_CELL8 && n0 * n1 * n2 >= (1ull << 32))
+        return fail(CRP_ERR_UNSUPPORTED, "%s: CELL8 layout limited to 2^32 cells", what);
+    if (need_data && !f->data) return fail(CRP_ERR_INVALID, "%s: null data pointer", what);
+    return CRP_OK;
+}
+
+crp::FieldDev make_field_dev(const crp_field &f) {
+    crp::FieldDev d;
+    std::memset(&d, 0, sizeof d);
+    d.data = f.data;
+    for (int a = 0; a < 3; ++a) {
+        d.n[a] = f.n[a];
+        d.origin[a] = f.origin[a];
+    }
+    d.pow2 = is_pow2(f.n[0]) && is_pow2(f.n[1]) && is_pow2(f.n[2]);
+    d.inv_spacing = 1.0 / f.spacing;
+    d.value_scale = f.value_scale;
+    d.sy = (uint32_t)(f.n[2] + 1);
+    d.sx = (uint32_t)((f.n[1] + 1) * (f.n[2] + 1));
+    d.cy = (uint32_t)f.n[2];
+    d.cx = (uint32_t)((uint64_t)f.n[1] * f.n[2]);
+    d.dtype = f.dtype;
+    d.layout = f.layout;
+    return d;
+}
+
+crp_status check_params(const crp_params *p, int32_t n_fields, int i) {
+    if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return fail(CRP_ERR_INVALID, "params[%d]: tol must be > 0", i);
+    if (!(p->h_min > 0.0) || !std::isfinite(p->h_max) || !(p->h_max >= p->h_min))
+        return fail(CRP_ERR_INVALID, "params[%d]: need 0 < h_min <= h_max < inf", i);
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(p->obs_center[a])) return fail(CRP_ERR_INVALID, "params[%d]: centre not finite", i);
+    if (!std::isfinite(p->obs_radius)) return fail(CRP_ERR_INVALID, "params[%d]: radius not finite", i);
+    if (std::isnan(p->l_max) || !(p->l_max > 0.0))
+        return fail(CRP_ERR_INVALID, "params[%d]: l_max must be > 0 (or +inf)", i);
+    if (p->max_steps < 0) return fail(CRP_ERR_INVALID, "params[%d]: max_steps < 0", i);
+    if (!std::isfinite(p->l_max) && p->max_steps == 0)
+        return fail(CRP_ERR_INVALID, "params[%d]: without l_max a max_steps budget is required", i);
+    if (std::isfinite(p->l_max) && p->h_min < p->l_max * 1e-14)
+        return fail(CRP_ERR_INVALID, "params[%d]: h_min below the FP64 resolution of l_max", i);
+    if (p->field_index < 0 || p->field_index >= n_fields)
+        return fail(CRP_ERR_INVALID, "params[%d]: field_index %d out of range", i, p->field_index);
+    return CRP_OK;
+}
+
+crp::ParamsDev make_params_dev(const crp_params &p) {
+    crp::ParamsDev d;
+    std::memset(&d, 0, sizeof d);
+    d.tol = p.tol;
+    d.h_min = p.h_min;
+    d.h_max = p.h_max;
+    for (int a = 0; a < 3; ++a) d.center[a] = p.obs_center[a];
+    d.radius = p.obs_radius;
+    d.r2 = p.obs_radius * p.obs_radius;
+    d.l_max = p.l_max;
+    d.max_steps = p.max_steps;
+    d.field_index = p.field_index;
+    d.sphere_on = p.obs_radius > 0.0;
+    d.lmax_on = std::isfinite(p.l_max);
+    return d;
+}
+
+int cu_count() {
+    static thread_local int dev_cached = -1, cus_cached = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (dev != dev_cached) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        dev_cached = dev;
+        cus_cached = cus;
+    }
+    return cus_cached;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *crp_last_error(void) { return g_last_error.c_str(); }
+
+const char *crp_version(void) { return "crp-mi355x 0.1 (gfx950)"; }
+
+size_t crp_field_bytes(const crp_field *f) {
+    if (check_field(f, false, "crp_field_bytes") != CRP_OK) return 0;
+    uint64_t n0 = f->n[0], n1 = f->n[1], n2 = f->n[2];
+    uint64_t vals = f->layout == CRP_LAYOUT_CELL8 ? n0 * n1 * n2 * 32ull : 3ull * (n0 + 1) * (n1 + 1) * (n2 + 1);
+    return (size_t)(vals * dtype_size(f->dtype));
+}
+
+crp_status crp_field_upload(const crp_field *f, const void *src, int32_t src_dtype, void *stream) {
+    crp_status st = check_field(f, true, "crp_field_upload");
+    if (st != CRP_OK) return st;
+    if (!src) return fail(CRP_ERR_INVALID, "crp_field_upload: null source");
+    if (src_dtype != CRP_F64 && src_dtype != CRP_F32)
+        return fail(CRP_ERR_INVALID, "crp_field_upload: source dtype must be F64 or F32");
+    uint64_t src_bytes = 3ull * f->n[0] * f->n[1] * f->n[2] * dtype_size(src_dtype);
+    const char *s0 = static_cast<const char *>(src);
+    const char *d0 = static_cast<const char *>(f->data);
+    if (s0 < d0 + crp_field_bytes(f) && d0 < s0 + src_bytes)
+        return fail(CRP_ERR_INVALID, "crp_field_upload: source and destination overlap");
+    crp::FieldDev d = make_field_dev(*f);
+    hipError_t e = crp::launch_upload(d, src, src_dtype, f->data, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_error(e, "crp_field_upload");
+    return ok();
+}
+
+size_t crp_workspace_bytes(int64_t n, int32_t n_fields, int32_t n_params) {
+    if (n < 0 || n_fields < 1 || n_params < 1) return 0;
+    return crp::ws_layout(n, n_fields, n_params).total;
+}
+
+crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_params *params, int32_t n_params,
+                         const crp_particles *p, int64_t n, int32_t precision, const crp_tuning *tuning,
+                         int64_t *counters, void *workspace, size_t workspace_bytes, void *stream) {
+    const char *fn = "crp_propagate";
+    if (!fields || n_fields < 1 || n_fields > 4096) return fail(CRP_ERR_INVALID, "%s: need 1..4096 fields", fn);
+    if (!params || n_params < 1 || n_params > 65536) return fail(CRP_ERR_INVALID, "%s: need 1..65536 params", fn);
+    if (!p) return fail(CRP_ERR_INVALID, "%s: null particles", fn);
+    if (n < 0 || n > (int64_t)0x7fffffff) return fail(CRP_ERR_INVALID, "%s: n = %lld out of range", fn, (long long)n);
+    for (int i = 0; i < n_fields; ++i) {
+        crp_status st = check_field(&fields[i], true, fn);
+        if (st != CRP_OK) return st;
+        if (fields[i].dtype != fields[0].dtype || fields[i].layout != fields[0].layout)
+            return fail(CRP_ERR_INVALID, "%s: all fields of one call must share dtype and layout", fn);
+    }
+    for (int i = 0; i < n_params; ++i) {
+        crp_status st = check_params(&params[i], n_fields, i);
+        if (st != CRP_OK) return st;
+    }
+    if (n > 0 && (!p->x || !p->y || !p->z || !p->ux || !p->uy || !p->uz || !p->energy || !p->charge ||
+                  !p->length || !p->h_next || !p->status || !p->n_accepted || !p->n_rejected))
+        return fail(CRP_ERR_INVALID, "%s: a required particle array is null", fn);
+    if (n > 0 && n_params > 1 && !p->param_index)
+        return fail(CRP_ERR_INVALID, "%s: param_index is required with several parameter groups", fn);
+    if (precision != CRP_PREC_FP64 && precision != CRP_PREC_MIXED_F64ACC && precision != CRP_PREC_MIXED_DFACC)
+        return fail(CRP_ERR_INVALID, "%s: unknown precision %d", fn, precision);
+    if (precision != CRP_PREC_FP64) return fail(CRP_ERR_UNSUPPORTED, "%s: precision %d not built", fn, precision);
+    crp_tuning t = {256, 4, 1, 1};
+    if (tuning) t = *tuning;
+    if (t.block_size != 64 && t.block_size != 128 && t.block_size != 256)
+        return fail(CRP_ERR_INVALID, "%s: block_size must be 64, 128 or 256", fn);
+    if (t.blocks_per_cu < 0 || t.blocks_per_cu > 64)
+        return fail(CRP_ERR_INVALID, "%s: blocks_per_cu must be in [0, 64]", fn);
+    if (t.refill_threshold < 1 || t.refill_threshold > 64)
+        return fail(CRP_ERR_INVALID, "%s: refill_threshold must be in [1, 64]", fn);
+    crp::WsLayout wl = crp::ws_layout(n, n_fields, n_params);
+    if (n == 0) return ok();
+    if (!workspace || workspace_bytes < wl.total)
+        return fail(CRP_ERR_WORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, wl.total,
+                    workspace ? workspace_bytes : (size_t)0);
+    if (reinterpret_cast<uintptr_t>(workspace) & 255)
+        return fail(CRP_ERR_WORKSPACE, "%s: workspace must be 256-byte aligned", fn);
+
+    int cus = cu_count();
+    if (cus <= 0) return fail(CRP_ERR_DEVICE, "%s: no HIP device available", fn);
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(workspace);
+    std::vector<crp::FieldDev> fd(n_fields);
+    for (int i = 0; i < n_fields; ++i) fd[i] = make_field_dev(fields[i]);
+    std::vector<crp::ParamsDev> pd(n_params);
+    for (int i = 0; i < n_params; ++i) pd[i] = make_params_dev(params[i]);
+    hipError_t e = crp::launch_write_table(ws + wl.fields, fd.data(), fd.size() * sizeof(crp::FieldDev), s);
+    if (e == hipSuccess) e = crp::launch_write_table(ws + wl.params, pd.data(), pd.size() * sizeof(crp::ParamsDev), s);
+    if (e == hipSuccess) e = crp::launch_fill_u64(reinterpret_cast<unsigned long long *>(ws), 0ull, 1, s);
+    int32_t *order = nullptr;
+    if (e == hipSuccess && t.order_by_rigidity) {
+        order = reinterpret_cast<int32_t *>(ws + wl.order);
+        e = crp::launch_order_by_rigidity(p->energy, p->charge, p->status, n, order,
+                                          reinterpret_cast<unsigned int *>(ws + wl.buckets), s);
+    }
+    if (e != hipSuccess) return device_error(e, fn);
+
+    crp::PropArgs a;
+    a.x = p->x;
+    a.y = p->y;
+    a.z = p->z;
+    a.ux = p->ux;
+    a.uy = p->uy;
+    a.uz = p->uz;
+    a.energy = p->energy;
+    a.charge = p->charge;
+    a.length = p->length;
+    a.h_next = p->h_next;
+    a.time = p->time;
+    a.status = p->status;
+    a.param_index = p->param_index;
+    a.n_acc = p->n_accepted;
+    a.n_rej = p->n_rejected;
+    a.n = n;
+    a.fields = reinterpret_cast<const crp::FieldDev *>(ws + wl.fields);
+    a.params = reinterpret_cast<const crp::ParamsDev *>(ws + wl.params);
+    a.order = order;
+    a.queue = reinterpret_cast<unsigned long long *>(ws);
+    a.counters = reinterpret_cast<unsigned long long *>(counters);
+    a.refill_threshold = t.refill_threshold;
+    a.n_params = n_params;
+
+    int64_t need_blocks = (n + t.block_size - 1) / t.block_size;
+    int64_t blocks = t.blocks_per_cu == 0 ? need_blocks : (int64_t)cus * t.blocks_per_cu;
+    if (blocks > need_blocks) blocks = need_blocks;
+    bool multi = n_params > 1 || p->param_index != nullptr;
+    e = crp::launch_propagate_fp64(a, fields[0].dtype, fields[0].layout, multi, (int)blocks, t.block_size, s);
+    if (e != hipSuccess) return device_error(e, fn);
+    return ok();
+}
+
+crp_status crp_selftest_arith(const double *in, double *out, int64_t n, int32_t op, void *stream) {
+    if (n < 0) return fail(CRP_ERR_INVALID, "crp_selftest_arith: n < 0");
+    if (n > 0 && (!in || !out)) return fail(CRP_ERR_INVALID, "crp_selftest_arith: null pointer");
+    if (op < 0 || op > 5) return fail(CRP_ERR_INVALID, "crp_selftest_arith: unknown op %d", op);
+    hipError_t e = crp::launch_selftest(in, out, n, op, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_error(e, "crp_selftest_arith");
+    return ok();
+}
+
+}  // extern "C"

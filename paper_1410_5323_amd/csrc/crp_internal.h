@@ -1,0 +1,96 @@
+// crp_internal.h -- descriptors shared by the host ABI and the gfx950 kernels of libcrp.
+//
+// Device-side copies of the field and parameter descriptors live in the
+// caller's workspace; the host packs them (crp_host.cpp) and a small kernel
+// writes them there, so every call is a pure sequence of stream operations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/crp.h"
+
+namespace crp {
+
+// Device descriptor of one field grid (128 bytes).
+struct FieldDev {
+    const void *data;
+    int32_t n[3];          // nodes per axis
+    int32_t pow2;          // 1 if every n is a power of two (wrap by mask)
+    double origin[3];
+    double inv_spacing;    // 1.0 / spacing (one FP64 division on the host)
+    double value_scale;    // nG per stored unit
+    uint32_t sx, sy;       // LINEAR: node strides of the padded grid, (n1+1)(n2+1) and (n2+1)
+    uint32_t cy, cx;       // CELL8: cell strides n2 and n1*n2
+    int32_t dtype, layout;
+    int32_t pad_[10];
+};
+static_assert(sizeof(FieldDev) == 128, "FieldDev layout");
+
+// Device descriptor of one parameter group (128 bytes).
+struct ParamsDev {
+    double tol, h_min, h_max;
+    double center[3];
+    double radius, r2;     // r2 = radius * radius
+    double l_max;
+    int64_t max_steps;
+    int32_t field_index;
+    int32_t sphere_on;     // radius > 0
+    int32_t lmax_on;       // l_max finite
+    int32_t pad_[9];
+};
+static_assert(sizeof(ParamsDev) == 128, "ParamsDev layout");
+
+// Workspace layout (offsets in bytes from the 256-byte aligned base).
+//   [0, 256)                 control: queue head (uint64 at 0)
+//   [256, 256 + 128*nf)      FieldDev table
+//   then 128*np              ParamsDev table
+//   then 4*n                 order (int32 particle indices, rigidity buckets ascending)
+//   then 4*(NBUCKET+1)*2     bucket counts and cursors
+constexpr int NBUCKET = 256;
+
+struct WsLayout {
+    size_t fields, params, order, buckets, total;
+};
+
+inline WsLayout ws_layout(int64_t n, int32_t nf, int32_t np) {
+    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+    WsLayout w;
+    w.fields = 256;
+    w.params = up(w.fields + 128 * size_t(nf));
+    w.order = up(w.params + 128 * size_t(np));
+    w.buckets = up(w.order + 4 * size_t(n > 0 ? n : 0));
+    w.total = up(w.buckets + 8 * size_t(NBUCKET + 1));
+    return w;
+}
+
+// Kernel arguments of the propagation kernels (passed by value).
+struct PropArgs {
+    double *x, *y, *z, *ux, *uy, *uz;
+    const double *energy;
+    const int32_t *charge;
+    double *length, *h_next, *time;
+    int32_t *status;
+    const int32_t *param_index;
+    int64_t *n_acc, *n_rej;
+    int64_t n;
+    const FieldDev *fields;
+    const ParamsDev *params;
+    const int32_t *order;            // NULL: particles in index order
+    unsigned long long *queue;       // work-queue head
+    unsigned long long *counters;    // NULL or CRP_NCOUNTERS accumulators
+    int32_t refill_threshold;
+    int32_t n_params;
+};
+
+// Launchers (defined in the .hip files, called by crp_host.cpp).
+hipError_t launch_write_table(void *dst, const void *src, size_t bytes, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *dst, unsigned long long v, int count, hipStream_t s);
+hipError_t launch_order_by_rigidity(const double *energy, const int32_t *charge, const int32_t *status,
+                                    int64_t n, int32_t *order, unsigned int *buckets, hipStream_t s);
+hipError_t launch_propagate_fp64(const PropArgs &a, int dtype, int layout, bool multi, int blocks,
+                                 int block_size, hipStream_t s);
+hipError_t launch_upload(const FieldDev &f, const void *src, int src_dtype, void *dst, hipStream_t s);
+hipError_t launch_selftest(const double *in, double *out, int64_t n, int op, hipStream_t s);
+
+}  // namespace crp

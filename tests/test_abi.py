@@ -1,0 +1,136 @@
+"""The C-ABI library loads, exports every function include/crp.h declares, and
+rejects bad arguments synchronously (no device work is needed for that)."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    txt = open(os.path.join(ROOT, "include", "crp.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(crp_[a-z_0-9]+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def crp():
+    from paper_1410_5323_amd import crp as m
+    m.lib()
+    return m
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("crp_field_upload", "crp_propagate", "crp_field_bytes", "crp_workspace_bytes",
+                     "crp_last_error"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(crp):
+    L = crp.lib()
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_struct_sizes_match_header(crp):
+    assert C.sizeof(crp.crp_field) == 4 * 6 + 8 * 3 + 8 + 8 + 8
+    assert C.sizeof(crp.crp_params) == 8 * 3 + 8 * 3 + 8 + 8 + 8 + 8
+    assert C.sizeof(crp.crp_particles) == 16 * 8
+    assert C.sizeof(crp.crp_tuning) == 16
+
+
+def _field(crp, n=(32, 32, 32), dtype=None, layout=None, spacing=0.1):
+    d = crp.crp_field()
+    d.n[0], d.n[1], d.n[2] = n
+    d.dtype = crp.CRP_F32 if dtype is None else dtype
+    d.layout = crp.CRP_LAYOUT_LINEAR if layout is None else layout
+    d.spacing = spacing
+    d.value_scale = 1.0
+    return d
+
+
+def test_field_bytes(crp):
+    assert crp.crp_field_bytes(_field(crp)) == 33 ** 3 * 3 * 4
+    assert crp.crp_field_bytes(_field(crp, dtype=crp.CRP_F16, layout=crp.CRP_LAYOUT_CELL8)) == 32 ** 3 * 32 * 2
+    assert crp.crp_field_bytes(_field(crp, n=(1, 32, 32))) == 0
+    assert crp.crp_field_bytes(_field(crp, spacing=-1.0)) == 0
+    assert crp.crp_field_bytes(_field(crp, dtype=9)) == 0
+    assert crp.crp_field_bytes(_field(crp, n=(1024, 1024, 1024))) == 1025 ** 3 * 3 * 4
+    assert crp.crp_field_bytes(_field(crp, n=(1200, 1200, 1200))) == 0  # beyond 2^32 stored values
+
+
+def test_workspace_bytes(crp):
+    a = crp.crp_workspace_bytes(1000, 1, 1)
+    b = crp.crp_workspace_bytes(1000000, 64, 64)
+    assert a >= 256 + 128 * 2 + 4000 and a % 256 == 0
+    assert b > a and crp.crp_workspace_bytes(-1, 1, 1) == 0
+
+
+def _call(crp, fields, nf, params, np_, parts, n, prec=0, ws=None, wsb=0):
+    L = crp.lib()
+    return L.crp_propagate(fields, nf, params, np_, parts, n, prec, None, None, ws, wsb, None)
+
+
+def test_propagate_rejects_bad_arguments_without_device(crp):
+    f = _field(crp)
+    f.data = 0x1000
+    farr = (crp.crp_field * 1)(f)
+    p = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0)
+    parr = (crp.crp_params * 1)(p)
+    parts = crp.crp_particles(**{k: 0x2000 for k in crp._PARTICLE_FIELDS})
+    assert _call(crp, None, 1, parr, 1, C.byref(parts), 10) == crp.CRP_ERR_INVALID
+    assert "fields" in crp.crp_last_error()
+    assert _call(crp, farr, 1, parr, 1, None, 10) == crp.CRP_ERR_INVALID
+    assert _call(crp, farr, 1, parr, 1, C.byref(parts), -5) == crp.CRP_ERR_INVALID
+    for bad in [dict(tol=0.0), dict(h_min=0.0), dict(h_min=2.0), dict(l_max=math.inf),
+                dict(l_max=-1.0), dict(obs_radius=math.nan)]:
+        kw = dict(tol=1e-4, h_min=0.01, h_max=1.0, l_max=10.0)
+        kw.update(bad)
+        q = (crp.crp_params * 1)(crp.make_params(**kw))
+        assert _call(crp, farr, 1, q, 1, C.byref(parts), 10) == crp.CRP_ERR_INVALID, bad
+    q = (crp.crp_params * 1)(crp.make_params(1e-4, 0.01, 1.0, l_max=10.0, field_index=1))
+    assert _call(crp, farr, 1, q, 1, C.byref(parts), 10) == crp.CRP_ERR_INVALID
+    nodata = _field(crp)
+    assert _call(crp, (crp.crp_field * 1)(nodata), 1, parr, 1, C.byref(parts), 10) == crp.CRP_ERR_INVALID
+    missing = crp.crp_particles(**{k: 0x2000 for k in crp._PARTICLE_FIELDS})
+    missing.energy = None
+    assert _call(crp, farr, 1, parr, 1, C.byref(missing), 10) == crp.CRP_ERR_INVALID
+    assert _call(crp, farr, 1, parr, 1, C.byref(parts), 10, prec=7) == crp.CRP_ERR_INVALID
+    # workspace missing
+    assert _call(crp, farr, 1, parr, 1, C.byref(parts), 10) == crp.CRP_ERR_WORKSPACE
+    # empty call is a no-op
+    assert _call(crp, farr, 1, parr, 1, C.byref(parts), 0) == crp.CRP_OK
+
+
+def test_valid_call_without_device_reports_device_error(crp):
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    f = _field(crp)
+    f.data = 0x1000
+    parts = crp.crp_particles(**{k: 0x2000 for k in crp._PARTICLE_FIELDS})
+    ws = 0x100000
+    rc = _call(crp, (crp.crp_field * 1)(f), 1, (crp.crp_params * 1)(crp.make_params(1e-4, 0.01, 1.0, l_max=1.0)),
+               1, C.byref(parts), 10, ws=ws, wsb=1 << 20)
+    assert rc == crp.CRP_ERR_DEVICE
+
+
+def test_upload_rejects_bad_arguments(crp):
+    L = crp.lib()
+    f = _field(crp)
+    assert L.crp_field_upload(C.byref(f), 0x1000, crp.CRP_F64, None) == crp.CRP_ERR_INVALID  # no data
+    f.data = 0x100000
+    assert L.crp_field_upload(C.byref(f), None, crp.CRP_F64, None) == crp.CRP_ERR_INVALID
+    assert L.crp_field_upload(C.byref(f), 0x1000, crp.CRP_F16, None) == crp.CRP_ERR_INVALID
+    assert L.crp_field_upload(C.byref(f), 0x100008, crp.CRP_F64, None) == crp.CRP_ERR_INVALID  # overlap
+
+
+def test_selftest_rejects_bad_op(crp):
+    L = crp.lib()
+    assert L.crp_selftest_arith(0x1000, 0x2000, 4, 99, None) == crp.CRP_ERR_INVALID
+    assert L.crp_selftest_arith(None, None, 4, 0, None) == crp.CRP_ERR_INVALID
