@@ -83,10 +83,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="production_256cube")
     ap.add_argument("--n", type=int, default=None, help="particle count (default: the workload's)")
-    ap.add_argument("--layout", default="linear", choices=["linear", "cell8"])
+    ap.add_argument("--layout", default="cell8", choices=["linear", "cell8"])
     ap.add_argument("--block-size", type=int, default=256)
     ap.add_argument("--blocks-per-cu", type=int, default=4)
-    ap.add_argument("--refill-threshold", type=int, default=1)
+    ap.add_argument("--refill-threshold", type=int, default=32)
+    ap.add_argument("--cache-cells", type=int, default=0, help="1 on, -1 off, 0 automatic")
     ap.add_argument("--no-order", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=200000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -127,7 +128,7 @@ def main():
     ws = torch.empty(crp.crp_workspace_bytes(n, 1, 1), dtype=torch.uint8, device=dev)
     counters = torch.zeros(crp.NCOUNTERS, dtype=torch.int64, device=dev)
     tuning = crp.make_tuning(args.block_size, args.blocks_per_cu, args.refill_threshold,
-                             0 if args.no_order else 1)
+                             0 if args.no_order else 1, args.cache_cells)
     stream = torch.cuda.current_stream()
 
     def step(ev=None):
@@ -187,7 +188,8 @@ def main():
                    "h_min_mpc": w.h_min, "h_max_mpc": w.h_max, "obs_radius_mpc": w.obs_radius,
                    "l_max_mpc": w.max_length, "precision": "fp64",
                    "tuning": {"block_size": args.block_size, "blocks_per_cu": args.blocks_per_cu,
-                              "refill_threshold": args.refill_threshold, "order_by_rigidity": not args.no_order}},
+                              "refill_threshold": args.refill_threshold, "order_by_rigidity": not args.no_order,
+                              "cache_cells": args.cache_cells}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": None if traffic is None else traffic},
@@ -196,6 +198,8 @@ def main():
                    "rejected_per_launch": int(c[2]) / args.steps,
                    "event_evaluations_per_launch": int(c[3]) / args.steps,
                    "floor_hits_per_launch": int(c[4]) / args.steps,
+                   "cell_loads_per_launch": int(c[6]) / args.steps,
+                   "cell_cache_hit_rate": 1.0 - int(c[6]) / max(1, 6 * evals),
                    "evaluations_per_s": evals / elapsed,
                    "avg_launch_ms": avg_launch_s * 1e3,
                    "algorithmic_bytes_per_evaluation": bytes_per_eval,

@@ -119,8 +119,11 @@ typedef struct {
 typedef struct {
     int32_t block_size;       /* threads per block: 64, 128 or 256 (default 256) */
     int32_t blocks_per_cu;    /* persistent blocks per compute unit (default 4); 0 = one lane per particle */
-    int32_t refill_threshold; /* refill a wavefront when at least this many lanes are idle (default 1) */
+    int32_t refill_threshold; /* refill a wavefront when at least this many lanes are idle (default 32) */
     int32_t order_by_rigidity;/* 1: hand out low-rigidity particles first (longest first); default 1 */
+    int32_t cache_cells;      /* keep each lane's last cell in LDS and skip repeated loads:
+                                 1 on, -1 off, 0 automatic (on for LINEAR, off for CELL8; default) */
+    int32_t reserved[3];
 } crp_tuning;
 
 /* Counters accumulated by crp_propagate into an optional [dev] int64 array. */
@@ -131,6 +134,7 @@ enum {
     CRP_CNT_EVENT_EVALS = 3,  /* evaluations spent locating sphere crossings */
     CRP_CNT_FLOOR_HITS = 4,   /* steps accepted at h_min with error above tolerance */
     CRP_CNT_PARTICLES = 5,    /* particles taken from the queue */
+    CRP_CNT_CELL_LOADS = 6,   /* field lookups that read grid memory (the others hit the cell cache) */
     CRP_NCOUNTERS = 8
 };
 
@@ -168,6 +172,23 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
  * fifth root x^(-1/5), 5 the controller's shrink factor 1/sqrt(sqrt(x)).  Used
  * to check that the device rounds exactly like the host. */
 crp_status crp_selftest_arith(const double *in, double *out, int64_t n, int32_t op, void *stream);
+
+/* Gather microbenchmark (measurement only): lanes threads each perform
+ * lookups_per_lane independent field lookups, with the propagation kernel's
+ * layout, dtype and FP64 trilinear arithmetic (section 3.2: the lookup cost of
+ * regular grids), at pseudo-random positions: uniform over the periodic box
+ * when spread <= 0, else a cloud of standard deviation ~spread Mpc around the
+ * origin.  sink: [dev] double[lanes], receives a checksum per lane.  Gives
+ * the achievable lookup rate that bounds the propagation kernel. */
+crp_status crp_bench_gather(const crp_field *f, int64_t lanes, int64_t lookups_per_lane, double spread,
+                            uint64_t seed, double *sink, void *stream);
+
+/* Streaming microbenchmark (measurement only): reads bytes of src ([dev],
+ * 16-byte aligned, bytes a multiple of 16) with blocks x 256 threads; copies
+ * them to dst ([dev]) when dst is not NULL, else writes per-thread sums to
+ * sink ([dev] double[blocks*256]).  A transfer of known size, used for the
+ * bandwidth ceiling and to calibrate hardware byte counters. */
+crp_status crp_bench_stream(const void *src, void *dst, size_t bytes, double *sink, int32_t blocks, void *stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *crp_last_error(void);

@@ -21,7 +21,7 @@ CRP_LAYOUT_LINEAR, CRP_LAYOUT_CELL8 = 0, 1
 CRP_PREC_FP64, CRP_PREC_MIXED_F64ACC, CRP_PREC_MIXED_DFACC = 0, 1, 2
 STATUS = {"ACTIVE": 0, "ARRIVED": 1, "MAX_LENGTH": 2, "MAX_STEPS": 3, "NONFINITE": 4,
           "CANCELLED": 5, "BAD_INPUT": 6}
-COUNTERS = ["evals", "accepted", "rejected", "event_evals", "floor_hits", "particles"]
+COUNTERS = ["evals", "accepted", "rejected", "event_evals", "floor_hits", "particles", "cell_loads"]
 NCOUNTERS = 8
 DTYPES = {"f64": CRP_F64, "f32": CRP_F32, "f16": CRP_F16, "bf16": CRP_BF16}
 LAYOUTS = {"linear": CRP_LAYOUT_LINEAR, "cell8": CRP_LAYOUT_CELL8}
@@ -55,7 +55,8 @@ class crp_particles(C.Structure):
 
 class crp_tuning(C.Structure):
     _fields_ = [("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("refill_threshold", C.c_int32), ("order_by_rigidity", C.c_int32)]
+                ("refill_threshold", C.c_int32), ("order_by_rigidity", C.c_int32),
+                ("cache_cells", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 _lib = None
@@ -77,6 +78,11 @@ def lib():
                                     C.POINTER(crp_particles), C.c_int64, C.c_int32,
                                     C.POINTER(crp_tuning), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         L.crp_selftest_arith.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+        L.crp_bench_gather.argtypes = [C.POINTER(crp_field), C.c_int64, C.c_int64, C.c_double, C.c_uint64,
+                                       C.c_void_p, C.c_void_p]
+        L.crp_bench_stream.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_int32, C.c_void_p]
+        L.crp_bench_gather.restype = C.c_int
+        L.crp_bench_stream.restype = C.c_int
         L.crp_last_error.restype = C.c_char_p
         L.crp_version.restype = C.c_char_p
         for f in (L.crp_field_upload, L.crp_propagate, L.crp_selftest_arith):
@@ -165,6 +171,16 @@ def crp_selftest_arith(inp, out, op: int, stream=None):
     _check(lib().crp_selftest_arith(_ptr(inp), _ptr(out), n, int(op), _stream_handle(stream)))
 
 
+def crp_bench_gather(field, lanes: int, lookups_per_lane: int, spread: float, seed: int, sink, stream=None):
+    _check(lib().crp_bench_gather(C.byref(field.desc), int(lanes), int(lookups_per_lane), float(spread),
+                                  int(seed), _ptr(sink), _stream_handle(stream)))
+
+
+def crp_bench_stream(src, dst, nbytes: int, sink, blocks: int, stream=None):
+    _check(lib().crp_bench_stream(_ptr(src), _ptr(dst), int(nbytes), _ptr(sink), int(blocks),
+                                  _stream_handle(stream)))
+
+
 # ------------------------------------------------------------- conveniences
 
 @dataclass
@@ -214,8 +230,9 @@ def make_params(tol, h_min, h_max, obs_radius=0.0, l_max=math.inf, obs_center=(0
     return p
 
 
-def make_tuning(block_size=256, blocks_per_cu=4, refill_threshold=1, order_by_rigidity=1) -> crp_tuning:
-    return crp_tuning(block_size, blocks_per_cu, refill_threshold, order_by_rigidity)
+def make_tuning(block_size=256, blocks_per_cu=4, refill_threshold=32, order_by_rigidity=1,
+                cache_cells=0) -> crp_tuning:
+    return crp_tuning(block_size, blocks_per_cu, refill_threshold, order_by_rigidity, cache_cells)
 
 
 def particles_to_device(pos, dir, energy, charge, mass=None, param_index=None, device="cuda",

@@ -89,45 +89,72 @@ __device__ __forceinline__ int cell_axis(double X, double o, double inv, int n, 
     return r < 0 ? r + n : r;
 }
 
-// Trilinear interpolation of the 8 corner vectors v[dz][dy][dx][c]: along x,
-// then y, then z, each a + t (b - a) with one fma.
-__device__ __forceinline__ void trilinear(const double (&v)[2][2][2][3], double tx, double ty, double tz,
-                                          double B[3]) {
+// Grid data is read through global-address-space pointers: the data pointer
+// comes from a descriptor table in memory, so without the cast the compiler
+// would emit flat loads, which also hold up the LDS counter.
+template <class T>
+using global_ptr = const __attribute__((address_space(1))) T *;
+
+template <class T>
+__device__ __forceinline__ global_ptr<T> as_global(const void *p) {
+    return (global_ptr<T>)(p);
+}
+
+// Raw storage type of a grid value (16-bit types are loaded as bits).
+template <class T> struct raw_of { using type = T; };
+template <> struct raw_of<__half> { using type = unsigned short; };
+template <> struct raw_of<__hip_bfloat16> { using type = unsigned short; };
+template <class T> using raw_t = typename raw_of<T>::type;
+
+template <class T> __device__ __forceinline__ T from_raw(raw_t<T> r) { return r; }
+template <> __device__ __forceinline__ __half from_raw<__half>(unsigned short r) { return __ushort_as_half(r); }
+template <> __device__ __forceinline__ __hip_bfloat16 from_raw<__hip_bfloat16>(unsigned short r) {
+    return __ushort_as_bfloat16(r);
+}
+
+// Corner values of cell (i, j, k) in the order v[((dz*2 + dy)*2 + dx)*3 + c].
+// LINEAR (wrap-padded) layout: corner (dx,dy,dz) is node (i+dx, j+dy, k+dz) of
+// the padded grid, so no corner needs a wrap.  CELL8 layout: one record of 32
+// values per cell holding the 8 corners in that order (24 used).
+template <class T, int LAYOUT>
+__device__ __forceinline__ void load_corners(const FieldDev &F, int i, int j, int k, T (&v)[24]) {
+    if (LAYOUT == CRP_LAYOUT_CELL8) {
+        const global_ptr<raw_t<T>> p = as_global<raw_t<T>>(F.data) +
+                                       32ull * (uint64_t)((uint32_t)i * F.cx + (uint32_t)j * F.cy + (uint32_t)k);
+#pragma unroll
+        for (int w = 0; w < 24; ++w) v[w] = from_raw<T>(p[w]);
+    } else {
+        const global_ptr<raw_t<T>> p =
+            as_global<raw_t<T>>(F.data) + 3u * ((uint32_t)i * F.sx + (uint32_t)j * F.sy + (uint32_t)k);
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx)
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy) {
+                const global_ptr<raw_t<T>> q = p + 3u * ((uint32_t)dx * F.sx + (uint32_t)dy * F.sy);
+#pragma unroll
+                for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) v[((dz * 2 + dy) * 2 + dx) * 3 + c] = from_raw<T>(q[3 * dz + c]);
+            }
+    }
+}
+
+// Trilinear interpolation of stored corner values, converted exactly to FP64,
+// one component at a time, then scaled by value_scale (a multiplication by 1
+// for FP64/FP32 grids).
+template <class T>
+__device__ __forceinline__ void interp_corners(const FieldDev &F, const T (&v)[24], double tx, double ty, double tz,
+                                               double B[3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        double c00 = lerp(v[0][0][0][c], v[0][0][1][c], tx);
-        double c10 = lerp(v[0][1][0][c], v[0][1][1][c], tx);
-        double c01 = lerp(v[1][0][0][c], v[1][0][1][c], tx);
-        double c11 = lerp(v[1][1][0][c], v[1][1][1][c], tx);
+        double c00 = lerp(to_f64<T>(v[0 + c]), to_f64<T>(v[3 + c]), tx);    // (dy, dz) = (0, 0)
+        double c10 = lerp(to_f64<T>(v[6 + c]), to_f64<T>(v[9 + c]), tx);    // (1, 0)
+        double c01 = lerp(to_f64<T>(v[12 + c]), to_f64<T>(v[15 + c]), tx);  // (0, 1)
+        double c11 = lerp(to_f64<T>(v[18 + c]), to_f64<T>(v[21 + c]), tx);  // (1, 1)
         double c0 = lerp(c00, c10, ty);
         double c1 = lerp(c01, c11, ty);
         B[c] = lerp(c0, c1, tz);
     }
-}
-
-// Field lookup at X (Mpc) -> B (nG) for the LINEAR (wrap-padded) layout:
-// corner (dx,dy,dz) of cell (i,j,k) is node (i+dx, j+dy, k+dz) of the padded
-// grid, so no corner needs a wrap.
-template <class T>
-__device__ __forceinline__ void lookup_linear(const FieldDev &F, const double X[3], double B[3]) {
-    double tx, ty, tz;
-    int i = cell_axis(X[0], F.origin[0], F.inv_spacing, F.n[0], F.pow2, tx);
-    int j = cell_axis(X[1], F.origin[1], F.inv_spacing, F.n[1], F.pow2, ty);
-    int k = cell_axis(X[2], F.origin[2], F.inv_spacing, F.n[2], F.pow2, tz);
-    const T *p = static_cast<const T *>(F.data) +
-                 3u * ((uint32_t)i * F.sx + (uint32_t)j * F.sy + (uint32_t)k);
-    double v[2][2][2][3];
-#pragma unroll
-    for (int dx = 0; dx < 2; ++dx)
-#pragma unroll
-        for (int dy = 0; dy < 2; ++dy) {
-            const T *q = p + 3u * ((uint32_t)dx * F.sx + (uint32_t)dy * F.sy);
-#pragma unroll
-            for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) v[dz][dy][dx][c] = to_f64<T>(q[3 * dz + c]);
-        }
-    trilinear(v, tx, ty, tz, B);
     if (F.value_scale != 1.0) {
         B[0] = B[0] * F.value_scale;
         B[1] = B[1] * F.value_scale;
@@ -135,46 +162,78 @@ __device__ __forceinline__ void lookup_linear(const FieldDev &F, const double X[
     }
 }
 
-// Field lookup for the CELL8 layout: one record of 32 values per cell, the
-// 8 corner vectors in the order (dz, dy, dx, component), 24 used.
-template <class T>
-__device__ __forceinline__ void lookup_cell8(const FieldDev &F, const double X[3], double B[3]) {
-    double tx, ty, tz;
-    int i = cell_axis(X[0], F.origin[0], F.inv_spacing, F.n[0], F.pow2, tx);
-    int j = cell_axis(X[1], F.origin[1], F.inv_spacing, F.n[1], F.pow2, ty);
-    int k = cell_axis(X[2], F.origin[2], F.inv_spacing, F.n[2], F.pow2, tz);
-    const T *p = static_cast<const T *>(F.data) +
-                 32ull * (uint64_t)((uint32_t)i * F.cx + (uint32_t)j * F.cy + (uint32_t)k);
-    double v[2][2][2][3];
-#pragma unroll
-    for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-        for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-            for (int dx = 0; dx < 2; ++dx)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) v[dz][dy][dx][c] = to_f64<T>(p[((dz * 2 + dy) * 2 + dx) * 3 + c]);
-    trilinear(v, tx, ty, tz, B);
-    if (F.value_scale != 1.0) {
-        B[0] = B[0] * F.value_scale;
-        B[1] = B[1] * F.value_scale;
-        B[2] = B[2] * F.value_scale;
-    }
-}
-
+// Field lookup at X (Mpc) -> B (nG), reading the corners from memory.
 template <class T, int LAYOUT>
 __device__ __forceinline__ void lookup(const FieldDev &F, const double X[3], double B[3]) {
-    if (LAYOUT == CRP_LAYOUT_CELL8)
-        lookup_cell8<T>(F, X, B);
-    else
-        lookup_linear<T>(F, X, B);
+    double tx, ty, tz;
+    int i = cell_axis(X[0], F.origin[0], F.inv_spacing, F.n[0], F.pow2, tx);
+    int j = cell_axis(X[1], F.origin[1], F.inv_spacing, F.n[1], F.pow2, ty);
+    int k = cell_axis(X[2], F.origin[2], F.inv_spacing, F.n[2], F.pow2, tz);
+    T v[24];
+    load_corners<T, LAYOUT>(F, i, j, k, v);
+    interp_corners<T>(F, v, tx, ty, tz, B);
+}
+
+// Per-lane cache of the corner values of the last cell looked up.  A particle
+// whose steps are small compared with the grid spacing looks up the same cell
+// many times in a row; those lookups then read no global memory.  The key
+// (cell and field) lives in registers, the 24 values in LDS, one column per
+// thread ([value][thread], so the reads of a wavefront hit distinct banks).
+// The values are the stored ones: results are bit-identical with or without it.
+constexpr int CACHE_BLOCK = 256;
+
+template <class T>
+struct CellCache {
+    uint32_t key;   // cell index (i*n1 + j)*n2 + k, 0xffffffff = empty
+    int32_t field;  // field the cell belongs to
+    T (*v)[CACHE_BLOCK];  // LDS [24][CACHE_BLOCK]
+    int t;          // thread's column
+    int misses;     // lookups that read global memory (diagnostic)
+};
+
+template <class T>
+__device__ __forceinline__ void cache_reset(CellCache<T> &c, T (*lds)[CACHE_BLOCK], int t) {
+    c.key = 0xffffffffu;
+    c.field = -1;
+    c.v = lds;
+    c.t = t;
+    c.misses = 0;
+}
+
+template <class T, int LAYOUT, bool CACHE>
+__device__ __forceinline__ void lookup_cached(const FieldDev &F, int fid, const double X[3], double B[3],
+                                              CellCache<T> &cache) {
+    if (!CACHE) {
+        lookup<T, LAYOUT>(F, X, B);
+        cache.misses++;
+        return;
+    }
+    double tx, ty, tz;
+    int i = cell_axis(X[0], F.origin[0], F.inv_spacing, F.n[0], F.pow2, tx);
+    int j = cell_axis(X[1], F.origin[1], F.inv_spacing, F.n[1], F.pow2, ty);
+    int k = cell_axis(X[2], F.origin[2], F.inv_spacing, F.n[2], F.pow2, tz);
+    uint32_t key = ((uint32_t)i * (uint32_t)F.n[1] + (uint32_t)j) * (uint32_t)F.n[2] + (uint32_t)k;
+    T v[24];
+    if (key != cache.key || fid != cache.field) {
+        load_corners<T, LAYOUT>(F, i, j, k, v);
+#pragma unroll
+        for (int w = 0; w < 24; ++w) cache.v[w][cache.t] = v[w];
+        cache.key = key;
+        cache.field = fid;
+        cache.misses++;
+    } else {
+#pragma unroll
+        for (int w = 0; w < 24; ++w) v[w] = cache.v[w][cache.t];
+    }
+    interp_corners<T>(F, v, tx, ty, tz, B);
 }
 
 // Right-hand side in path length: k = (U, kappa * U x B(X)) for Y = (X, U).
-template <class T, int LAYOUT>
-__device__ __forceinline__ void rhs(const FieldDev &F, double kap, const double Y[6], double k[6]) {
+template <class T, int LAYOUT, bool CACHE>
+__device__ __forceinline__ void rhs(const FieldDev &F, int fid, CellCache<T> &cache, double kap, const double Y[6],
+                                    double k[6]) {
     double B[3];
-    lookup<T, LAYOUT>(F, Y, B);
+    lookup_cached<T, LAYOUT, CACHE>(F, fid, Y, B, cache);
     k[0] = Y[3];
     k[1] = Y[4];
     k[2] = Y[5];
@@ -193,30 +252,30 @@ __device__ __forceinline__ double norm3(double a, double b, double c) { return s
 // position (ex) and direction (eu) parts.  Stage sums accumulate over j in
 // increasing order with fma starting from zero; terms with a zero weight are
 // omitted (they only add a signed zero).
-template <class T, int LAYOUT>
-__device__ __forceinline__ void ck_eval(const FieldDev &F, double kap, const double y[6], double h,
-                                        double y5[6], double &ex, double &eu) {
+template <class T, int LAYOUT, bool CACHE>
+__device__ __forceinline__ void ck_eval(const FieldDev &F, int fid, CellCache<T> &cache, double kap,
+                                        const double y[6], double h, double y5[6], double &ex, double &eu) {
     double k1[6], k2[6], k3[6], k4[6], k5[6], k6[6], Y[6];
-    rhs<T, LAYOUT>(F, kap, y, k1);
+    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, y, k1);
 #pragma unroll
     for (int c = 0; c < 6; ++c) Y[c] = fma(h, fma(A21, k1[c], 0.0), y[c]);
-    rhs<T, LAYOUT>(F, kap, Y, k2);
+    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k2);
 #pragma unroll
     for (int c = 0; c < 6; ++c) Y[c] = fma(h, fma(A32, k2[c], fma(A31, k1[c], 0.0)), y[c]);
-    rhs<T, LAYOUT>(F, kap, Y, k3);
+    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k3);
 #pragma unroll
     for (int c = 0; c < 6; ++c)
         Y[c] = fma(h, fma(A43, k3[c], fma(A42, k2[c], fma(A41, k1[c], 0.0))), y[c]);
-    rhs<T, LAYOUT>(F, kap, Y, k4);
+    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k4);
 #pragma unroll
     for (int c = 0; c < 6; ++c)
         Y[c] = fma(h, fma(A54, k4[c], fma(A53, k3[c], fma(A52, k2[c], fma(A51, k1[c], 0.0)))), y[c]);
-    rhs<T, LAYOUT>(F, kap, Y, k5);
+    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k5);
 #pragma unroll
     for (int c = 0; c < 6; ++c)
         Y[c] = fma(h, fma(A65, k5[c], fma(A64, k4[c], fma(A63, k3[c], fma(A62, k2[c], fma(A61, k1[c], 0.0))))),
                    y[c]);
-    rhs<T, LAYOUT>(F, kap, Y, k6);
+    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k6);
     double d[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {

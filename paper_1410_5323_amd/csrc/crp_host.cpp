@@ -206,7 +206,7 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
     if (precision != CRP_PREC_FP64 && precision != CRP_PREC_MIXED_F64ACC && precision != CRP_PREC_MIXED_DFACC)
         return fail(CRP_ERR_INVALID, "%s: unknown precision %d", fn, precision);
     if (precision != CRP_PREC_FP64) return fail(CRP_ERR_UNSUPPORTED, "%s: precision %d not built", fn, precision);
-    crp_tuning t = {256, 4, 1, 1};
+    crp_tuning t = {256, 4, 32, 1, 0, 0, 0, 0};
     if (tuning) t = *tuning;
     if (t.block_size != 64 && t.block_size != 128 && t.block_size != 256)
         return fail(CRP_ERR_INVALID, "%s: block_size must be 64, 128 or 256", fn);
@@ -214,6 +214,11 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
         return fail(CRP_ERR_INVALID, "%s: blocks_per_cu must be in [0, 64]", fn);
     if (t.refill_threshold < 1 || t.refill_threshold > 64)
         return fail(CRP_ERR_INVALID, "%s: refill_threshold must be in [1, 64]", fn);
+    if (t.cache_cells < -1 || t.cache_cells > 1)
+        return fail(CRP_ERR_INVALID, "%s: cache_cells must be -1, 0 or 1", fn);
+    // automatic: the LINEAR layout spreads a cell over several lines and gains
+    // from the cache; a CELL8 record is one line that stays hot in L1/L2
+    bool cache = t.cache_cells == 0 ? fields[0].layout == CRP_LAYOUT_LINEAR : t.cache_cells > 0;
     crp::WsLayout wl = crp::ws_layout(n, n_fields, n_params);
     if (n == 0) return ok();
     if (!workspace || workspace_bytes < wl.total)
@@ -271,7 +276,8 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
     int64_t blocks = t.blocks_per_cu == 0 ? need_blocks : (int64_t)cus * t.blocks_per_cu;
     if (blocks > need_blocks) blocks = need_blocks;
     bool multi = n_params > 1 || p->param_index != nullptr;
-    e = crp::launch_propagate_fp64(a, fields[0].dtype, fields[0].layout, multi, (int)blocks, t.block_size, s);
+    e = crp::launch_propagate_fp64(a, fields[0].dtype, fields[0].layout, multi, cache, (int)blocks,
+                                   t.block_size, s);
     if (e != hipSuccess) return device_error(e, fn);
     return ok();
 }
@@ -282,6 +288,28 @@ crp_status crp_selftest_arith(const double *in, double *out, int64_t n, int32_t 
     if (op < 0 || op > 5) return fail(CRP_ERR_INVALID, "crp_selftest_arith: unknown op %d", op);
     hipError_t e = crp::launch_selftest(in, out, n, op, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return device_error(e, "crp_selftest_arith");
+    return ok();
+}
+
+crp_status crp_bench_gather(const crp_field *f, int64_t lanes, int64_t lookups_per_lane, double spread,
+                            uint64_t seed, double *sink, void *stream) {
+    crp_status st = check_field(f, true, "crp_bench_gather");
+    if (st != CRP_OK) return st;
+    if (lanes < 1 || lanes > (int64_t)1 << 30 || lookups_per_lane < 0 || !sink || !std::isfinite(spread))
+        return fail(CRP_ERR_INVALID, "crp_bench_gather: bad lanes, lookups, spread or sink");
+    hipError_t e = crp::launch_gather_bench(make_field_dev(*f), lanes, lookups_per_lane, spread, (uint32_t)seed,
+                                            sink, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_error(e, "crp_bench_gather");
+    return ok();
+}
+
+crp_status crp_bench_stream(const void *src, void *dst, size_t bytes, double *sink, int32_t blocks, void *stream) {
+    if (!src || bytes < 16 || (bytes & 15) || blocks < 1 || blocks > (1 << 20) || (!dst && !sink))
+        return fail(CRP_ERR_INVALID, "crp_bench_stream: bad arguments");
+    if (reinterpret_cast<uintptr_t>(src) & 15 || reinterpret_cast<uintptr_t>(dst) & 15)
+        return fail(CRP_ERR_INVALID, "crp_bench_stream: buffers must be 16-byte aligned");
+    hipError_t e = crp::launch_stream(src, dst, bytes, sink, blocks, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_error(e, "crp_bench_stream");
     return ok();
 }
 

@@ -88,9 +88,12 @@ hipError_t launch_write_table(void *dst, const void *src, size_t bytes, hipStrea
 hipError_t launch_fill_u64(unsigned long long *dst, unsigned long long v, int count, hipStream_t s);
 hipError_t launch_order_by_rigidity(const double *energy, const int32_t *charge, const int32_t *status,
                                     int64_t n, int32_t *order, unsigned int *buckets, hipStream_t s);
-hipError_t launch_propagate_fp64(const PropArgs &a, int dtype, int layout, bool multi, int blocks,
+hipError_t launch_propagate_fp64(const PropArgs &a, int dtype, int layout, bool multi, bool cache, int blocks,
                                  int block_size, hipStream_t s);
 hipError_t launch_upload(const FieldDev &f, const void *src, int src_dtype, void *dst, hipStream_t s);
 hipError_t launch_selftest(const double *in, double *out, int64_t n, int op, hipStream_t s);
+hipError_t launch_gather_bench(const FieldDev &F, int64_t lanes, int64_t lookups, double spread, uint32_t seed,
+                               double *sink, hipStream_t s);
+hipError_t launch_stream(const void *src, void *dst, size_t bytes, double *sink, int blocks, hipStream_t s);
 
 }  // namespace crp

@@ -22,12 +22,21 @@ using namespace dev;
 
 enum { MODE_NORMAL = 0, MODE_EVENT = 1, MODE_FINAL = 2 };
 
+constexpr int MAX_BLOCK = 256;
+
+// Per-lane state kept in registers for the whole loop.
 struct Lane {
     double y[6];          // current state (x, u); the pre-step state while locating an event
     double kap, L, hctrl, h;
-    double lo, hi, glo, ghi, hacc, lacc;
-    int64_t nacc, nrej, ncall;
-    int mode, binding, side, eit, pidx;
+    int32_t dacc, drej;   // accepted / rejected attempts of this call
+    int32_t mode, binding, pidx;
+};
+
+// Event-location state, used once per particle: kept in LDS, one slot per
+// thread, so it costs no registers in the main loop.
+struct EventLDS {
+    double lo[MAX_BLOCK], hi[MAX_BLOCK], glo[MAX_BLOCK], ghi[MAX_BLOCK], hacc[MAX_BLOCK], lacc[MAX_BLOCK];
+    int32_t side[MAX_BLOCK], eit[MAX_BLOCK];
 };
 
 __device__ __forceinline__ double sphere_g(const ParamsDev &P, const double x[3]) {
@@ -57,20 +66,19 @@ __device__ __forceinline__ void bid(const ParamsDev &P, Lane &s) {
     s.h = h;
 }
 
-__device__ __forceinline__ void store(const PropArgs &a, int64_t p, const Lane &s, int st, bool state) {
-    if (state) {
-        a.x[p] = s.y[0];
-        a.y[p] = s.y[1];
-        a.z[p] = s.y[2];
-        a.ux[p] = s.y[3];
-        a.uy[p] = s.y[4];
-        a.uz[p] = s.y[5];
-        a.length[p] = s.L;
-        a.h_next[p] = s.hctrl;
-        a.n_acc[p] = s.nacc;
-        a.n_rej[p] = s.nrej;
-        if (a.time) a.time[p] = s.L * SEC_PER_MPC;
-    }
+// Write the particle's state back (its own slots only).
+__device__ __forceinline__ void store(const PropArgs &a, int64_t p, const Lane &s, double hnext, int st) {
+    a.x[p] = s.y[0];
+    a.y[p] = s.y[1];
+    a.z[p] = s.y[2];
+    a.ux[p] = s.y[3];
+    a.uy[p] = s.y[4];
+    a.uz[p] = s.y[5];
+    a.length[p] = s.L;
+    a.h_next[p] = hnext;
+    if (s.dacc) a.n_acc[p] += s.dacc;
+    if (s.drej) a.n_rej[p] += s.drej;
+    if (a.time) a.time[p] = s.L * SEC_PER_MPC;
     a.status[p] = st;
 }
 
@@ -78,18 +86,19 @@ __device__ __forceinline__ void store(const PropArgs &a, int64_t p, const Lane &
 // iteration: stop when the outside end is on the sphere to 1e-14 R^2, the
 // bracket is below 1e-15 h, or after 30 iterations; otherwise the next
 // regula-falsi point.
-__device__ __forceinline__ void event_next(const ParamsDev &P, Lane &s) {
-    if (s.ghi <= 1e-14 * P.r2 || (s.hi - s.lo) <= 1e-15 * s.hacc || s.eit >= 30) {
+__device__ __forceinline__ void event_next(const ParamsDev &P, Lane &s, EventLDS &e, int t) {
+    double lo = e.lo[t], hi = e.hi[t], glo = e.glo[t], ghi = e.ghi[t];
+    if (ghi <= 1e-14 * P.r2 || (hi - lo) <= 1e-15 * e.hacc[t] || e.eit[t] >= 30) {
         s.mode = MODE_FINAL;
-        s.h = s.hi;
+        s.h = hi;
     } else {
-        s.h = (s.lo * s.ghi - s.hi * s.glo) / (s.ghi - s.glo);
+        s.h = (lo * ghi - hi * glo) / (ghi - glo);
     }
 }
 
-struct LocalCounters {
-    unsigned int evals, acc, rej, ev, fl, taken;
-};
+// Per-iteration outcome bits of a lane; the wavefront sums them with ballots
+// into wave-uniform (scalar) counters.
+enum { F_EVAL = 1, F_ACC = 2, F_REJ = 4, F_EVENT = 8, F_FLOOR = 16 };
 
 // Start particle p in lane state s.  Returns true if it needs steps; false if
 // it was skipped (not ACTIVE) or finished at once (its result is stored).
@@ -112,9 +121,9 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
     s.y[4] = a.uy[p];
     s.y[5] = a.uz[p];
     s.L = a.length[p];
+    s.dacc = 0;
+    s.drej = 0;
     double hn = a.h_next[p];
-    s.nacc = a.n_acc[p];
-    s.nrej = a.n_rej[p];
     bool ok = E > 0.0 && isfinite(E) && isfinite(s.L) && hn >= 0.0 && isfinite(hn);
 #pragma unroll
     for (int c = 0; c < 6; ++c) ok = ok && isfinite(s.y[c]);
@@ -133,21 +142,16 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
         a.status[p] = CRP_ST_BAD_INPUT;
         return false;
     }
-    s.hctrl = hn == 0.0 ? P.h_max : hn;
     if (P.sphere_on && sphere_g(P, s.y) >= 0.0) {
-        double keep = s.hctrl;
-        s.hctrl = hn;
-        store(a, p, s, CRP_ST_ARRIVED, true);
-        s.hctrl = keep;
+        store(a, p, s, hn, CRP_ST_ARRIVED);
         return false;
     }
     if (P.lmax_on && s.L >= P.l_max) {
-        s.hctrl = hn;
-        store(a, p, s, CRP_ST_MAX_LENGTH, true);
+        store(a, p, s, hn, CRP_ST_MAX_LENGTH);
         return false;
     }
+    s.hctrl = hn == 0.0 ? P.h_max : hn;
     s.kap = ((double)Z * K_LORENTZ) / E;
-    s.ncall = 0;
     s.mode = MODE_NORMAL;
     bid(P, s);
     return true;
@@ -155,18 +159,21 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
 
 // One loop iteration of a working lane.  Returns a status != ACTIVE when the
 // particle ended (its result already stored).
-template <class T, int LAYOUT, bool MULTI>
-__device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, LocalCounters &cnt) {
+template <class T, int LAYOUT, bool MULTI, bool CACHE>
+__device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, CellCache<T> &cache, EventLDS &e,
+                                       int &flags) {
+    const int t = threadIdx.x;
     const ParamsDev &P = a.params[MULTI ? s.pidx : 0];
-    const FieldDev &F = a.fields[MULTI ? P.field_index : 0];
+    const int fid = MULTI ? P.field_index : 0;
+    const FieldDev &F = a.fields[fid];
     double y5[6], ex, eu;
-    ck_eval<T, LAYOUT>(F, s.kap, s.y, s.h, y5, ex, eu);
-    cnt.evals++;
+    ck_eval<T, LAYOUT, CACHE>(F, fid, cache, s.kap, s.y, s.h, y5, ex, eu);
+    flags = F_EVAL;
 
     if (s.mode == MODE_NORMAL) {
         double exh = ex / s.h;
         if (!isfinite(eu) || !isfinite(exh)) {
-            store(a, p, s, CRP_ST_NONFINITE, true);
+            store(a, p, s, s.hctrl, CRP_ST_NONFINITE);
             return CRP_ST_NONFINITE;
         }
         double em = eu > exh ? eu : exh;
@@ -178,15 +185,15 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Lo
             if (h < P.h_min) h = P.h_min;
             s.h = h;
             s.binding = 0;
-            s.nrej++;
-            cnt.rej++;
+            s.drej++;
+            flags |= F_REJ;
             return CRP_ST_ACTIVE;
         }
         // accepted: next controller bid
         double g;
         if (err > 1.0) {
             g = 1.0;
-            cnt.fl++;
+            flags |= F_FLOOR;
         } else if (err == 0.0) {
             g = 5.0;
         } else {
@@ -198,20 +205,19 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Lo
         if (hc > P.h_max) hc = P.h_max;
         s.hctrl = hc;
         double Lnew = s.binding ? P.l_max : s.L + s.h;
-        s.nacc++;
-        s.ncall++;
-        cnt.acc++;
+        s.dacc++;
+        flags |= F_ACC;
         if (P.sphere_on && sphere_g(P, y5) >= 0.0) {
             s.mode = MODE_EVENT;
-            s.lo = 0.0;
-            s.glo = sphere_g(P, s.y);
-            s.hi = s.h;
-            s.ghi = sphere_g(P, y5);
-            s.hacc = s.h;
-            s.lacc = Lnew;
-            s.side = 0;
-            s.eit = 0;
-            event_next(P, s);
+            e.lo[t] = 0.0;
+            e.glo[t] = sphere_g(P, s.y);
+            e.hi[t] = s.h;
+            e.ghi[t] = sphere_g(P, y5);
+            e.hacc[t] = s.h;
+            e.lacc[t] = Lnew;
+            e.side[t] = 0;
+            e.eit[t] = 0;
+            event_next(P, s, e, t);
             return CRP_ST_ACTIVE;
         }
         double un = sqrt(y5[3] * y5[3] + y5[4] * y5[4] + y5[5] * y5[5]);
@@ -223,37 +229,37 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Lo
         s.y[5] = y5[5] / un;
         s.L = Lnew;
         if (P.lmax_on && s.L >= P.l_max) {
-            store(a, p, s, CRP_ST_MAX_LENGTH, true);
+            store(a, p, s, s.hctrl, CRP_ST_MAX_LENGTH);
             return CRP_ST_MAX_LENGTH;
         }
-        if (P.max_steps > 0 && s.ncall >= P.max_steps) {
-            store(a, p, s, CRP_ST_MAX_STEPS, true);
+        if (P.max_steps > 0 && s.dacc >= P.max_steps) {
+            store(a, p, s, s.hctrl, CRP_ST_MAX_STEPS);
             return CRP_ST_MAX_STEPS;
         }
         bid(P, s);
         return CRP_ST_ACTIVE;
     }
 
-    cnt.ev++;
+    flags |= F_EVENT;
     if (s.mode == MODE_EVENT) {
         double gs = sphere_g(P, y5);
         if (!isfinite(gs)) {
-            store(a, p, s, CRP_ST_NONFINITE, true);
+            store(a, p, s, s.hctrl, CRP_ST_NONFINITE);
             return CRP_ST_NONFINITE;
         }
         if (gs >= 0.0) {
-            s.hi = s.h;
-            s.ghi = gs;
-            if (s.side == 1) s.glo = s.glo * 0.5;
-            s.side = 1;
+            e.hi[t] = s.h;
+            e.ghi[t] = gs;
+            if (e.side[t] == 1) e.glo[t] = e.glo[t] * 0.5;
+            e.side[t] = 1;
         } else {
-            s.lo = s.h;
-            s.glo = gs;
-            if (s.side == -1) s.ghi = s.ghi * 0.5;
-            s.side = -1;
+            e.lo[t] = s.h;
+            e.glo[t] = gs;
+            if (e.side[t] == -1) e.ghi[t] = e.ghi[t] * 0.5;
+            e.side[t] = -1;
         }
-        s.eit++;
-        event_next(P, s);
+        e.eit[t] += 1;
+        event_next(P, s, e, t);
         return CRP_ST_ACTIVE;
     }
 
@@ -265,24 +271,23 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Lo
     s.y[3] = y5[3] / sn;
     s.y[4] = y5[4] / sn;
     s.y[5] = y5[5] / sn;
-    s.L = s.hi == s.hacc ? s.lacc : s.L + s.hi;
-    store(a, p, s, CRP_ST_ARRIVED, true);
+    s.L = e.hi[t] == e.hacc[t] ? e.lacc[t] : s.L + e.hi[t];
+    store(a, p, s, s.hctrl, CRP_ST_ARRIVED);
     return CRP_ST_ARRIVED;
 }
 
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-template <class T, int LAYOUT, bool MULTI>
-__global__ void __launch_bounds__(256) k_propagate_fp64(PropArgs a) {
+template <class T, int LAYOUT, bool MULTI, bool CACHE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) k_propagate_fp64(PropArgs a) {
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
     int64_t pid = -1;  // >= 0 working, -1 wants work, -2 queue exhausted
+    __shared__ EventLDS ev;
+    __shared__ T cache_lds[CACHE ? 24 : 1][CACHE_BLOCK];
     Lane s;
-    LocalCounters cnt = {0, 0, 0, 0, 0, 0};
+    CellCache<T> cache;
+    cache_reset(cache, cache_lds, threadIdx.x);
+    // wave-uniform counters, summed from ballots (scalar registers)
+    unsigned long long n_eval = 0, n_acc = 0, n_rej = 0, n_ev = 0, n_fl = 0, n_taken = 0;
 
     for (;;) {
         // refill idle lanes from the work queue
@@ -296,61 +301,76 @@ __global__ void __launch_bounds__(256) k_propagate_fp64(PropArgs a) {
             unsigned long long base = 0;
             if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)nwant);
             base = __shfl(base, leader, 64);
+            unsigned long long got = 0;
             if (pid == -1) {
                 unsigned long long q = base + (unsigned long long)__popcll(want & below);
                 if (q < (unsigned long long)a.n) {
                     int64_t p = a.order ? (int64_t)a.order[q] : (int64_t)q;
-                    cnt.taken++;
+                    got = 1;
                     pid = start<MULTI>(a, p, s) ? p : -1;
                 } else {
                     pid = -2;
                 }
             }
+            n_taken += __popcll(__ballot(got != 0));
         }
         if (__ballot(pid >= 0) == 0ull) {
             if (__ballot(pid == -1) == 0ull) break;
             continue;
         }
+        int flags = 0;
         if (pid >= 0) {
-            int st = advance<T, LAYOUT, MULTI>(a, pid, s, cnt);
+            int st = advance<T, LAYOUT, MULTI, CACHE>(a, pid, s, cache, ev, flags);
             if (st != CRP_ST_ACTIVE) pid = -1;
         }
+        n_eval += __popcll(__ballot(flags & F_EVAL));
+        n_acc += __popcll(__ballot(flags & F_ACC));
+        n_rej += __popcll(__ballot(flags & F_REJ));
+        n_ev += __popcll(__ballot(flags & F_EVENT));
+        n_fl += __popcll(__ballot(flags & F_FLOOR));
     }
 
     if (a.counters) {
-        unsigned long long v[6] = {cnt.evals, cnt.acc, cnt.rej, cnt.ev, cnt.fl, cnt.taken};
+        // cell loads: per-lane totals summed across the wavefront
+        unsigned long long m = (unsigned long long)cache.misses;
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            unsigned long long t = wave_sum(v[i]);
-            if (lane == 0 && t) atomicAdd(a.counters + i, t);
+        for (int off = 32; off > 0; off >>= 1) m += __shfl_xor(m, off, 64);
+        if (lane == 0) {
+            unsigned long long v[7] = {n_eval, n_acc, n_rej, n_ev, n_fl, n_taken, m};
+#pragma unroll
+            for (int i = 0; i < 7; ++i)
+                if (v[i]) atomicAdd(a.counters + i, v[i]);
         }
     }
 }
 
-template <class T, int LAYOUT>
-hipError_t launch_t(const PropArgs &a, bool multi, int blocks, int bs, hipStream_t s) {
-    if (multi)
-        hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, true>), dim3(blocks), dim3(bs), 0, s, a);
+template <class T, int LAYOUT, bool MULTI>
+hipError_t launch_c(const PropArgs &a, bool cache, int blocks, int bs, hipStream_t s) {
+    if (cache)
+        hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, MULTI, true>), dim3(blocks), dim3(bs), 0, s, a);
     else
-        hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, false>), dim3(blocks), dim3(bs), 0, s, a);
+        hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, MULTI, false>), dim3(blocks), dim3(bs), 0, s, a);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_layout(const PropArgs &a, int layout, bool multi, int blocks, int bs, hipStream_t s) {
-    if (layout == CRP_LAYOUT_CELL8) return launch_t<T, CRP_LAYOUT_CELL8>(a, multi, blocks, bs, s);
-    return launch_t<T, CRP_LAYOUT_LINEAR>(a, multi, blocks, bs, s);
+hipError_t launch_layout(const PropArgs &a, int layout, bool multi, bool cache, int blocks, int bs, hipStream_t s) {
+    if (layout == CRP_LAYOUT_CELL8)
+        return multi ? launch_c<T, CRP_LAYOUT_CELL8, true>(a, cache, blocks, bs, s)
+                     : launch_c<T, CRP_LAYOUT_CELL8, false>(a, cache, blocks, bs, s);
+    return multi ? launch_c<T, CRP_LAYOUT_LINEAR, true>(a, cache, blocks, bs, s)
+                 : launch_c<T, CRP_LAYOUT_LINEAR, false>(a, cache, blocks, bs, s);
 }
 
 }  // namespace
 
-hipError_t launch_propagate_fp64(const PropArgs &a, int dtype, int layout, bool multi, int blocks,
+hipError_t launch_propagate_fp64(const PropArgs &a, int dtype, int layout, bool multi, bool cache, int blocks,
                                  int block_size, hipStream_t s) {
     switch (dtype) {
-        case CRP_F64: return launch_layout<double>(a, layout, multi, blocks, block_size, s);
-        case CRP_F32: return launch_layout<float>(a, layout, multi, blocks, block_size, s);
-        case CRP_F16: return launch_layout<__half>(a, layout, multi, blocks, block_size, s);
-        case CRP_BF16: return launch_layout<__hip_bfloat16>(a, layout, multi, blocks, block_size, s);
+        case CRP_F64: return launch_layout<double>(a, layout, multi, cache, blocks, block_size, s);
+        case CRP_F32: return launch_layout<float>(a, layout, multi, cache, blocks, block_size, s);
+        case CRP_F16: return launch_layout<__half>(a, layout, multi, cache, blocks, block_size, s);
+        case CRP_BF16: return launch_layout<__hip_bfloat16>(a, layout, multi, cache, blocks, block_size, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -41,7 +41,7 @@ def test_struct_sizes_match_header(crp):
     assert C.sizeof(crp.crp_field) == 4 * 6 + 8 * 3 + 8 + 8 + 8
     assert C.sizeof(crp.crp_params) == 8 * 3 + 8 * 3 + 8 + 8 + 8 + 8
     assert C.sizeof(crp.crp_particles) == 16 * 8
-    assert C.sizeof(crp.crp_tuning) == 16
+    assert C.sizeof(crp.crp_tuning) == 32
 
 
 def _field(crp, n=(32, 32, 32), dtype=None, layout=None, spacing=0.1):

@@ -130,6 +130,8 @@ def test_production_grid_sample(dev, oracle_mod, c2_field):
     dict(block_size=128, blocks_per_cu=0, refill_threshold=1, order_by_rigidity=1),
     dict(block_size=256, blocks_per_cu=2, refill_threshold=16, order_by_rigidity=1),
     dict(block_size=256, blocks_per_cu=8, refill_threshold=64, order_by_rigidity=0),
+    dict(block_size=256, blocks_per_cu=4, refill_threshold=1, order_by_rigidity=1, cache_cells=-1),
+    dict(block_size=256, blocks_per_cu=4, refill_threshold=32, order_by_rigidity=1, cache_cells=1),
 ])
 def test_results_independent_of_launch_configuration(dev, c2_field, tuning):
     torch, crp = dev
