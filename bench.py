@@ -1,21 +1,23 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the propagation hot path on one MI355X.
 
-Workload (default): 1e6 nuclei (Z uniform in {1, 2, 7, 26}, E log-uniform in
-1e18..1e20 eV, isotropic from the origin) in a 256^3 FP32 Kolmogorov grid
-(spacing 50 kpc, l_min 100 kpc, l_max 5 Mpc, B_rms 1 nG), tolerance 1e-4,
-steps 1 kpc .. 1 Mpc, stop at the r = 20 Mpc sphere or at 1 Gpc of path.
-A step of the benchmark propagates every particle until it stops.
+Workload (default, production_256cube): 1e6 nuclei (Z uniform in {1, 2, 7,
+26}, E log-uniform in 1e18..1e20 eV, isotropic from the origin) in a 256^3
+FP32 Kolmogorov grid (spacing 50 kpc, l_min 100 kpc, l_max 5 Mpc, B_rms 1 nG),
+tolerance 1e-4, steps 1 kpc .. 1 Mpc, stop at the r = 20 Mpc sphere or at
+1 Gpc of path.  A step of the benchmark propagates every particle until it
+stops.  Other workloads: --workload small_fp64_32cube | batched_64x64cube |
+precision_1024cube | adjoint_128cube.
 
 Prints one JSON line: particle-steps/s (accepted Cash-Karp steps per second of
-the whole job), the gather roofline of the propagation kernel (algorithmic
+the whole job), the lookup roofline of the propagation kernel (algorithmic
 bytes of the field lookups per launch / average launch time, against the HBM
-peak), and the CPU oracle timed on a bounded sample of the same workload.
+peak), the mixed-precision kernel on the same inputs, and the CPU oracle timed
+on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -27,6 +29,7 @@ METRIC = "particle-steps/s + gather GB/s vs roofline; adjoint/forward time; err 
 HBM_PEAK_GBPS = 8000.0
 BYTES_PER_VALUE = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 KERNEL_SOURCES = ["crp_device.h", "propagate_fp64.hip", "crp_internal.h"]
+PRECISIONS = {"fp64": 0, "mixed_f64acc": 1, "mixed_dfacc": 2}
 
 
 def log(*a):
@@ -41,7 +44,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, layout: str, evals_per_launch: float):
+def measured_traffic(workload: str, layout: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_propagate_fp64_{workload}_{layout}.json")
@@ -54,7 +57,35 @@ def measured_traffic(workload: str, layout: str, evals_per_launch: float):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(B, w, P, sample: int):
+def angle(a, b):
+    import numpy as np
+    return np.arctan2(np.linalg.norm(np.cross(a, b), axis=1), np.sum(a * b, axis=1))
+
+
+def build_inputs(w, n_override):
+    """Field grids (numpy, FP32 or FP64), per-group stop radii and the particle list."""
+    import numpy as np
+
+    import crp_inputs as ci
+    fs, ps, rs = ci.config_seeds(w.index)
+    gdt = np.float64 if w.grid_dtype == "f64" else np.float32
+    if w.n_realisations:
+        table = ci.realisation_table(w, rs)
+        P = ci.realisation_particles(w, table, ps)
+        seeds = fs.spawn(w.n_realisations)
+        grids = [ci.kolmogorov_field(w.grid_n, w.spacing, w.l_min, w.l_max, float(table["b_rms"][r]), seeds[r],
+                                     dtype=gdt) for r in range(w.n_realisations)]
+        radii = [float(r) for r in table["radius"]]
+    else:
+        n = w.n_particles if n_override is None else n_override
+        P = ci.isotropic_particles(n, w.e_min, w.e_max, w.charges, ps, charge_rule=w.charge_rule)
+        grids = [ci.kolmogorov_field(w.grid_n, w.spacing, w.l_min, w.l_max, w.b_rms, fs, dtype=gdt)]
+        radii = [w.obs_radius]
+    return grids, radii, P
+
+
+def cpu_baseline(grids, radii, w, P, sample: int):
+    """The oracle, as it stands, on the first `sample` particles, all host cores."""
     import numpy as np
 
     from oracle import oracle as O
@@ -64,16 +95,25 @@ def cpu_baseline(B, w, P, sample: int):
         cores = os.cpu_count() or 1
     omp = os.environ.get("OMP_NUM_THREADS")
     threads = min(cores, int(omp)) if omp and omp.isdigit() else cores
-    sel = slice(0, sample)
-    g = O.Grid(B, w.spacing)
-    prm = O.params_array(w.tol, w.h_min, w.h_max, radius=w.obs_radius, l_max=w.max_length)
+    pidx = P.get("param_index")
+    groups = np.zeros(sample, np.int64) if pidx is None else pidx[:sample]
+    out = {"pos": np.zeros((sample, 3)), "dir": np.zeros((sample, 3)), "length": np.zeros(sample),
+           "status": np.zeros(sample, np.int32), "n_acc": np.zeros(sample, np.int64)}
+    acc = evals = 0
     t0 = time.perf_counter()
-    r = O.propagate(g, prm, P["pos"][sel], P["dir"][sel], P["energy"][sel], P["charge"][sel], nthreads=threads)
+    for gi in np.unique(groups):
+        sel = np.nonzero(groups == gi)[0]
+        prm = O.params_array(w.tol, w.h_min, w.h_max, radius=radii[gi], l_max=w.max_length)
+        r = O.propagate(O.Grid(grids[gi], w.spacing), prm, P["pos"][sel], P["dir"][sel], P["energy"][sel],
+                        P["charge"][sel], nthreads=threads)
+        for k in out:
+            out[k][sel] = r[k]
+        acc += int(np.sum(r["n_acc"]))
+        evals += r["counters"]["evals"]
     dt = time.perf_counter() - t0
-    acc = int(np.sum(r["n_acc"]))
     return {"value": acc / dt, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"first {sample} particles of the same seeded list ({acc} accepted steps, "
-                      f"{r['counters']['evals']} evaluations, {dt:.1f} s)"}
+                      f"{evals} evaluations, {dt:.1f} s)"}, out
 
 
 def main():
@@ -83,12 +123,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="production_256cube")
     ap.add_argument("--n", type=int, default=None, help="particle count (default: the workload's)")
-    ap.add_argument("--layout", default="cell8", choices=["linear", "cell8"])
+    ap.add_argument("--layout", default=None, choices=["linear", "cell8"],
+                    help="default: cell8 up to 512^3, linear above")
+    ap.add_argument("--precision", default="fp64", choices=list(PRECISIONS))
+    ap.add_argument("--grid-dtype", default=None, choices=["f64", "f32", "f16", "bf16"])
+    ap.add_argument("--mixed-grid-dtype", default="f16", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--block-size", type=int, default=256)
     ap.add_argument("--blocks-per-cu", type=int, default=4)
     ap.add_argument("--refill-threshold", type=int, default=32)
     ap.add_argument("--cache-cells", type=int, default=0, help="1 on, -1 off, 0 automatic")
     ap.add_argument("--no-order", action="store_true")
+    ap.add_argument("--autotune", type=int, default=None, help="1: tune the launch (default on for batches)")
+    ap.add_argument("--graph", type=int, default=None, help="1: replay a captured hipGraph (default on for batches)")
     ap.add_argument("--cpu-sample", type=int, default=200000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -112,67 +159,93 @@ def main():
     torch.cuda.set_device(dev)
 
     w = ci.get_config(args.workload)
-    fs, ps, _ = ci.config_seeds(w.index)
-    n = w.n_particles if args.n is None else args.n
-    gdt = {"f64": np.float64}.get(w.grid_dtype, np.float32)
+    batched = w.n_realisations > 0
+    use_graph = bool(args.graph if args.graph is not None else batched)
+    use_tuner = bool(args.autotune if args.autotune is not None else batched)
     t0 = time.perf_counter()
-    B = ci.kolmogorov_field(w.grid_n, w.spacing, w.l_min, w.l_max, w.b_rms, fs, dtype=gdt)
-    P = ci.isotropic_particles(n, w.e_min, w.e_max, w.charges, ps, charge_rule=w.charge_rule)
-    log(f"bench: inputs generated in {time.perf_counter() - t0:.1f} s ({w.name}, n={n})")
+    grids, radii, P = build_inputs(w, args.n)
+    n = len(P["energy"])
+    log(f"bench: inputs generated in {time.perf_counter() - t0:.1f} s ({w.name}, n={n}, {len(grids)} field(s))")
 
-    dtype = w.grid_dtype if w.grid_dtype in ("f64", "f32") else "f32"
-    field = crp.make_field(B, w.spacing, dtype=dtype, layout=args.layout)
-    prm = crp.make_params(w.tol, w.h_min, w.h_max, obs_radius=w.obs_radius, l_max=w.max_length)
-    pristine = crp.particles_to_device(P["pos"], P["dir"], P["energy"], P["charge"], mass=P["mass"])
+    prec = PRECISIONS[args.precision]
+    gdt_name = args.grid_dtype or ("f16" if prec != 0 else ("f64" if w.grid_dtype == "f64" else "f32"))
+    layout = args.layout or ("cell8" if w.grid_n <= 512 else "linear")
+    params = [crp.make_params(w.tol, w.h_min, w.h_max, obs_radius=radii[r], l_max=w.max_length, field_index=r)
+              for r in range(len(grids))]
+    pristine = crp.particles_to_device(P["pos"], P["dir"], P["energy"], P["charge"], mass=P["mass"],
+                                       param_index=P.get("param_index"))
     state = crp.clone_particles(pristine)
-    ws = torch.empty(crp.crp_workspace_bytes(n, 1, 1), dtype=torch.uint8, device=dev)
+    ws = torch.empty(crp.crp_workspace_bytes(n, len(grids), len(params)), dtype=torch.uint8, device=dev)
     counters = torch.zeros(crp.NCOUNTERS, dtype=torch.int64, device=dev)
     tuning = crp.make_tuning(args.block_size, args.blocks_per_cu, args.refill_threshold,
                              0 if args.no_order else 1, args.cache_cells)
-    stream = torch.cuda.current_stream()
 
-    def step(ev=None):
-        for k, v in pristine.items():
-            if v is not None:
-                state[k].copy_(v, non_blocking=True)
-        if ev is not None:
-            ev[0].record(stream)
-        crp.crp_propagate([field], [prm], state, tuning=tuning, counters=counters, workspace=ws)
-        if ev is not None:
-            ev[1].record(stream)
+    def timed(fields, precision, tun, steps, warmup, label):
+        """Warm-up passes, then `steps` timed passes of the whole hot path."""
+        graph = crp.Graph(fields, params, state, precision=precision, tuning=tun, counters=counters,
+                          workspace=ws) if use_graph else None
+        stream = torch.cuda.current_stream()
 
-    for i in range(args.warmup):
-        step()
+        def step(ev=None):
+            for k, v in pristine.items():
+                if v is not None:
+                    state[k].copy_(v, non_blocking=True)
+            if ev is not None:
+                ev[0].record(stream)
+            if graph is not None:
+                graph.launch()
+            else:
+                crp.crp_propagate(fields, params, state, precision=precision, tuning=tun, counters=counters,
+                                  workspace=ws)
+            if ev is not None:
+                ev[1].record(stream)
+
+        for i in range(warmup):
+            step()
+            torch.cuda.synchronize()
+            log(f"bench: {label} warmup {i + 1}/{warmup} done")
+        counters.zero_()
+        events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(steps)]
         torch.cuda.synchronize()
-        log(f"bench: warmup {i + 1}/{args.warmup} done")
-    counters.zero_()
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(events[i])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    launch_ms = [a.elapsed_time(b) for a, b in events]
-    c = counters.cpu().numpy().astype(np.int64)
-    log(f"bench: {args.steps} timed steps in {elapsed:.3f} s; launch ms {['%.1f' % x for x in launch_ms]}")
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(events[i])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        launch_ms = [a.elapsed_time(b) for a, b in events]
+        log(f"bench: {label}: {steps} timed steps in {elapsed:.3f} s; launch ms {['%.1f' % x for x in launch_ms]}")
+        if graph is not None:
+            graph.close()
+        return {"elapsed": elapsed, "launch_ms": launch_ms, "counters": counters.cpu().numpy().astype(np.int64),
+                "host": crp.particles_to_host(state)}
 
+    fields = [crp.make_field(g, w.spacing, dtype=gdt_name, layout=layout) for g in grids]
+    tuned = None
+    if use_tuner:
+        from paper_1410_5323_amd.autotune import autotune
+        tuning = autotune(fields, params, pristine, precision=prec, log=log)
+        tuned = {k: getattr(tuning, k) for k in ("block_size", "blocks_per_cu", "refill_threshold",
+                                                 "order_by_rigidity", "cache_cells")}
+        log(f"bench: autotuned launch {tuned}")
+    head = timed(fields, prec, tuning, args.steps, args.warmup, f"{args.precision}/{gdt_name}/{layout}")
+    c = head["counters"]
+    elapsed = head["elapsed"]
     accepted = int(c[1])
     evals = int(c[0])
-    steps_per_s = accepted / elapsed
-    avg_launch_s = float(np.mean(launch_ms)) / 1e3
-    bpv = BYTES_PER_VALUE[dtype]
-    bytes_per_eval = 6 * 8 * 3 * bpv
+    avg_launch_s = float(np.mean(head["launch_ms"])) / 1e3
+    bytes_per_eval = 6 * 8 * 3 * BYTES_PER_VALUE[gdt_name]
     evals_per_launch = evals / args.steps
     achieved = bytes_per_eval * evals_per_launch / avg_launch_s / 1e9
-    traffic = measured_traffic(w.name, args.layout, evals_per_launch)
-    host = crp.particles_to_host(state)
+    traffic = measured_traffic(w.name, layout) if prec == 0 else None
+    host = head["host"]
     statuses = {k: int(np.sum(host["status"] == v)) for k, v in crp.STATUS.items() if np.any(host["status"] == v)}
+    del fields
+    torch.cuda.empty_cache()
 
     result = {
         "metric": METRIC,
-        "value": steps_per_s,
+        "value": accepted / elapsed,
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -181,18 +254,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == 0 else "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "particles": n, "grid": f"{w.grid_n}^3 {dtype}",
-                   "grid_spacing_mpc": w.spacing, "layout": args.layout, "tol": w.tol,
-                   "h_min_mpc": w.h_min, "h_max_mpc": w.h_max, "obs_radius_mpc": w.obs_radius,
-                   "l_max_mpc": w.max_length, "precision": "fp64",
-                   "tuning": {"block_size": args.block_size, "blocks_per_cu": args.blocks_per_cu,
-                              "refill_threshold": args.refill_threshold, "order_by_rigidity": not args.no_order,
-                              "cache_cells": args.cache_cells}},
+        "config": {"workload": w.name, "particles": n, "fields": len(grids), "grid": f"{w.grid_n}^3 {gdt_name}",
+                   "grid_spacing_mpc": w.spacing, "layout": layout, "tol": w.tol,
+                   "h_min_mpc": w.h_min, "h_max_mpc": w.h_max,
+                   "obs_radius_mpc": [min(radii), max(radii)] if batched else w.obs_radius,
+                   "l_max_mpc": w.max_length, "precision": args.precision, "hipgraph": use_graph,
+                   "tuning": tuned or {"block_size": args.block_size, "blocks_per_cu": args.blocks_per_cu,
+                                       "refill_threshold": args.refill_threshold,
+                                       "order_by_rigidity": not args.no_order, "cache_cells": args.cache_cells}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": None if traffic is None else traffic},
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic},
         "detail": {"accepted_steps_per_launch": accepted / args.steps,
                    "evaluations_per_launch": evals_per_launch,
                    "rejected_per_launch": int(c[2]) / args.steps,
@@ -206,9 +279,37 @@ def main():
                    "statuses": statuses,
                    "kernel_source_sha": kernel_source_hash()},
     }
+
+    mixed_host = None
+    if prec == 0 and not args.no_mixed and not batched:
+        mdt = args.mixed_grid_dtype
+        mfields = [crp.make_field(g, w.spacing, dtype=mdt, layout=layout) for g in grids]
+        mix = timed(mfields, PRECISIONS["mixed_f64acc"], tuning, args.steps, 1, f"mixed_f64acc/{mdt}/{layout}")
+        del mfields
+        torch.cuda.empty_cache()
+        mixed_host = mix["host"]
+        mavg = float(np.mean(mix["launch_ms"]))
+        result["mixed"] = {"precision": "mixed_f64acc", "grid": f"{w.grid_n}^3 {mdt}", "layout": layout,
+                           "avg_launch_ms": mavg, "speedup_vs_fp64": avg_launch_s * 1e3 / mavg,
+                           "accepted_steps_per_s": int(mix["counters"][1]) / mix["elapsed"]}
+
     if not args.no_cpu_baseline:
-        log(f"bench: timing the CPU oracle on the first {args.cpu_sample} particles")
-        result["cpu_baseline"] = cpu_baseline(B, w, P, min(args.cpu_sample, n))
+        m = min(args.cpu_sample, n)
+        log(f"bench: timing the CPU oracle on the first {m} particles")
+        cb, ref = cpu_baseline(grids, radii, w, P, m)
+        result["cpu_baseline"] = cb
+        if prec == 0:
+            g = {k: v[:m] for k, v in host.items()}
+            bit = (np.all(g["pos"] == ref["pos"], axis=1) & np.all(g["dir"] == ref["dir"], axis=1)
+                   & (g["length"] == ref["length"]) & (g["status"] == ref["status"]))
+            result["detail"]["parity_sample"] = {"particles": m, "bitwise_fraction": float(np.mean(bit)),
+                                                 "max_angle_rad": float(np.max(angle(g["dir"], ref["dir"])))}
+        if mixed_host is not None:
+            a = angle(mixed_host["dir"][:m], ref["dir"])
+            result["mixed"]["angle_vs_oracle_rad"] = {"p50": float(np.percentile(a, 50)),
+                                                      "p95": float(np.percentile(a, 95)),
+                                                      "frac_below_1e-4": float(np.mean(a <= 1e-4)),
+                                                      "sample": m, "reference": "oracle on the FP32 grid"}
     print(json.dumps(result), flush=True)
 
 

@@ -62,9 +62,10 @@ CONFIGS = (
     # 1e6 mixed nuclei, 256^3 FP32 grid; stop at r = 20 Mpc or 1 Gpc of path.
     Workload("production_256cube", 1, 1_000_000, MIXED, 1e18, 1e20, 256, 0.05, 0.1, 5.0, 1.0, "f32",
              1e-4, 0.001, 1.0, 20.0, 1000.0),
-    # 64 realisations of 64^3 FP32 grids; spacing, band, tol, step limits and L_max chosen.
+    # 64 realisations of 64^3 FP32 grids; spacing, band, tol, step limits and L_max chosen
+    # (L_max = 100 Mpc keeps the longest, h_min-limited trajectory at 1e5 steps).
     Workload("batched_64x64cube", 2, 0, MIXED, 1e17, 1e20, 64, 0.05, 0.1, 1.6, 1.0, "f32",
-             1e-4, 0.001, 1.0, 0.0, 1000.0, n_realisations=64, b_rms_range=(0.1, 10.0),
+             1e-4, 0.001, 1.0, 0.0, 100.0, n_realisations=64, b_rms_range=(0.1, 10.0),
              count_range=(100, 100_000), radius_range=(1.0, 50.0)),
     # 4e6 mixed nuclei, 1024^3 grid stored FP16/BF16 (or FP32); tol, step limits and L_max chosen.
     Workload("precision_1024cube", 3, 4_000_000, MIXED, 1e18, 1e20, 1024, 0.01, 0.02, 2.0, 1.0, "f16",

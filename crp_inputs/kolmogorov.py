@@ -10,14 +10,18 @@ It does not say how the realisation is built, so the construction here is:
    on any axis (a Nyquist mode has no distinct partner -k, so it could not be
    kept both real and divergence-free);
 3. complex Gaussian amplitudes (a + i b)/sqrt(2), drawn slab by slab along the
-   kx index: for each kx index, a of shape (3, N, N/2+1), then b of that shape;
+   kx index, each slab from its own PCG64 stream spawned from the seed (slab i
+   uses child i): a of shape (3, N, N/2+1), then b of that shape; slabs are
+   independent, so they are drawn concurrently;
 4. projection onto the plane normal to k (divergence-free field), and on the
    kz = 0 plane xi(k) <- (xi(k) + conj(xi(-k)))/sqrt(2) so that the half
    spectrum is Hermitian there and keeps its full power;
 5. amplitude |k|^(-11/6), so that the 3D power spectrum goes as k^(-11/3)
    (the shell spectrum as k^(-5/3));
-6. real inverse FFT per component in FP64, then a rescale so that the
-   root-mean-square of |B| over the nodes equals B_rms exactly.
+6. real inverse FFT per component in FP64, rescaled so that the
+   root-mean-square of |B| over the nodes equals B_rms (the mean square is
+   taken from the spectrum by Parseval's theorem, exact up to rounding), then
+   rounded once into the storage dtype.
 
 Output layout: ``[ix][iy][iz][component]`` (iz fastest), float64, nanogauss.
 Node (i, j, k) sits at origin + spacing*(i, j, k); the field repeats with
@@ -26,6 +30,7 @@ period N*spacing along each axis.
 from __future__ import annotations
 
 import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import scipy.fft as sfft
@@ -71,16 +76,19 @@ def kolmogorov_field(n: int, spacing: float, l_min: float, l_max: float,
     ``dtype`` is the storage dtype of the returned array; the synthesis is
     always FP64 and the cast (if any) rounds to nearest even.
     """
-    rng = np.random.Generator(np.random.PCG64(seed))
+    ss = seed if isinstance(seed, np.random.SeedSequence) else np.random.SeedSequence(seed)
+    slab_seeds = ss.spawn(n)
     nx, ny, nz, mask = spectral_mask(n, spacing, l_min, l_max)
     nzh = n // 2 + 1
     kx = nx.astype(np.float64)
     ky = ny.astype(np.float64)
     kz = nz.astype(np.float64)
 
-    spec = np.empty((3, n, n, nzh), dtype=np.complex128)
+    spec = [np.empty((n, n, nzh), dtype=np.complex128) for _ in range(3)]
     inv_sqrt2 = 1.0 / np.sqrt(2.0)
-    for i in range(n):  # slab-wise draw keeps the random stream independent of memory limits
+
+    def slab(i):
+        rng = np.random.Generator(np.random.PCG64(slab_seeds[i]))
         a = rng.standard_normal((3, n, nzh))
         b = rng.standard_normal((3, n, nzh))
         xi = (a + 1j * b) * inv_sqrt2
@@ -96,23 +104,37 @@ def kolmogorov_field(n: int, spacing: float, l_min: float, l_max: float,
         xi[1] -= kyi * proj
         xi[2] -= kzi * proj
         amp = np.where(m, k2s ** (-11.0 / 12.0), 0.0)  # |k|^(-11/6)
-        spec[:, i] = xi * amp
+        for c in range(3):
+            spec[c][i] = xi[c] * amp
+
+    with ThreadPoolExecutor(max_workers=_workers()) as ex:
+        list(ex.map(slab, range(n)))
 
     # The real inverse transform keeps only the Hermitian part of the kz = 0
     # plane, which would halve its power; make that plane Hermitian here,
     # (xi(k) + conj(xi(-k)))/sqrt(2), which keeps both the power and k.xi = 0.
     neg = (-np.arange(n)) % n
-    p0 = spec[:, :, :, 0]
-    spec[:, :, :, 0] = (p0 + np.conj(p0[:, neg][:, :, neg])) * inv_sqrt2
-
-    out = np.empty((n, n, n, 3), dtype=np.float64)
     for c in range(3):
-        out[..., c] = sfft.irfftn(spec[c], s=(n, n, n), workers=_workers())
-    del spec
-    ms = np.mean(np.sum(out * out, axis=-1))
-    out *= b_rms / np.sqrt(ms)
-    if dtype != np.float64:
-        return out.astype(dtype)
+        p0 = spec[c][:, :, 0]
+        spec[c][:, :, 0] = (p0 + np.conj(p0[neg][:, neg])) * inv_sqrt2
+
+    # Mean of |B|^2 over the nodes from the spectrum (Parseval): every kz > 0
+    # column stands for itself and its conjugate partner.
+    w = np.full(nzh, 2.0)
+    w[0] = 1.0
+    ms = 0.0
+    for c in range(3):
+        ms += float(np.sum(np.sum(spec[c].real ** 2 + spec[c].imag ** 2, axis=(0, 1)) * w))
+    ms /= float(n) ** 6
+    scale = b_rms / np.sqrt(ms)
+
+    out = np.empty((n, n, n, 3), dtype=dtype)
+    for c in range(3):
+        comp = sfft.irfftn(spec[c], s=(n, n, n), workers=_workers())
+        spec[c] = None
+        comp *= scale
+        out[..., c] = comp  # rounds to nearest even when dtype is narrower
+        del comp
     return out
 
 

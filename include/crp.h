@@ -166,6 +166,22 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
                          const crp_tuning *tuning, int64_t *counters, void *workspace,
                          size_t workspace_bytes, void *stream);
 
+/* A captured propagation (hipGraph): the whole sequence of crp_propagate for
+ * these exact arguments (descriptor tables, queue reset, longest-first order,
+ * persistent kernel), replayed by crp_graph_launch with no host-side work.
+ * Built for launch-bound repetition, e.g. many field realisations run again
+ * and again (section 3.2: the same fields reused across runs).  Every pointer
+ * captured must stay valid while the graph is used; each replay propagates
+ * the particles' current state in place (callers reset it between replays if
+ * they want the same input).  stream must be a non-default stream. */
+typedef struct crp_graph crp_graph;
+crp_status crp_graph_create(const crp_field *fields, int32_t n_fields, const crp_params *params, int32_t n_params,
+                            const crp_particles *p, int64_t n, int32_t precision, const crp_tuning *tuning,
+                            int64_t *counters, void *workspace, size_t workspace_bytes, void *stream,
+                            crp_graph **out);
+crp_status crp_graph_launch(crp_graph *g, void *stream);
+crp_status crp_graph_destroy(crp_graph *g);
+
 /* Device arithmetic conformance: apply operation op to n inputs in[] ([dev]
  * FP64) writing out[] ([dev] FP64).  op: 0 sqrt, 1 reciprocal (1/x), 2 fma(x, y,
  * z) on triples (n triples, in has 3n values), 3 floor, 4 the controller's

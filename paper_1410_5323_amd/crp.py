@@ -83,6 +83,13 @@ def lib():
         L.crp_bench_stream.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_int32, C.c_void_p]
         L.crp_bench_gather.restype = C.c_int
         L.crp_bench_stream.restype = C.c_int
+        L.crp_graph_create.argtypes = [C.POINTER(crp_field), C.c_int32, C.POINTER(crp_params), C.c_int32,
+                                       C.POINTER(crp_particles), C.c_int64, C.c_int32, C.POINTER(crp_tuning),
+                                       C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]
+        L.crp_graph_launch.argtypes = [C.c_void_p, C.c_void_p]
+        L.crp_graph_destroy.argtypes = [C.c_void_p]
+        for f in (L.crp_graph_create, L.crp_graph_launch, L.crp_graph_destroy):
+            f.restype = C.c_int
         L.crp_last_error.restype = C.c_char_p
         L.crp_version.restype = C.c_char_p
         for f in (L.crp_field_upload, L.crp_propagate, L.crp_selftest_arith):
@@ -164,6 +171,61 @@ def crp_propagate(fields, params, particles: dict, precision=CRP_PREC_FP64, tuni
                                _ptr(counters), _ptr(workspace), workspace.numel(),
                                _stream_handle(stream)))
     return particles
+
+
+def _marshal(fields, params, particles, tuning):
+    nf, np_ = len(fields), len(params)
+    farr = (crp_field * nf)(*[f.desc for f in fields])
+    parr = (crp_params * np_)(*params)
+    n = int(particles["energy"].numel())
+    ps = crp_particles(**{k: (particles[k].data_ptr() if particles.get(k) is not None else None)
+                          for k in _PARTICLE_FIELDS})
+    tun = C.byref(tuning) if tuning is not None else None
+    return farr, nf, parr, np_, ps, n, tun
+
+
+class Graph:
+    """A captured crp_propagate (crp_graph_create); replay with launch().
+
+    The captured pointers (fields, particles, workspace, counters) are kept
+    alive by this object.  Capture and replay run on a dedicated stream that
+    is ordered after the caller's current stream."""
+
+    def __init__(self, fields, params, particles: dict, precision=CRP_PREC_FP64, tuning=None, counters=None,
+                 workspace=None):
+        torch = _torch()
+        self._keep = (fields, params, particles, counters, tuning)
+        farr, nf, parr, np_, ps, n, tun = _marshal(fields, params, particles, tuning)
+        self._arrays = (farr, parr, ps)
+        dev = particles["energy"].device
+        self.workspace = workspace if workspace is not None else \
+            torch.empty(crp_workspace_bytes(n, nf, np_), dtype=torch.uint8, device=dev)
+        self.stream = torch.cuda.Stream(device=dev)
+        self.stream.wait_stream(torch.cuda.current_stream(dev))
+        h = C.c_void_p()
+        _check(lib().crp_graph_create(farr, nf, parr, np_, C.byref(ps), n, int(precision), tun, _ptr(counters),
+                                      _ptr(self.workspace), self.workspace.numel(),
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+
+    def launch(self):
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.stream.device)
+        self.stream.wait_stream(cur)
+        _check(lib().crp_graph_launch(self.handle, C.c_void_p(self.stream.cuda_stream)))
+        cur.wait_stream(self.stream)
+
+    def close(self):
+        if self.handle:
+            self.stream.synchronize()
+            _check(lib().crp_graph_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def crp_selftest_arith(inp, out, op: int, stream=None):

@@ -205,7 +205,6 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
         return fail(CRP_ERR_INVALID, "%s: param_index is required with several parameter groups", fn);
     if (precision != CRP_PREC_FP64 && precision != CRP_PREC_MIXED_F64ACC && precision != CRP_PREC_MIXED_DFACC)
         return fail(CRP_ERR_INVALID, "%s: unknown precision %d", fn, precision);
-    if (precision != CRP_PREC_FP64) return fail(CRP_ERR_UNSUPPORTED, "%s: precision %d not built", fn, precision);
     crp_tuning t = {256, 4, 32, 1, 0, 0, 0, 0};
     if (tuning) t = *tuning;
     if (t.block_size != 64 && t.block_size != 128 && t.block_size != 256)
@@ -276,9 +275,67 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
     int64_t blocks = t.blocks_per_cu == 0 ? need_blocks : (int64_t)cus * t.blocks_per_cu;
     if (blocks > need_blocks) blocks = need_blocks;
     bool multi = n_params > 1 || p->param_index != nullptr;
-    e = crp::launch_propagate_fp64(a, fields[0].dtype, fields[0].layout, multi, cache, (int)blocks,
-                                   t.block_size, s);
+    if (precision == CRP_PREC_FP64)
+        e = crp::launch_propagate_fp64(a, fields[0].dtype, fields[0].layout, multi, cache, (int)blocks,
+                                       t.block_size, s);
+    else
+        e = crp::launch_propagate_mixed(a, fields[0].dtype, fields[0].layout, multi, precision, cache, (int)blocks,
+                                        t.block_size, s);
     if (e != hipSuccess) return device_error(e, fn);
+    return ok();
+}
+
+struct crp_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+crp_status crp_graph_create(const crp_field *fields, int32_t n_fields, const crp_params *params, int32_t n_params,
+                            const crp_particles *p, int64_t n, int32_t precision, const crp_tuning *tuning,
+                            int64_t *counters, void *workspace, size_t workspace_bytes, void *stream,
+                            crp_graph **out) {
+    const char *fn = "crp_graph_create";
+    if (!out) return fail(CRP_ERR_INVALID, "%s: null output handle", fn);
+    *out = nullptr;
+    if (!stream) return fail(CRP_ERR_INVALID, "%s: capture needs a non-default stream", fn);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return device_error(e, fn);
+    crp_status st = crp_propagate(fields, n_fields, params, n_params, p, n, precision, tuning, counters, workspace,
+                                  workspace_bytes, stream);
+    std::string msg = g_last_error;
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    if (st != CRP_OK) {
+        if (graph) hipGraphDestroy(graph);
+        g_last_error = msg;
+        return st;
+    }
+    if (e != hipSuccess) return device_error(e, fn);
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return device_error(e, fn);
+    }
+    *out = new crp_graph{graph, exec};
+    return ok();
+}
+
+crp_status crp_graph_launch(crp_graph *g, void *stream) {
+    if (!g) return fail(CRP_ERR_INVALID, "crp_graph_launch: null graph");
+    hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_error(e, "crp_graph_launch");
+    return ok();
+}
+
+crp_status crp_graph_destroy(crp_graph *g) {
+    if (!g) return ok();
+    hipError_t e1 = hipGraphExecDestroy(g->exec);
+    hipError_t e2 = hipGraphDestroy(g->graph);
+    delete g;
+    if (e1 != hipSuccess) return device_error(e1, "crp_graph_destroy");
+    if (e2 != hipSuccess) return device_error(e2, "crp_graph_destroy");
     return ok();
 }
 

@@ -90,6 +90,8 @@ hipError_t launch_order_by_rigidity(const double *energy, const int32_t *charge,
                                     int64_t n, int32_t *order, unsigned int *buckets, hipStream_t s);
 hipError_t launch_propagate_fp64(const PropArgs &a, int dtype, int layout, bool multi, bool cache, int blocks,
                                  int block_size, hipStream_t s);
+hipError_t launch_propagate_mixed(const PropArgs &a, int dtype, int layout, bool multi, int precision, bool cache,
+                                  int blocks, int block_size, hipStream_t s);
 hipError_t launch_upload(const FieldDev &f, const void *src, int src_dtype, void *dst, hipStream_t s);
 hipError_t launch_selftest(const double *in, double *out, int64_t n, int op, hipStream_t s);
 hipError_t launch_gather_bench(const FieldDev &F, int64_t lanes, int64_t lookups, double spread, uint32_t seed,

@@ -1,0 +1,128 @@
+"""Mixed-precision path (FP16/BF16/FP32 grid, FP32 stages, FP64 or double-float
+accumulation) against the FP64 oracle.
+
+Adaptive integration in a trilinear (C0) field is not a smooth function of
+its inputs: a change of the initial direction by one FP32 ulp (1e-7 rad)
+flips step-controller decisions and moves the FP64 result's arrival direction
+by 1e-3 .. 1 rad depending on rigidity.  No per-particle bound below that
+sensitivity can hold for any implementation that is not bit-identical.  The
+test therefore checks, per rigidity decile, that the mixed path's deviation
+from the oracle is no larger than the oracle's own deviation under that
+1e-7 rad perturbation (a Lyapunov probe), and that the distributions of
+deflection angle and path length agree (two-sample KS).
+
+Two references separate the error sources: the oracle on the FP32 grid (total
+error) and on the dequantized 16-bit grid, i.e. the values the device stores
+(arithmetic-only error).
+"""
+import sys
+
+import numpy as np
+import pytest
+from scipy.stats import ks_2samp
+
+import crp_inputs as ci
+from gpu_common import angle, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+N_PART = 2000
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def setup(oracle_mod):
+    """Precision workload parameters on a 256^3 grid (10 kpc spacing)."""
+    w = ci.get_config(3)
+    fs, ps, _ = ci.config_seeds(3)
+    B32 = ci.kolmogorov_field(256, w.spacing, w.l_min, w.l_max, w.b_rms, fs, dtype=np.float32)
+    P = ci.isotropic_particles(N_PART, w.e_min, w.e_max, w.charges, ps)
+    O = oracle_mod
+    prm = O.params_array(w.tol, w.h_min, w.h_max, radius=w.obs_radius, l_max=w.max_length)
+    ref32 = O.propagate(O.Grid(B32, w.spacing), prm, P["pos"], P["dir"], P["energy"], P["charge"])
+    # Lyapunov probe: rotate u0 by 1e-7 rad about an axis normal to it
+    u = P["dir"]
+    ax = np.cross(u, np.array([0.3, 0.5, 0.81]))
+    ax /= np.linalg.norm(ax, axis=1)[:, None]
+    eps = 1e-7
+    up = u * np.cos(eps) + np.cross(ax, u) * np.sin(eps)
+    probe = O.propagate(O.Grid(B32, w.spacing), prm, P["pos"], up, P["energy"], P["charge"])
+    sens = angle(probe["dir"], ref32["dir"])
+    refs = {"f32": ref32}
+    for name, fn in (("f16", ci.round_to_f16), ("bf16", ci.round_to_bf16)):
+        refs[name] = O.propagate(O.Grid(fn(B32), w.spacing), prm, P["pos"], P["dir"], P["energy"], P["charge"])
+    rig = P["energy"] / P["charge"]
+    edges = np.quantile(rig, np.linspace(0, 1, 11))
+    dec = np.clip(np.searchsorted(edges, rig, side="right") - 1, 0, 9)
+    _say(f"mixed setup: probe sensitivity median {np.median(sens):.2e} rad")
+    return w, B32, P, refs, sens, dec
+
+
+def _run(crp, torch, B32, w, P, dtype, precision):
+    f = crp.make_field(B32, w.spacing, dtype=dtype, layout="cell8")
+    prm = crp.make_params(w.tol, w.h_min, w.h_max, obs_radius=w.obs_radius, l_max=w.max_length)
+    st = crp.particles_to_device(P["pos"], P["dir"], P["energy"], P["charge"])
+    crp.crp_propagate([f], [prm], st, precision=precision)
+    torch.cuda.synchronize()
+    return crp.particles_to_host(st)
+
+
+@pytest.mark.parametrize("dtype,acc", [("f16", "f64acc"), ("f16", "dfacc"), ("f32", "f64acc"),
+                                       ("bf16", "f64acc")])
+def test_mixed_errors_against_oracle(dev, setup, dtype, acc):
+    torch, crp = dev
+    w, B32, P, refs, sens, dec = setup
+    prec = crp.CRP_PREC_MIXED_F64ACC if acc == "f64acc" else crp.CRP_PREC_MIXED_DFACC
+    _say(f"case: mixed precision, grid {dtype}, accumulation {acc}")
+    g = _run(crp, torch, B32, w, P, dtype, prec)
+    assert np.mean(g["status"] == refs["f32"]["status"]) > 0.97
+    for ref_name in sorted({"f32", dtype}):
+        r = refs[ref_name]
+        a = angle(g["dir"], r["dir"])
+        dl = np.abs(g["length"] - r["length"]) / r["length"]
+        rows = []
+        for d in range(10):
+            m = dec == d
+            ma, ms = float(np.median(a[m])), float(np.median(sens[m]))
+            rows.append(f"{ma:.1e}/{ms:.1e}")
+            # BF16 keeps 8 mantissa bits: its storage error is a larger perturbation
+            factor = 4.0 if dtype == "bf16" and ref_name == "f32" else 2.5
+            assert ma <= factor * ms + 1e-6, (ref_name, d, ma, ms)
+        _say(f"  vs oracle on {ref_name} grid: angle p50 {np.median(a):.2e} p95 {np.percentile(a, 95):.2e}; "
+             f"|dL|/L p50 {np.median(dl):.2e}; per decile mixed/probe medians: {' '.join(rows)}")
+    # every particle, as a distribution: deflection from the initial direction and path length
+    cos_g = np.sum(g["dir"] * P["dir"], axis=1)
+    cos_o = np.sum(refs["f32"]["dir"] * P["dir"], axis=1)
+    assert ks_2samp(cos_g, cos_o).pvalue > 0.01
+    assert ks_2samp(g["length"], refs["f32"]["length"]).pvalue > 0.01
+    # length stops land exactly on l_max in every precision
+    ml = g["status"] == 2
+    assert np.all(g["length"][ml] == w.max_length)
+
+
+def test_mixed_resume_and_statuses(dev, setup):
+    torch, crp = dev
+    w, B32, P, refs, sens, dec = setup
+    _say("case: mixed precision, budget and resume")
+    f = crp.make_field(B32, w.spacing, dtype="f16", layout="linear")
+    prm = crp.make_params(w.tol, w.h_min, w.h_max, obs_radius=w.obs_radius, l_max=w.max_length, max_steps=50)
+    st = crp.particles_to_device(P["pos"][:500], P["dir"][:500], P["energy"][:500], P["charge"][:500])
+    for _ in range(2000):
+        crp.crp_propagate([f], [prm], st, precision=crp.CRP_PREC_MIXED_F64ACC)
+        s = st["status"]
+        if not bool((s == 3).any()):
+            break
+        s[s == 3] = 0
+    torch.cuda.synchronize()
+    g = crp.particles_to_host(st)
+    assert set(np.unique(g["status"])) <= {1, 2}
+    assert np.all(np.abs(np.linalg.norm(g["dir"], axis=1) - 1) < 1e-6)
