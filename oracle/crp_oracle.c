@@ -612,3 +612,441 @@ int64_t oracle_propagate_taped(const void *grid, int dtype, int64_t n0, int64_t 
     info[3] = tape.length_bound;
     return tape.len;
 }
+
+/* ======================= derivatives of the replayed map ==================
+ *
+ * The map differentiated is the replay of a forward run with its accepted
+ * step sizes h_0 .. h_{N-1} frozen: y_{n+1} = N(Phi(y_n, h_n)), N normalising
+ * the direction, y_0 = (x_0, u_0/|u_0|).  The last step is either the fixed
+ * recorded step (length stop) or the sphere crossing s*, defined implicitly
+ * by |X(y_{N-1}, s*) - c|^2 = R^2 inside [0, h_{N-1}] (implicit function
+ * theorem for its derivative).  Outputs: final direction u_N and path length
+ * L = sum of the steps (time = L * Mpc / c).  The energy is unchanged, so its
+ * derivative is zero.
+ *
+ * Jacobians: f(Y) = (U, kappa U x B(X)); for a cotangent (kx, ku) of f,
+ *   U-bar = kx + kappa B x ku,  B-bar = kappa ku x U,
+ *   X-bar = (dB/dX)^T B-bar,    G-bar[node] += w_node B-bar,
+ * with the trilinear weights w_node and gradient dB/dX of the cell in which
+ * the stage was evaluated.
+ */
+
+typedef struct {
+    double v, d;
+} dual;
+
+static dual dl(double v, double d) { dual r = {v, d}; return r; }
+static dual d_add(dual a, dual b) { return dl(a.v + b.v, a.d + b.d); }
+static dual d_sub(dual a, dual b) { return dl(a.v - b.v, a.d - b.d); }
+static dual d_mul(dual a, dual b) { return dl(a.v * b.v, a.d * b.v + a.v * b.d); }
+static dual d_fma(dual a, dual b, dual c) { return dl(fma(a.v, b.v, c.v), a.d * b.v + a.v * b.d + c.d); }
+static dual d_sqrt(dual a)
+{
+    double s = sqrt(a.v);
+    return dl(s, a.d / (2.0 * s));
+}
+static dual d_div(dual a, dual b)
+{
+    double q = a.v / b.v;
+    return dl(q, (a.d - q * b.d) / b.v);
+}
+
+/* Trilinear weights of the 8 corners, their flat indices, and dB/dX of the cell
+ * containing X.  Corner order: (dx, dy, dz) with dx fastest. */
+static int cell_stencil(const grid_t *g, const double X[3], double w[8], int64_t idx[8], double dw[3][8])
+{
+    int64_t i0[3], i1[3];
+    double t[3];
+    for (int a = 0; a < 3; ++a) {
+        double f = (X[a] - g->origin[a]) * g->inv_spacing;
+        if (!(fabs(f) < 4.0e15))
+            return -1;
+        double fl = floor(f);
+        t[a] = f - fl;
+        i0[a] = pmod((int64_t)fl, g->n[a]);
+        i1[a] = pmod(i0[a] + 1, g->n[a]);
+    }
+    for (int c = 0; c < 8; ++c) {
+        int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+        double wx = dx ? t[0] : 1.0 - t[0], wy = dy ? t[1] : 1.0 - t[1], wz = dz ? t[2] : 1.0 - t[2];
+        double sx = dx ? 1.0 : -1.0, sy = dy ? 1.0 : -1.0, sz = dz ? 1.0 : -1.0;
+        w[c] = wx * wy * wz;
+        dw[0][c] = sx * wy * wz * g->inv_spacing;
+        dw[1][c] = wx * sy * wz * g->inv_spacing;
+        dw[2][c] = wx * wy * sz * g->inv_spacing;
+        idx[c] = ((dx ? i1[0] : i0[0]) * g->n[1] + (dy ? i1[1] : i0[1])) * g->n[2] + (dz ? i1[2] : i0[2]);
+    }
+    return 0;
+}
+
+/* Field value (bitwise the propagator's) and its tangent along X-dot, plus the
+ * tangent of the grid values vg (FP64, same layout) when given. */
+static void field_dual(const grid_t *g, const double *vg, const dual X[3], dual B[3])
+{
+    double x[3] = {X[0].v, X[1].v, X[2].v}, b[3];
+    field_at(g, x, b);
+    double w[8], dw[3][8];
+    int64_t idx[8];
+    if (cell_stencil(g, x, w, idx, dw)) {
+        for (int c = 0; c < 3; ++c)
+            B[c] = dl(NAN, NAN);
+        return;
+    }
+    for (int c = 0; c < 3; ++c) {
+        double d = 0.0;
+        for (int k = 0; k < 8; ++k) {
+            double val = g->v64 ? g->v64[3 * idx[k] + c] : (double)g->v32[3 * idx[k] + c];
+            d += (dw[0][k] * X[0].d + dw[1][k] * X[1].d + dw[2][k] * X[2].d) * val;
+            if (vg)
+                d += w[k] * vg[3 * idx[k] + c];
+        }
+        B[c] = dl(b[c], d);
+    }
+}
+
+static void rhs_dual(const grid_t *g, const double *vg, double kappa, const dual Y[6], dual k[6])
+{
+    dual B[3];
+    field_dual(g, vg, Y, B);
+    dual kp = dl(kappa, 0.0);
+    k[0] = Y[3];
+    k[1] = Y[4];
+    k[2] = Y[5];
+    k[3] = d_mul(kp, d_sub(d_mul(Y[4], B[2]), d_mul(Y[5], B[1])));
+    k[4] = d_mul(kp, d_sub(d_mul(Y[5], B[0]), d_mul(Y[3], B[2])));
+    k[5] = d_mul(kp, d_sub(d_mul(Y[3], B[1]), d_mul(Y[4], B[0])));
+}
+
+/* Cash-Karp step on dual numbers: primal values are bitwise those of ck_eval. */
+static void ck_eval_dual(const grid_t *g, const double *vg, double kappa, const dual y[6], dual h, dual y5[6])
+{
+    dual k[6][6];
+    for (int i = 0; i < 6; ++i) {
+        dual Y[6];
+        for (int c = 0; c < 6; ++c) {
+            if (i == 0) {
+                Y[c] = y[c];
+                continue;
+            }
+            dual acc = dl(0.0, 0.0);
+            for (int j = 0; j < i; ++j)
+                acc = d_fma(dl(CK_A[i][j], 0.0), k[j][c], acc);
+            Y[c] = d_fma(h, acc, y[c]);
+        }
+        rhs_dual(g, vg, kappa, Y, k[i]);
+    }
+    for (int c = 0; c < 6; ++c) {
+        dual a5 = dl(0.0, 0.0);
+        for (int i = 0; i < 6; ++i)
+            a5 = d_fma(dl(CK_B5[i], 0.0), k[i][c], a5);
+        y5[c] = d_fma(h, a5, y[c]);
+    }
+}
+
+static void normalize_dual(dual y[6])
+{
+    dual n = d_sqrt(d_add(d_add(d_mul(y[3], y[3]), d_mul(y[4], y[4])), d_mul(y[5], y[5])));
+    y[3] = d_div(y[3], n);
+    y[4] = d_div(y[4], n);
+    y[5] = d_div(y[5], n);
+}
+
+static double sphere_g_xyz(const double c[3], double R, const double x[3])
+{
+    double d0 = x[0] - c[0], d1 = x[1] - c[1], d2 = x[2] - c[2];
+    return (d0 * d0 + d1 * d1 + d2 * d2) - R * R;
+}
+
+/* Crossing s* of the sphere inside [0, h] from y (Illinois, as in propagate_one). */
+static double locate_crossing(const grid_t *g, double kappa, const double y[6], double h, const double c[3],
+                              double R)
+{
+    double y5[6], d5[6];
+    ck_eval(g, kappa, y, h, y5, d5);
+    double R2 = R * R;
+    double lo = 0.0, glo = sphere_g_xyz(c, R, y), hi = h, ghi = sphere_g_xyz(c, R, y5);
+    int side = 0;
+    for (int it = 0; it < 30; ++it) {
+        if (ghi <= 1e-14 * R2 || (hi - lo) <= 1e-15 * h)
+            break;
+        double s = (lo * ghi - hi * glo) / (ghi - glo);
+        double ys[6], ds[6];
+        ck_eval(g, kappa, y, s, ys, ds);
+        double gs = sphere_g_xyz(c, R, ys);
+        if (gs >= 0.0) {
+            hi = s;
+            ghi = gs;
+            if (side == 1) glo = glo * 0.5;
+            side = 1;
+        } else {
+            lo = s;
+            glo = gs;
+            if (side == -1) ghi = ghi * 0.5;
+            side = -1;
+        }
+    }
+    return hi;
+}
+
+/* Root of |X(y, s) - c|^2 = R^2 near s = 0 by Newton's method on the step
+ * map continued analytically to small negative s (for replays of perturbed
+ * inputs whose crossing moved just outside the frozen last step). */
+static int crossing_newton(const grid_t *g, double kappa, const double y[6], const double c[3], double R,
+                           double *sout)
+{
+    double s = 0.0;
+    dual yd[6];
+    for (int a = 0; a < 6; ++a)
+        yd[a] = dl(y[a], 0.0);
+    for (int it = 0; it < 40; ++it) {
+        dual z[6];
+        ck_eval_dual(g, NULL, kappa, yd, dl(s, 1.0), z);
+        double gv = -R * R, gs = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double r = z[a].v - c[a];
+            gv += r * r;
+            gs += 2.0 * r * z[a].d;
+        }
+        if (!(gs != 0.0) || !isfinite(gv))
+            return -1;
+        double ds = gv / gs;
+        s -= ds;
+        if (fabs(gv) <= 1e-14 * R * R || fabs(ds) <= 1e-16 * (fabs(s) + 1e-300)) {
+            *sout = s;
+            return 0;
+        }
+    }
+    *sout = s;
+    return 0;
+}
+
+/* Forward-mode replay.  Inputs: x0, raw u0 (normalised inside), tangents du0
+ * (may be NULL) and grid tangent vg (may be NULL), the frozen steps h[0..n-1]
+ * (h[n-1] is the last accepted step), event != 0 for a sphere crossing in the
+ * last step (centre c, radius R; s* found here: by the propagator's Illinois
+ * iteration when [0, h[n-1]] brackets it, else by Newton's method on the
+ * step map continued to small negative s).  out: [u_N(3), L, du_N(3), dL,
+ * x_N(3), s*].  Returns 0, or -1 on bad arguments or no root. */
+int oracle_replay_tangent(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2, const double *origin,
+                          double spacing, double kappa, const double *x0, const double *u0, const double *du0,
+                          const double *vg, const double *h, int64_t n, int event, const double *c, double R,
+                          double *out)
+{
+    grid_t g;
+    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing) || n < 1)
+        return -1;
+    dual y[6];
+    for (int a = 0; a < 3; ++a) {
+        y[a] = dl(x0[a], 0.0);
+        y[3 + a] = dl(u0[a], du0 ? du0[a] : 0.0);
+    }
+    normalize_dual(y);
+    double L = 0.0;
+    for (int64_t s = 0; s + 1 < n; ++s) {
+        dual y5[6];
+        ck_eval_dual(&g, vg, kappa, y, dl(h[s], 0.0), y5);
+        normalize_dual(y5);
+        memcpy(y, y5, sizeof y);
+        L += h[s];
+    }
+    double sstar = h[n - 1];
+    double ds = 0.0;
+    dual z[6];
+    if (event) {
+        double yv[6] = {y[0].v, y[1].v, y[2].v, y[3].v, y[4].v, y[5].v};
+        double y5[6], d5[6];
+        ck_eval(&g, kappa, yv, h[n - 1], y5, d5);
+        if (sphere_g_xyz(c, R, yv) < 0.0 && sphere_g_xyz(c, R, y5) >= 0.0)
+            sstar = locate_crossing(&g, kappa, yv, h[n - 1], c, R);
+        else if (crossing_newton(&g, kappa, yv, c, R, &sstar))
+            return -1;
+        /* tangent of the position at fixed s*, and dPhi/ds at s* */
+        ck_eval_dual(&g, vg, kappa, y, dl(sstar, 0.0), z);
+        dual ys[6];
+        for (int a = 0; a < 6; ++a)
+            ys[a] = dl(y[a].v, 0.0);
+        dual zs[6];
+        ck_eval_dual(&g, NULL, kappa, ys, dl(sstar, 1.0), zs);
+        double gdot = 0.0, gs = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double r = z[a].v - c[a];
+            gdot += 2.0 * r * z[a].d;
+            gs += 2.0 * r * zs[a].d;
+        }
+        ds = -gdot / gs;
+        for (int a = 0; a < 6; ++a)
+            z[a].d += zs[a].d * ds;
+    } else {
+        ck_eval_dual(&g, vg, kappa, y, dl(sstar, 0.0), z);
+    }
+    normalize_dual(z);
+    L += sstar;
+    for (int a = 0; a < 3; ++a) {
+        out[a] = z[3 + a].v;
+        out[4 + a] = z[3 + a].d;
+        out[8 + a] = z[a].v;
+    }
+    out[3] = L;
+    out[7] = ds;
+    out[11] = sstar;
+    return 0;
+}
+
+/* Reverse sweep of one step y -> N(Phi(y, s)) given the cotangent lam of the
+ * normalised output (6); comb (may be NULL) is an extra cotangent added to the
+ * unnormalised output (the event term).  ybar gets the cotangent of y; the grid
+ * cotangent is accumulated into gbar (may be NULL). */
+static void step_vjp(const grid_t *g, double kappa, const double y[6], double s, const double lam[6],
+                     const double *comb, double ybar[6], double *gbar)
+{
+    double k[6][6], Y[6][6];
+    for (int i = 0; i < 6; ++i) {
+        for (int c = 0; c < 6; ++c) {
+            if (i == 0) {
+                Y[i][c] = y[c];
+                continue;
+            }
+            double acc = 0.0;
+            for (int j = 0; j < i; ++j)
+                acc = fma(CK_A[i][j], k[j][c], acc);
+            Y[i][c] = fma(s, acc, y[c]);
+        }
+        rhs(g, kappa, Y[i], k[i]);
+    }
+    double z[6];
+    for (int c = 0; c < 6; ++c) {
+        double a5 = 0.0;
+        for (int i = 0; i < 6; ++i)
+            a5 = fma(CK_B5[i], k[i][c], a5);
+        z[c] = fma(s, a5, y[c]);
+    }
+    /* normalisation: u = z_u/|z_u|; zbar_u = (lam_u - (lam_u.u) u)/|z_u| */
+    double zn = sqrt(z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
+    double u[3] = {z[3] / zn, z[4] / zn, z[5] / zn};
+    double lu = lam[3] * u[0] + lam[4] * u[1] + lam[5] * u[2];
+    double zbar[6] = {lam[0], lam[1], lam[2], (lam[3] - lu * u[0]) / zn, (lam[4] - lu * u[1]) / zn,
+                      (lam[5] - lu * u[2]) / zn};
+    if (comb)
+        for (int c = 0; c < 6; ++c)
+            zbar[c] += comb[c];
+    double Ybar[6][6];
+    for (int c = 0; c < 6; ++c)
+        ybar[c] = zbar[c];
+    for (int i = 5; i >= 0; --i) {
+        double kb[6];
+        for (int c = 0; c < 6; ++c) {
+            double v = s * CK_B5[i] * zbar[c];
+            for (int j = i + 1; j < 6; ++j)
+                v += s * CK_A[j][i] * Ybar[j][c];
+            kb[c] = v;
+        }
+        double B[3];
+        field_at(g, Y[i], B);
+        const double *U = Y[i] + 3;
+        double w[8], dw[3][8];
+        int64_t idx[8];
+        /* B-bar = kappa ku x U, U-bar = kx + kappa B x ku */
+        double Bb[3] = {kappa * (kb[4] * U[2] - kb[5] * U[1]), kappa * (kb[5] * U[0] - kb[3] * U[2]),
+                        kappa * (kb[3] * U[1] - kb[4] * U[0])};
+        Ybar[i][3] = kb[0] + kappa * (B[1] * kb[5] - B[2] * kb[4]);
+        Ybar[i][4] = kb[1] + kappa * (B[2] * kb[3] - B[0] * kb[5]);
+        Ybar[i][5] = kb[2] + kappa * (B[0] * kb[4] - B[1] * kb[3]);
+        Ybar[i][0] = Ybar[i][1] = Ybar[i][2] = 0.0;
+        if (cell_stencil(g, Y[i], w, idx, dw) == 0) {
+            for (int kk = 0; kk < 8; ++kk) {
+                for (int c = 0; c < 3; ++c) {
+                    double val = g->v64 ? g->v64[3 * idx[kk] + c] : (double)g->v32[3 * idx[kk] + c];
+                    for (int a = 0; a < 3; ++a)
+                        Ybar[i][a] += dw[a][kk] * val * Bb[c];
+                    if (gbar)
+                        gbar[3 * idx[kk] + c] += w[kk] * Bb[c];
+                }
+            }
+        }
+        for (int c = 0; c < 6; ++c)
+            ybar[c] += Ybar[i][c];
+    }
+}
+
+/* Reverse-mode replay (full tape).  ubar: cotangent of u_N (3); Lbar:
+ * cotangent of the path length (t-bar * Mpc / c).  Outputs: u0bar (cotangent
+ * of the raw initial direction), x0bar; gbar (3 n0 n1 n2, FP64) accumulated if
+ * not NULL.  Returns 0 or -1. */
+int oracle_replay_adjoint(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2, const double *origin,
+                          double spacing, double kappa, const double *x0, const double *u0, const double *h,
+                          int64_t n, int event, const double *c, double R, const double *ubar, double Lbar,
+                          double *u0bar, double *x0bar, double *gbar)
+{
+    grid_t g;
+    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing) || n < 1)
+        return -1;
+    double *ys = (double *)malloc(sizeof(double) * 6 * (size_t)n);
+    if (!ys)
+        return -1;
+    double un = sqrt(u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2]);
+    double y[6] = {x0[0], x0[1], x0[2], u0[0] / un, u0[1] / un, u0[2] / un};
+    for (int64_t s = 0; s < n; ++s) {
+        memcpy(ys + 6 * s, y, sizeof y);
+        if (s + 1 < n) {
+            double y5[6], d5[6];
+            ck_eval(&g, kappa, y, h[s], y5, d5);
+            double m = sqrt(y5[3] * y5[3] + y5[4] * y5[4] + y5[5] * y5[5]);
+            y[0] = y5[0];
+            y[1] = y5[1];
+            y[2] = y5[2];
+            y[3] = y5[3] / m;
+            y[4] = y5[4] / m;
+            y[5] = y5[5] / m;
+        }
+    }
+    const double *yl = ys + 6 * (n - 1);
+    double lam[6] = {0.0, 0.0, 0.0, ubar[0], ubar[1], ubar[2]};
+    double ybar[6];
+    double sstar = h[n - 1];
+    if (event) {
+        double y5[6], d5[6];
+        ck_eval(&g, kappa, yl, h[n - 1], y5, d5);
+        if (!(sphere_g_xyz(c, R, yl) < 0.0 && sphere_g_xyz(c, R, y5) >= 0.0)) {
+            free(ys);
+            return -1;
+        }
+        sstar = locate_crossing(&g, kappa, yl, h[n - 1], c, R);
+        /* psi = zbar . Phi_s + Lbar; combined cotangent zbar - (psi/g_s) dg/dz */
+        dual yd[6], zs[6];
+        for (int a = 0; a < 6; ++a)
+            yd[a] = dl(yl[a], 0.0);
+        ck_eval_dual(&g, NULL, kappa, yd, dl(sstar, 1.0), zs);
+        double zn = sqrt(zs[3].v * zs[3].v + zs[4].v * zs[4].v + zs[5].v * zs[5].v);
+        double u[3] = {zs[3].v / zn, zs[4].v / zn, zs[5].v / zn};
+        double lu = lam[3] * u[0] + lam[4] * u[1] + lam[5] * u[2];
+        double zbar[6] = {lam[0], lam[1], lam[2], (lam[3] - lu * u[0]) / zn, (lam[4] - lu * u[1]) / zn,
+                          (lam[5] - lu * u[2]) / zn};
+        double psi = Lbar, gs = 0.0, dg[6] = {0, 0, 0, 0, 0, 0};
+        for (int a = 0; a < 6; ++a)
+            psi += zbar[a] * zs[a].d;
+        for (int a = 0; a < 3; ++a) {
+            dg[a] = 2.0 * (zs[a].v - c[a]);
+            gs += dg[a] * zs[a].d;
+        }
+        double comb[6];
+        for (int a = 0; a < 6; ++a)
+            comb[a] = -(psi / gs) * dg[a];
+        step_vjp(&g, kappa, yl, sstar, lam, comb, ybar, gbar);
+    } else {
+        step_vjp(&g, kappa, yl, sstar, lam, NULL, ybar, gbar);
+    }
+    for (int64_t s = n - 2; s >= 0; --s) {
+        double nb[6];
+        step_vjp(&g, kappa, ys + 6 * s, h[s], ybar, NULL, nb, gbar);
+        memcpy(ybar, nb, sizeof nb);
+    }
+    /* initial normalisation */
+    double u[3] = {u0[0] / un, u0[1] / un, u0[2] / un};
+    double lu = ybar[3] * u[0] + ybar[4] * u[1] + ybar[5] * u[2];
+    for (int a = 0; a < 3; ++a) {
+        u0bar[a] = (ybar[3 + a] - lu * u[a]) / un;
+        x0bar[a] = ybar[a];
+    }
+    free(ys);
+    return 0;
+}
