@@ -115,6 +115,32 @@ typedef struct {
     int64_t *n_rejected;      /* in/out rejected attempts (cumulative) */
 } crp_particles;
 
+/* Tape of a forward run for the adjoint (checkpointed replay).  The forward
+ * kernel writes, per particle i, a checkpoint record every K accepted steps
+ * into checkpoints[offsets[i] + c] (c = 0 is the state at the start of the
+ * call): 8 doubles (x, y, z, ux, uy, uz, length, controller bid).  Particle i
+ * needs ceil(N_i / K) + 1 records for N_i accepted steps; a particle that
+ * runs out sets the overflow flag.  For every particle it writes finals[4 i ..]:
+ * accepted steps N, the located crossing step s* (0 without one), the last
+ * accepted step size, and flags (CRP_TAPE_* bits, stored as a double); all
+ * zero for a particle that was not ACTIVE on entry or did not complete.
+ * The tape is valid only for crp_propagate_adjoint on the same particles,
+ * field and parameters. */
+typedef struct {
+    double *checkpoints;      /* [dev] pool of 8-double records */
+    const int64_t *offsets;   /* [dev] n + 1 record offsets */
+    double *finals;           /* [dev] 4 n doubles */
+    int32_t every_k;          /* checkpoint interval K, 1 .. 4096 */
+    int32_t reserved;
+} crp_tape;
+
+enum {
+    CRP_TAPE_EVENT = 1,       /* ended by a located sphere crossing */
+    CRP_TAPE_OVERFLOW = 2,    /* more checkpoints than records: no adjoint */
+    CRP_TAPE_FRESH = 4,       /* started fresh (direction normalised on entry) */
+    CRP_TAPE_COMPLETE = 8     /* ended ARRIVED or MAX_LENGTH in this call */
+};
+
 /* Launch configuration; NULL selects the defaults. */
 typedef struct {
     int32_t block_size;       /* threads per block: 64, 128 or 256 (default 256) */
@@ -156,15 +182,39 @@ size_t crp_workspace_bytes(int64_t n, int32_t n_fields, int32_t n_params);
 /* Propagate n particles in place (sections 2, 3.1, 3.2): each ACTIVE particle
  * is stepped until it arrives at its observer sphere, reaches l_max, uses up
  * max_steps, or fails.  fields[n_fields] and params[n_params] are host
- * arrays; every field of one call must share dtype and layout.  precision is
- * a crp_precision.  counters: optional [dev] int64[CRP_NCOUNTERS],
- * accumulated (caller zeroes).  workspace: [dev], crp_workspace_bytes long,
- * 256-byte aligned; its contents are scratch.  Calls that share a workspace
- * must be ordered on one stream. */
+ * arrays; every field of one call must share dtype and layout.  tape: NULL,
+ * or a tape to record for crp_propagate_adjoint (FP64 precision only).
+ * precision is a crp_precision.  counters: optional [dev]
+ * int64[CRP_NCOUNTERS], accumulated (caller zeroes).  workspace: [dev],
+ * crp_workspace_bytes long, 256-byte aligned; its contents are scratch.
+ * Calls that share a workspace must be ordered on one stream. */
 crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_params *params,
-                         int32_t n_params, const crp_particles *p, int64_t n, int32_t precision,
-                         const crp_tuning *tuning, int64_t *counters, void *workspace,
+                         int32_t n_params, const crp_particles *p, int64_t n, const crp_tape *tape,
+                         int32_t precision, const crp_tuning *tuning, int64_t *counters, void *workspace,
                          size_t workspace_bytes, void *stream);
+
+/* Workspace for crp_propagate_adjoint: n particles, checkpoint interval K. */
+size_t crp_adjoint_workspace_bytes(int64_t n, int32_t every_k);
+
+/* Reverse-mode derivatives of the taped forward run (FP64).  The map
+ * differentiated replays the forward pass's accepted steps (their sizes held
+ * fixed) from the checkpoints, segment by segment from the last; the sphere
+ * crossing in the last step is differentiated through its defining equation
+ * |x - c| = R (implicit function theorem).  Inputs: the single field and
+ * parameter group of the forward run; `initial` = the particles' state before
+ * the forward run (raw direction, energy, charge); the cotangents gbar_dir
+ * ([dev] n x 3) of the final direction and gbar_time ([dev] n, per second) of
+ * the arrival time; gbar_energy may be NULL (the energy is unchanged, so it
+ * contributes nothing).  Outputs: grad_u0 ([dev] n x 3, written) with
+ * respect to the initial direction (as given, before normalisation),
+ * grad_x0 ([dev] n x 3, written, may be NULL), and grad_field ([dev] FP64
+ * [n0][n1][n2][3], accumulated: the caller zeroes it) with respect to the
+ * grid values in nG.  Particles without a complete tape get zero gradients.
+ * workspace: [dev] crp_adjoint_workspace_bytes(n, K) bytes, 256-aligned. */
+crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *params, const crp_particles *initial,
+                                 int64_t n, const crp_tape *tape, const double *gbar_dir, const double *gbar_time,
+                                 const double *gbar_energy, double *grad_u0, double *grad_x0,
+                                 double *grad_field, void *workspace, size_t workspace_bytes, void *stream);
 
 /* A captured propagation (hipGraph): the whole sequence of crp_propagate for
  * these exact arguments (descriptor tables, queue reset, longest-first order,

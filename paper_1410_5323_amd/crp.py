@@ -53,6 +53,14 @@ class crp_particles(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in _PARTICLE_FIELDS]
 
 
+class crp_tape(C.Structure):
+    _fields_ = [("checkpoints", C.c_void_p), ("offsets", C.c_void_p), ("finals", C.c_void_p),
+                ("every_k", C.c_int32), ("reserved", C.c_int32)]
+
+
+CRP_TAPE_EVENT, CRP_TAPE_OVERFLOW, CRP_TAPE_FRESH, CRP_TAPE_COMPLETE = 1, 2, 4, 8
+
+
 class crp_tuning(C.Structure):
     _fields_ = [("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("refill_threshold", C.c_int32), ("order_by_rigidity", C.c_int32),
@@ -75,8 +83,15 @@ def lib():
         L.crp_workspace_bytes.argtypes = [C.c_int64, C.c_int32, C.c_int32]
         L.crp_workspace_bytes.restype = C.c_size_t
         L.crp_propagate.argtypes = [C.POINTER(crp_field), C.c_int32, C.POINTER(crp_params), C.c_int32,
-                                    C.POINTER(crp_particles), C.c_int64, C.c_int32,
+                                    C.POINTER(crp_particles), C.c_int64, C.POINTER(crp_tape), C.c_int32,
                                     C.POINTER(crp_tuning), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.crp_adjoint_workspace_bytes.argtypes = [C.c_int64, C.c_int32]
+        L.crp_adjoint_workspace_bytes.restype = C.c_size_t
+        L.crp_propagate_adjoint.argtypes = [C.POINTER(crp_field), C.POINTER(crp_params), C.POINTER(crp_particles),
+                                            C.c_int64, C.POINTER(crp_tape), C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                            C.c_void_p]
+        L.crp_propagate_adjoint.restype = C.c_int
         L.crp_selftest_arith.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
         L.crp_bench_gather.argtypes = [C.POINTER(crp_field), C.c_int64, C.c_int64, C.c_double, C.c_uint64,
                                        C.c_void_p, C.c_void_p]
@@ -152,25 +167,58 @@ def crp_field_upload(desc: crp_field, src, stream=None):
     _check(lib().crp_field_upload(C.byref(desc), _ptr(src), sd, _stream_handle(stream)))
 
 
+class Tape:
+    """Device tape of a forward run: checkpoints every `every_k` accepted steps."""
+
+    def __init__(self, n_accepted, every_k: int = 64, device="cuda"):
+        torch = _torch()
+        per = (n_accepted.to(torch.int64) + every_k - 1) // every_k + 1
+        self.offsets = torch.zeros(len(per) + 1, dtype=torch.int64, device=device)
+        self.offsets[1:] = torch.cumsum(per, 0)
+        total = int(self.offsets[-1].item())
+        self.checkpoints = torch.empty(max(total, 1) * 8, dtype=torch.float64, device=device)
+        self.finals = torch.zeros(4 * len(per), dtype=torch.float64, device=device)
+        self.every_k = int(every_k)
+        self.desc = crp_tape(self.checkpoints.data_ptr(), self.offsets.data_ptr(), self.finals.data_ptr(),
+                             self.every_k, 0)
+
+    def flags(self):
+        return self.finals.view(-1, 4)[:, 3].to(_torch().int32)
+
+
 def crp_propagate(fields, params, particles: dict, precision=CRP_PREC_FP64, tuning=None,
-                  counters=None, workspace=None, stream=None):
+                  counters=None, workspace=None, stream=None, tape=None):
     """Propagate in place.  fields: list of Field; params: list of crp_params;
-    particles: dict of device tensors keyed as in crp_particles."""
+    particles: dict of device tensors keyed as in crp_particles; tape: a Tape."""
     torch = _torch()
-    nf, np_ = len(fields), len(params)
-    farr = (crp_field * nf)(*[f.desc for f in fields])
-    parr = (crp_params * np_)(*params)
-    n = int(particles["energy"].numel())
-    ps = crp_particles(**{k: (particles[k].data_ptr() if particles.get(k) is not None else None)
-                          for k in _PARTICLE_FIELDS})
+    farr, nf, parr, np_, ps, n, tun = _marshal(fields, params, particles, tuning)
     need = crp_workspace_bytes(n, nf, np_)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=particles["energy"].device)
-    tun = C.byref(tuning) if tuning is not None else None
-    _check(lib().crp_propagate(farr, nf, parr, np_, C.byref(ps), n, int(precision), tun,
-                               _ptr(counters), _ptr(workspace), workspace.numel(),
+    _check(lib().crp_propagate(farr, nf, parr, np_, C.byref(ps), n, C.byref(tape.desc) if tape else None,
+                               int(precision), tun, _ptr(counters), _ptr(workspace), workspace.numel(),
                                _stream_handle(stream)))
     return particles
+
+
+def crp_adjoint_workspace_bytes(n: int, every_k: int) -> int:
+    return int(lib().crp_adjoint_workspace_bytes(int(n), int(every_k)))
+
+
+def crp_propagate_adjoint(field, params, initial: dict, tape: Tape, gbar_dir, gbar_time, grad_u0, grad_field,
+                          grad_x0=None, gbar_energy=None, workspace=None, stream=None):
+    """Reverse-mode derivatives of a taped forward run (see crp.h)."""
+    torch = _torch()
+    n = int(initial["energy"].numel())
+    ps = crp_particles(**{k: (initial[k].data_ptr() if initial.get(k) is not None else None)
+                          for k in _PARTICLE_FIELDS})
+    if workspace is None:
+        workspace = torch.empty(crp_adjoint_workspace_bytes(n, tape.every_k), dtype=torch.uint8,
+                                device=initial["energy"].device)
+    _check(lib().crp_propagate_adjoint(C.byref(field.desc), C.byref(params), C.byref(ps), n, C.byref(tape.desc),
+                                       _ptr(gbar_dir), _ptr(gbar_time), _ptr(gbar_energy), _ptr(grad_u0),
+                                       _ptr(grad_x0), _ptr(grad_field), _ptr(workspace), workspace.numel(),
+                                       _stream_handle(stream)))
 
 
 def _marshal(fields, params, particles, tuning):

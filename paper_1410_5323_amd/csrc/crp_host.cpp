@@ -181,8 +181,9 @@ size_t crp_workspace_bytes(int64_t n, int32_t n_fields, int32_t n_params) {
 }
 
 crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_params *params, int32_t n_params,
-                         const crp_particles *p, int64_t n, int32_t precision, const crp_tuning *tuning,
-                         int64_t *counters, void *workspace, size_t workspace_bytes, void *stream) {
+                         const crp_particles *p, int64_t n, const crp_tape *tape, int32_t precision,
+                         const crp_tuning *tuning, int64_t *counters, void *workspace, size_t workspace_bytes,
+                         void *stream) {
     const char *fn = "crp_propagate";
     if (!fields || n_fields < 1 || n_fields > 4096) return fail(CRP_ERR_INVALID, "%s: need 1..4096 fields", fn);
     if (!params || n_params < 1 || n_params > 65536) return fail(CRP_ERR_INVALID, "%s: need 1..65536 params", fn);
@@ -205,6 +206,13 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
         return fail(CRP_ERR_INVALID, "%s: param_index is required with several parameter groups", fn);
     if (precision != CRP_PREC_FP64 && precision != CRP_PREC_MIXED_F64ACC && precision != CRP_PREC_MIXED_DFACC)
         return fail(CRP_ERR_INVALID, "%s: unknown precision %d", fn, precision);
+    if (tape) {
+        if (precision != CRP_PREC_FP64) return fail(CRP_ERR_UNSUPPORTED, "%s: a tape needs FP64 precision", fn);
+        if (tape->every_k < 1 || tape->every_k > 4096)
+            return fail(CRP_ERR_INVALID, "%s: tape interval must be in [1, 4096]", fn);
+        if (n > 0 && (!tape->checkpoints || !tape->offsets || !tape->finals))
+            return fail(CRP_ERR_INVALID, "%s: tape arrays must not be null", fn);
+    }
     crp_tuning t = {256, 4, 32, 1, 0, 0, 0, 0};
     if (tuning) t = *tuning;
     if (t.block_size != 64 && t.block_size != 128 && t.block_size != 256)
@@ -270,6 +278,10 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
     a.counters = reinterpret_cast<unsigned long long *>(counters);
     a.refill_threshold = t.refill_threshold;
     a.n_params = n_params;
+    a.tape_ckpt = tape ? tape->checkpoints : nullptr;
+    a.tape_off = tape ? tape->offsets : nullptr;
+    a.tape_fin = tape ? tape->finals : nullptr;
+    a.tape_k = tape ? tape->every_k : 1;
 
     int64_t need_blocks = (n + t.block_size - 1) / t.block_size;
     int64_t blocks = t.blocks_per_cu == 0 ? need_blocks : (int64_t)cus * t.blocks_per_cu;
@@ -281,6 +293,79 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
     else
         e = crp::launch_propagate_mixed(a, fields[0].dtype, fields[0].layout, multi, precision, cache, (int)blocks,
                                         t.block_size, s);
+    if (e != hipSuccess) return device_error(e, fn);
+    return ok();
+}
+
+// Threads of an adjoint launch (each keeps a column of replay records).
+static int64_t adjoint_lanes(int64_t n) { return n < 65536 ? ((n + 63) / 64) * 64 : 65536; }
+
+size_t crp_adjoint_workspace_bytes(int64_t n, int32_t every_k) {
+    if (n < 0 || every_k < 1 || every_k > 4096) return 0;
+    return crp::adjoint_ws_bytes(n, every_k, adjoint_lanes(n));
+}
+
+crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *params, const crp_particles *initial,
+                                 int64_t n, const crp_tape *tape, const double *gbar_dir, const double *gbar_time,
+                                 const double *gbar_energy, double *grad_u0, double *grad_x0, double *grad_field,
+                                 void *workspace, size_t workspace_bytes, void *stream) {
+    const char *fn = "crp_propagate_adjoint";
+    (void)gbar_energy;  // the energy is unchanged by the propagation: no contribution
+    crp_status st = check_field(field, true, fn);
+    if (st != CRP_OK) return st;
+    if (field->dtype != CRP_F64 && field->dtype != CRP_F32)
+        return fail(CRP_ERR_UNSUPPORTED, "%s: the adjoint reads F64 or F32 grids", fn);
+    if (!params) return fail(CRP_ERR_INVALID, "%s: null params", fn);
+    st = check_params(params, 1, 0);
+    if (st != CRP_OK) return st;
+    if (!initial || !tape) return fail(CRP_ERR_INVALID, "%s: null particles or tape", fn);
+    if (n < 0 || n > (int64_t)0x7fffffff) return fail(CRP_ERR_INVALID, "%s: n out of range", fn);
+    if (tape->every_k < 1 || tape->every_k > 4096) return fail(CRP_ERR_INVALID, "%s: bad tape interval", fn);
+    if (n == 0) return ok();
+    if (!initial->ux || !initial->uy || !initial->uz || !initial->energy || !initial->charge || !tape->checkpoints ||
+        !tape->offsets || !tape->finals || !gbar_dir || !grad_u0 || !grad_field)
+        return fail(CRP_ERR_INVALID, "%s: a required array is null", fn);
+    int64_t lanes = adjoint_lanes(n);
+    size_t need = crp::adjoint_ws_bytes(n, tape->every_k, lanes);
+    if (!workspace || workspace_bytes < need)
+        return fail(CRP_ERR_WORKSPACE, "%s: workspace of %zu bytes needed", fn, need);
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(CRP_ERR_WORKSPACE, "%s: workspace alignment", fn);
+    if (cu_count() <= 0) return fail(CRP_ERR_DEVICE, "%s: no HIP device available", fn);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(workspace);
+    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+    size_t off_order = 256, off_buckets = up(off_order + 4 * size_t(n)), off_seg = up(off_buckets + 8 * size_t(crp::NBUCKET + 1));
+    crp::AdjArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.F = make_field_dev(*field);
+    a.P = make_params_dev(*params);
+    a.x0 = initial->x;
+    a.y0 = initial->y;
+    a.z0 = initial->z;
+    a.ux0 = initial->ux;
+    a.uy0 = initial->uy;
+    a.uz0 = initial->uz;
+    a.energy = initial->energy;
+    a.charge = initial->charge;
+    a.ckpt = tape->checkpoints;
+    a.off = tape->offsets;
+    a.fin = tape->finals;
+    a.K = tape->every_k;
+    a.gbar_dir = gbar_dir;
+    a.gbar_time = gbar_time;
+    a.grad_u0 = grad_u0;
+    a.grad_x0 = grad_x0;
+    a.grad_field = grad_field;
+    a.segbuf = reinterpret_cast<double *>(ws + off_seg);
+    a.lanes = lanes;
+    a.queue = reinterpret_cast<unsigned long long *>(ws);
+    a.order = reinterpret_cast<const int32_t *>(ws + off_order);
+    a.n = n;
+    hipError_t e = crp::launch_fill_u64(a.queue, 0ull, 1, s);
+    if (e == hipSuccess)
+        e = crp::launch_order_by_steps(tape->finals, n, reinterpret_cast<int32_t *>(ws + off_order),
+                                       reinterpret_cast<unsigned int *>(ws + off_buckets), s);
+    if (e == hipSuccess) e = crp::launch_adjoint_fp64(a, (int)(lanes / 64), s);
     if (e != hipSuccess) return device_error(e, fn);
     return ok();
 }
@@ -301,8 +386,8 @@ crp_status crp_graph_create(const crp_field *fields, int32_t n_fields, const crp
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return device_error(e, fn);
-    crp_status st = crp_propagate(fields, n_fields, params, n_params, p, n, precision, tuning, counters, workspace,
-                                  workspace_bytes, stream);
+    crp_status st = crp_propagate(fields, n_fields, params, n_params, p, n, nullptr, precision, tuning, counters,
+                                  workspace, workspace_bytes, stream);
     std::string msg = g_last_error;
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);

@@ -79,9 +79,42 @@ struct PropArgs {
     const int32_t *order;            // NULL: particles in index order
     unsigned long long *queue;       // work-queue head
     unsigned long long *counters;    // NULL or CRP_NCOUNTERS accumulators
+    double *tape_ckpt;               // NULL: no tape; else 8-double checkpoint records
+    const int64_t *tape_off;         // n + 1 record offsets
+    double *tape_fin;                // 4 doubles per particle
+    int32_t tape_k;                  // checkpoint interval
     int32_t refill_threshold;
     int32_t n_params;
 };
+
+// Kernel arguments of the adjoint kernel.
+struct AdjArgs {
+    FieldDev F;
+    ParamsDev P;
+    const double *x0, *y0, *z0, *ux0, *uy0, *uz0, *energy;
+    const int32_t *charge;
+    const double *ckpt;
+    const int64_t *off;
+    const double *fin;
+    int32_t K;
+    int32_t pad_;
+    const double *gbar_dir, *gbar_time;
+    double *grad_u0, *grad_x0, *grad_field;
+    double *segbuf;                  // [step j][7][lane] replay records
+    int64_t lanes;                   // threads launched (segbuf stride)
+    unsigned long long *queue;
+    const int32_t *order;            // NULL: index order
+    int64_t n;
+};
+
+inline size_t adjoint_ws_bytes(int64_t n, int32_t K, int64_t lanes) {
+    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+    size_t b = 256;                                  // queue head
+    b = up(b + 4 * size_t(n > 0 ? n : 0));           // order
+    b = up(b + 8 * size_t(NBUCKET + 1));             // bucket counters
+    b = up(b + 8 * 7 * size_t(K) * size_t(lanes));   // replay records
+    return b;
+}
 
 // Launchers (defined in the .hip files, called by crp_host.cpp).
 hipError_t launch_write_table(void *dst, const void *src, size_t bytes, hipStream_t s);
@@ -92,6 +125,8 @@ hipError_t launch_propagate_fp64(const PropArgs &a, int dtype, int layout, bool 
                                  int block_size, hipStream_t s);
 hipError_t launch_propagate_mixed(const PropArgs &a, int dtype, int layout, bool multi, int precision, bool cache,
                                   int blocks, int block_size, hipStream_t s);
+hipError_t launch_adjoint_fp64(const AdjArgs &a, int blocks, hipStream_t s);
+hipError_t launch_order_by_steps(const double *fin, int64_t n, int32_t *order, unsigned int *buckets, hipStream_t s);
 hipError_t launch_upload(const FieldDev &f, const void *src, int src_dtype, void *dst, hipStream_t s);
 hipError_t launch_selftest(const double *in, double *out, int64_t n, int op, hipStream_t s);
 hipError_t launch_gather_bench(const FieldDev &F, int64_t lanes, int64_t lookups, double spread, uint32_t seed,

@@ -30,7 +30,35 @@ struct Lane {
     double kap, L, hctrl, h;
     int32_t dacc, drej;   // accepted / rejected attempts of this call
     int32_t mode, binding, pidx;
+    int32_t tflags;       // tape flags of this particle (fresh start, overflow)
 };
+
+// Tape: checkpoint c of particle p (state before accepted step c*K).
+__device__ __forceinline__ void tape_checkpoint(const PropArgs &a, int64_t p, Lane &s, int64_t c) {
+    int64_t base = a.tape_off[p], cap = a.tape_off[p + 1] - base;
+    if (c >= cap) {
+        s.tflags |= CRP_TAPE_OVERFLOW;
+        return;
+    }
+    double *r = a.tape_ckpt + 8 * (base + c);
+    r[0] = s.y[0];
+    r[1] = s.y[1];
+    r[2] = s.y[2];
+    r[3] = s.y[3];
+    r[4] = s.y[4];
+    r[5] = s.y[5];
+    r[6] = s.L;
+    r[7] = s.hctrl;
+}
+
+__device__ __forceinline__ void tape_final(const PropArgs &a, int64_t p, const Lane &s, double sstar, double hlast,
+                                           int flags) {
+    double *f = a.tape_fin + 4 * p;
+    f[0] = (double)s.dacc;
+    f[1] = sstar;
+    f[2] = hlast;
+    f[3] = (double)(s.tflags | flags);
+}
 
 // Event-location state, used once per particle: kept in LDS, one slot per
 // thread, so it costs no registers in the main loop.
@@ -105,6 +133,10 @@ enum { F_EVAL = 1, F_ACC = 2, F_REJ = 4, F_EVENT = 8, F_FLOOR = 16 };
 template <bool MULTI>
 __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
     int st = a.status[p];
+    if (a.tape_ckpt) {
+        double *f = a.tape_fin + 4 * p;  // overwritten when the particle completes
+        f[0] = f[1] = f[2] = f[3] = 0.0;
+    }
     if (st != CRP_ST_ACTIVE) return false;
     s.pidx = MULTI && a.param_index ? a.param_index[p] : 0;
     if (MULTI && (s.pidx < 0 || s.pidx >= a.n_params)) {
@@ -142,17 +174,21 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
         a.status[p] = CRP_ST_BAD_INPUT;
         return false;
     }
+    s.tflags = hn == 0.0 ? CRP_TAPE_FRESH : 0;
     if (P.sphere_on && sphere_g(P, s.y) >= 0.0) {
         store(a, p, s, hn, CRP_ST_ARRIVED);
+        if (a.tape_ckpt) tape_final(a, p, s, 0.0, 0.0, CRP_TAPE_COMPLETE);
         return false;
     }
     if (P.lmax_on && s.L >= P.l_max) {
         store(a, p, s, hn, CRP_ST_MAX_LENGTH);
+        if (a.tape_ckpt) tape_final(a, p, s, 0.0, 0.0, CRP_TAPE_COMPLETE);
         return false;
     }
     s.hctrl = hn == 0.0 ? P.h_max : hn;
     s.kap = ((double)Z * K_LORENTZ) / E;
     s.mode = MODE_NORMAL;
+    if (a.tape_ckpt) tape_checkpoint(a, p, s, 0);
     bid(P, s);
     return true;
 }
@@ -174,6 +210,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
         double exh = ex / s.h;
         if (!isfinite(eu) || !isfinite(exh)) {
             store(a, p, s, s.hctrl, CRP_ST_NONFINITE);
+            if (a.tape_ckpt) tape_final(a, p, s, 0.0, 0.0, 0);
             return CRP_ST_NONFINITE;
         }
         double em = eu > exh ? eu : exh;
@@ -230,12 +267,15 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
         s.L = Lnew;
         if (P.lmax_on && s.L >= P.l_max) {
             store(a, p, s, s.hctrl, CRP_ST_MAX_LENGTH);
+            if (a.tape_ckpt) tape_final(a, p, s, 0.0, s.h, CRP_TAPE_COMPLETE);
             return CRP_ST_MAX_LENGTH;
         }
         if (P.max_steps > 0 && s.dacc >= P.max_steps) {
             store(a, p, s, s.hctrl, CRP_ST_MAX_STEPS);
+            if (a.tape_ckpt) tape_final(a, p, s, 0.0, s.h, 0);
             return CRP_ST_MAX_STEPS;
         }
+        if (a.tape_ckpt && s.dacc % a.tape_k == 0) tape_checkpoint(a, p, s, s.dacc / a.tape_k);
         bid(P, s);
         return CRP_ST_ACTIVE;
     }
@@ -245,6 +285,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
         double gs = sphere_g(P, y5);
         if (!isfinite(gs)) {
             store(a, p, s, s.hctrl, CRP_ST_NONFINITE);
+            if (a.tape_ckpt) tape_final(a, p, s, 0.0, 0.0, 0);
             return CRP_ST_NONFINITE;
         }
         if (gs >= 0.0) {
@@ -273,6 +314,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
     s.y[5] = y5[5] / sn;
     s.L = e.hi[t] == e.hacc[t] ? e.lacc[t] : s.L + e.hi[t];
     store(a, p, s, s.hctrl, CRP_ST_ARRIVED);
+    if (a.tape_ckpt) tape_final(a, p, s, e.hi[t], e.hacc[t], CRP_TAPE_COMPLETE | CRP_TAPE_EVENT);
     return CRP_ST_ARRIVED;
 }
 
@@ -362,7 +404,323 @@ hipError_t launch_layout(const PropArgs &a, int layout, bool multi, bool cache, 
                  : launch_c<T, CRP_LAYOUT_LINEAR, false>(a, cache, blocks, bs, s);
 }
 
+// ============================ adjoint ======================================
+//
+// The derivative is that of the replayed map: the accepted step sizes of the
+// taped forward run are held fixed and the sphere crossing in the last step
+// is differentiated through its defining equation (implicit function theorem).
+// Each lane takes one particle; from its last checkpoint segment to its first
+// it replays the segment's accepted steps with the forward kernel's own step
+// logic (so the states are bit-identical), then sweeps them in reverse.
+// Grid-gradient contributions go to a natural-layout FP64 array by atomics.
+
+// Replay m accepted steps from lane state s exactly as advance() takes them,
+// writing (state before the step, step size) into the lane's record column.
+template <class T, int LAYOUT>
+__device__ void replay_segment(const FieldDev &F, const ParamsDev &P, Lane &s, int m, double *buf, int64_t stride,
+                               int64_t lane) {
+    CellCache<T> cache;
+    cache_reset(cache, (T(*)[CACHE_BLOCK]) nullptr, 0);
+    for (int j = 0; j < m; ++j) {
+        bid(P, s);
+        double y5[6], ex, eu, err;
+        for (;;) {
+            ck_eval<T, LAYOUT, false>(F, 0, cache, s.kap, s.y, s.h, y5, ex, eu);
+            double exh = ex / s.h;
+            double em = eu > exh ? eu : exh;
+            err = em / P.tol;
+            if (err > 1.0 && s.h > P.h_min) {
+                double fac = 0.9 * (1.0 / sqrt(sqrt(err)));
+                if (fac < 0.1) fac = 0.1;
+                double h = s.h * fac;
+                if (h < P.h_min) h = P.h_min;
+                s.h = h;
+                s.binding = 0;
+                continue;
+            }
+            break;
+        }
+        double *r = buf + (int64_t)j * 7 * stride + lane;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) r[c * stride] = s.y[c];
+        r[6 * stride] = s.h;
+        double g;
+        if (err > 1.0) {
+            g = 1.0;
+        } else if (err == 0.0) {
+            g = 5.0;
+        } else {
+            g = 0.9 * inv_fifth_root(err);
+            if (g > 5.0) g = 5.0;
+        }
+        double hc = s.h * g;
+        if (hc < P.h_min) hc = P.h_min;
+        if (hc > P.h_max) hc = P.h_max;
+        s.hctrl = hc;
+        double Lnew = s.binding ? P.l_max : s.L + s.h;
+        double un = sqrt(y5[3] * y5[3] + y5[4] * y5[4] + y5[5] * y5[5]);
+        s.y[0] = y5[0];
+        s.y[1] = y5[1];
+        s.y[2] = y5[2];
+        s.y[3] = y5[3] / un;
+        s.y[4] = y5[4] / un;
+        s.y[5] = y5[5] / un;
+        s.L = Lnew;
+    }
+}
+
+// Trilinear stencil of the cell containing X: weights w, their gradients dw
+// (per Mpc), corner values v[corner][c] and flat node indices (natural layout).
+template <class T, int LAYOUT>
+__device__ __forceinline__ void stencil(const FieldDev &F, const double X[3], double w[8], double dw[3][8],
+                                        double v[8][3], int64_t node[8]) {
+    double t[3];
+    int ci[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ci[a] = cell_axis(X[a], F.origin[a], F.inv_spacing, F.n[a], F.pow2, t[a]);
+    T raw[24];
+    load_corners<T, LAYOUT>(F, ci[0], ci[1], ci[2], raw);
+    int i1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) i1[a] = ci[a] + 1 == F.n[a] ? 0 : ci[a] + 1;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+        double wx = dx ? t[0] : 1.0 - t[0], wy = dy ? t[1] : 1.0 - t[1], wz = dz ? t[2] : 1.0 - t[2];
+        double sx = dx ? 1.0 : -1.0, sy = dy ? 1.0 : -1.0, sz = dz ? 1.0 : -1.0;
+        w[k] = wx * wy * wz;
+        dw[0][k] = sx * wy * wz * F.inv_spacing;
+        dw[1][k] = wx * sy * wz * F.inv_spacing;
+        dw[2][k] = wx * wy * sz * F.inv_spacing;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[k][c] = to_f64<T>(raw[k * 3 + c]) * F.value_scale;
+        node[k] = ((int64_t)(dx ? i1[0] : ci[0]) * F.n[1] + (dy ? i1[1] : ci[1])) * F.n[2] + (dz ? i1[2] : ci[2]);
+    }
+}
+
+// Step map and its derivative in the step size at s: z = Phi(y, s), zs = dPhi/ds.
+template <class T, int LAYOUT>
+__device__ void ck_eval_ds(const FieldDev &F, double kap, const double y[6], double s, double z[6], double zs[6]) {
+    CellCache<T> cache;
+    cache_reset(cache, (T(*)[CACHE_BLOCK]) nullptr, 0);
+    constexpr double A[6][5] = {{0, 0, 0, 0, 0},
+                                {A21, 0, 0, 0, 0},
+                                {A31, A32, 0, 0, 0},
+                                {A41, A42, A43, 0, 0},
+                                {A51, A52, A53, A54, 0},
+                                {A61, A62, A63, A64, A65}};
+    constexpr double Bw[6] = {B51, 0.0, B53, B54, 0.0, B56};
+    double k[6][6], kd[6][6];
+    for (int i = 0; i < 6; ++i) {
+        double Y[6], Yd[6];
+        for (int c = 0; c < 6; ++c) {
+            if (i == 0) {
+                Y[c] = y[c];
+                Yd[c] = 0.0;
+                continue;
+            }
+            double acc = 0.0, accd = 0.0;
+            for (int j = 0; j < i; ++j) {
+                acc = fma(A[i][j], k[j][c], acc);
+                accd = A[i][j] * kd[j][c] + accd;
+            }
+            Y[c] = fma(s, acc, y[c]);
+            Yd[c] = acc + s * accd;
+        }
+        rhs<T, LAYOUT, false>(F, 0, cache, kap, Y, k[i]);
+        double w[8], dw[3][8], v[8][3];
+        int64_t node[8];
+        stencil<T, LAYOUT>(F, Y, w, dw, v, node);
+        double B[3], Bd[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double b = 0.0, bd = 0.0;
+            for (int q = 0; q < 8; ++q) {
+                b += w[q] * v[q][c];
+                bd += (dw[0][q] * Yd[0] + dw[1][q] * Yd[1] + dw[2][q] * Yd[2]) * v[q][c];
+            }
+            B[c] = b;
+            Bd[c] = bd;
+        }
+        const double *U = Y + 3;
+        const double *Ud = Yd + 3;
+        kd[i][0] = Ud[0];
+        kd[i][1] = Ud[1];
+        kd[i][2] = Ud[2];
+        kd[i][3] = kap * ((Ud[1] * B[2] + U[1] * Bd[2]) - (Ud[2] * B[1] + U[2] * Bd[1]));
+        kd[i][4] = kap * ((Ud[2] * B[0] + U[2] * Bd[0]) - (Ud[0] * B[2] + U[0] * Bd[2]));
+        kd[i][5] = kap * ((Ud[0] * B[1] + U[0] * Bd[1]) - (Ud[1] * B[0] + U[1] * Bd[0]));
+    }
+    for (int c = 0; c < 6; ++c) {
+        double a5 = 0.0, a5d = 0.0;
+        for (int i = 0; i < 6; ++i) {
+            a5 = fma(Bw[i], k[i][c], a5);
+            a5d = Bw[i] * kd[i][c] + a5d;
+        }
+        z[c] = fma(s, a5, y[c]);
+        zs[c] = a5 + s * a5d;
+    }
+}
+
+// Reverse sweep of one step y -> normalise(Phi(y, s)).  lam: in, cotangent of
+// the normalised output; out, cotangent of y.  comb: optional extra cotangent
+// of the unnormalised output (the crossing term).
+template <class T, int LAYOUT>
+__device__ void step_vjp(const FieldDev &F, double kap, const double y[6], double s, double lam[6],
+                         const double *comb, double *gbar) {
+    CellCache<T> cache;
+    cache_reset(cache, (T(*)[CACHE_BLOCK]) nullptr, 0);
+    constexpr double A[6][5] = {{0, 0, 0, 0, 0},
+                                {A21, 0, 0, 0, 0},
+                                {A31, A32, 0, 0, 0},
+                                {A41, A42, A43, 0, 0},
+                                {A51, A52, A53, A54, 0},
+                                {A61, A62, A63, A64, A65}};
+    constexpr double Bw[6] = {B51, 0.0, B53, B54, 0.0, B56};
+    double k[6][6], Y[6][6];
+    for (int i = 0; i < 6; ++i) {
+        for (int c = 0; c < 6; ++c) {
+            if (i == 0) {
+                Y[i][c] = y[c];
+                continue;
+            }
+            double acc = 0.0;
+            for (int j = 0; j < i; ++j) acc = fma(A[i][j], k[j][c], acc);
+            Y[i][c] = fma(s, acc, y[c]);
+        }
+        rhs<T, LAYOUT, false>(F, 0, cache, kap, Y[i], k[i]);
+    }
+    double z[6];
+    for (int c = 0; c < 6; ++c) {
+        double a5 = 0.0;
+        for (int i = 0; i < 6; ++i) a5 = fma(Bw[i], k[i][c], a5);
+        z[c] = fma(s, a5, y[c]);
+    }
+    double zn = sqrt(z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
+    double u[3] = {z[3] / zn, z[4] / zn, z[5] / zn};
+    double lu = lam[3] * u[0] + lam[4] * u[1] + lam[5] * u[2];
+    double zb[6] = {lam[0], lam[1], lam[2], (lam[3] - lu * u[0]) / zn, (lam[4] - lu * u[1]) / zn,
+                    (lam[5] - lu * u[2]) / zn};
+    if (comb)
+        for (int c = 0; c < 6; ++c) zb[c] += comb[c];
+    double Yb[6][6];
+    double yb[6];
+    for (int c = 0; c < 6; ++c) yb[c] = zb[c];
+    for (int i = 5; i >= 0; --i) {
+        double kb[6];
+        for (int c = 0; c < 6; ++c) {
+            double v = s * Bw[i] * zb[c];
+            for (int j = i + 1; j < 6; ++j) v += s * A[j][i] * Yb[j][c];
+            kb[c] = v;
+        }
+        double w[8], dw[3][8], v[8][3];
+        int64_t node[8];
+        stencil<T, LAYOUT>(F, Y[i], w, dw, v, node);
+        double B[3];
+        lookup<T, LAYOUT>(F, Y[i], B);
+        const double *U = Y[i] + 3;
+        double Bb[3] = {kap * (kb[4] * U[2] - kb[5] * U[1]), kap * (kb[5] * U[0] - kb[3] * U[2]),
+                        kap * (kb[3] * U[1] - kb[4] * U[0])};
+        Yb[i][3] = kb[0] + kap * (B[1] * kb[5] - B[2] * kb[4]);
+        Yb[i][4] = kb[1] + kap * (B[2] * kb[3] - B[0] * kb[5]);
+        Yb[i][5] = kb[2] + kap * (B[0] * kb[4] - B[1] * kb[3]);
+        Yb[i][0] = Yb[i][1] = Yb[i][2] = 0.0;
+        for (int q = 0; q < 8; ++q) {
+            for (int c = 0; c < 3; ++c) {
+                for (int a = 0; a < 3; ++a) Yb[i][a] += dw[a][q] * v[q][c] * Bb[c];
+                unsafeAtomicAdd(gbar + 3 * node[q] + c, w[q] * Bb[c]);
+            }
+        }
+        for (int c = 0; c < 6; ++c) yb[c] += Yb[i][c];
+    }
+    for (int c = 0; c < 6; ++c) lam[c] = yb[c];
+}
+
+template <class T, int LAYOUT>
+__global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
+    const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (;;) {
+        unsigned long long q = atomicAdd(a.queue, 1ull);
+        if (q >= (unsigned long long)a.n) break;
+        const int64_t p = a.order ? (int64_t)a.order[q] : (int64_t)q;
+        const double *fin = a.fin + 4 * p;
+        const int flags = (int)fin[3];
+        const int64_t N = (int64_t)fin[0];
+        double u0[3] = {a.ux0[p], a.uy0[p], a.uz0[p]};
+        double lam[6] = {0.0, 0.0, 0.0, a.gbar_dir[3 * p], a.gbar_dir[3 * p + 1], a.gbar_dir[3 * p + 2]};
+        if (!(flags & CRP_TAPE_COMPLETE) || (flags & CRP_TAPE_OVERFLOW)) {
+            for (int c = 0; c < 3; ++c) {
+                a.grad_u0[3 * p + c] = 0.0;
+                if (a.grad_x0) a.grad_x0[3 * p + c] = 0.0;
+            }
+            continue;
+        }
+        const double kap = ((double)a.charge[p] * K_LORENTZ) / a.energy[p];
+        const double Lbar = a.gbar_time ? a.gbar_time[p] * SEC_PER_MPC : 0.0;
+        const int64_t nseg = N > 0 ? (N + a.K - 1) / a.K : 0;
+        for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+            const double *r = a.ckpt + 8 * (a.off[p] + seg);
+            Lane s;
+            for (int c = 0; c < 6; ++c) s.y[c] = r[c];
+            s.L = r[6];
+            s.hctrl = r[7];
+            s.kap = kap;
+            const int m = (int)(seg == nseg - 1 ? N - seg * a.K : a.K);
+            replay_segment<T, LAYOUT>(a.F, a.P, s, m, a.segbuf, a.lanes, lane);
+            for (int j = m - 1; j >= 0; --j) {
+                const double *rj = a.segbuf + (int64_t)j * 7 * a.lanes + lane;
+                double y[6];
+                for (int c = 0; c < 6; ++c) y[c] = rj[c * a.lanes];
+                double h = rj[6 * a.lanes];
+                if (seg == nseg - 1 && j == m - 1 && (flags & CRP_TAPE_EVENT)) {
+                    // crossing: psi = zbar . Phi_s + Lbar, cotangent zbar - (psi / g_s) dg/dz
+                    const double sstar = fin[1];
+                    double z[6], zs[6];
+                    ck_eval_ds<T, LAYOUT>(a.F, kap, y, sstar, z, zs);
+                    double zn = sqrt(z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
+                    double u[3] = {z[3] / zn, z[4] / zn, z[5] / zn};
+                    double lu = lam[3] * u[0] + lam[4] * u[1] + lam[5] * u[2];
+                    double zb[6] = {lam[0], lam[1], lam[2], (lam[3] - lu * u[0]) / zn, (lam[4] - lu * u[1]) / zn,
+                                    (lam[5] - lu * u[2]) / zn};
+                    double psi = Lbar, gs = 0.0, dg[3];
+                    for (int c = 0; c < 6; ++c) psi += zb[c] * zs[c];
+                    for (int c = 0; c < 3; ++c) {
+                        dg[c] = 2.0 * (z[c] - a.P.center[c]);
+                        gs += dg[c] * zs[c];
+                    }
+                    double comb[6] = {-(psi / gs) * dg[0], -(psi / gs) * dg[1], -(psi / gs) * dg[2], 0.0, 0.0, 0.0};
+                    step_vjp<T, LAYOUT>(a.F, kap, y, sstar, lam, comb, a.grad_field);
+                } else {
+                    step_vjp<T, LAYOUT>(a.F, kap, y, h, lam, nullptr, a.grad_field);
+                }
+            }
+        }
+        // the direction entering the map: normalised on a fresh start
+        if (flags & CRP_TAPE_FRESH) {
+            double un = sqrt(u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2]);
+            double uh[3] = {u0[0] / un, u0[1] / un, u0[2] / un};
+            double lu = lam[3] * uh[0] + lam[4] * uh[1] + lam[5] * uh[2];
+            for (int c = 0; c < 3; ++c) a.grad_u0[3 * p + c] = (lam[3 + c] - lu * uh[c]) / un;
+        } else {
+            for (int c = 0; c < 3; ++c) a.grad_u0[3 * p + c] = lam[3 + c];
+        }
+        if (a.grad_x0)
+            for (int c = 0; c < 3; ++c) a.grad_x0[3 * p + c] = lam[c];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_adjoint_fp64(const AdjArgs &a, int blocks, hipStream_t s) {
+    switch (a.F.dtype * 2 + (a.F.layout == CRP_LAYOUT_CELL8)) {
+        case CRP_F64 * 2: hipLaunchKernelGGL((k_adjoint_fp64<double, CRP_LAYOUT_LINEAR>), dim3(blocks), dim3(64), 0, s, a); break;
+        case CRP_F64 * 2 + 1: hipLaunchKernelGGL((k_adjoint_fp64<double, CRP_LAYOUT_CELL8>), dim3(blocks), dim3(64), 0, s, a); break;
+        case CRP_F32 * 2: hipLaunchKernelGGL((k_adjoint_fp64<float, CRP_LAYOUT_LINEAR>), dim3(blocks), dim3(64), 0, s, a); break;
+        case CRP_F32 * 2 + 1: hipLaunchKernelGGL((k_adjoint_fp64<float, CRP_LAYOUT_CELL8>), dim3(blocks), dim3(64), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_propagate_fp64(const PropArgs &a, int dtype, int layout, bool multi, bool cache, int blocks,
                                  int block_size, hipStream_t s) {

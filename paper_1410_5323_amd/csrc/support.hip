@@ -35,13 +35,33 @@ __device__ __forceinline__ int rigidity_bucket(double E, int Z, int st) {
     return b < 0 ? 0 : (b > NBUCKET - 1 ? NBUCKET - 1 : b);
 }
 
-__global__ void __launch_bounds__(256) k_bucket_count(const double *E, const int32_t *Z, const int32_t *st,
-                                                      int64_t n, unsigned int *counts) {
+// Adjoint work order: most accepted steps first (buckets of 1/8 in log2 N).
+__device__ __forceinline__ int steps_bucket(const double *fin, int64_t i) {
+    double N = fin[4 * i];
+    float l = __log2f((float)N + 1.0f);
+    int b = NBUCKET - 1 - (int)(l * 8.0f);
+    return b < 0 ? 0 : (b > NBUCKET - 1 ? NBUCKET - 1 : b);
+}
+
+struct RigidityKey {
+    const double *E;
+    const int32_t *Z;
+    const int32_t *st;
+    __device__ int operator()(int64_t i) const { return rigidity_bucket(E[i], Z[i], st[i]); }
+};
+
+struct StepsKey {
+    const double *fin;
+    __device__ int operator()(int64_t i) const { return steps_bucket(fin, i); }
+};
+
+template <class Key>
+__global__ void __launch_bounds__(256) k_bucket_count(Key key, int64_t n, unsigned int *counts) {
     __shared__ unsigned int h[NBUCKET];
     h[threadIdx.x] = 0;
     __syncthreads();
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&h[rigidity_bucket(E[i], Z[i], st[i])], 1u);
+        atomicAdd(&h[key(i)], 1u);
     __syncthreads();
     if (h[threadIdx.x]) atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
 }
@@ -61,8 +81,8 @@ __global__ void __launch_bounds__(256) k_bucket_scan(const unsigned int *counts,
     cursors[t] = t == 0 ? 0u : s[t - 1];
 }
 
-__global__ void __launch_bounds__(256) k_bucket_scatter(const double *E, const int32_t *Z, const int32_t *st,
-                                                        int64_t n, unsigned int *cursors, int32_t *order) {
+template <class Key>
+__global__ void __launch_bounds__(256) k_bucket_scatter(Key key, int64_t n, unsigned int *cursors, int32_t *order) {
     __shared__ unsigned int h[NBUCKET];
     __shared__ unsigned int base[NBUCKET];
     for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
@@ -72,7 +92,7 @@ __global__ void __launch_bounds__(256) k_bucket_scatter(const double *E, const i
         int b = 0;
         unsigned int r = 0;
         if (i < n) {
-            b = rigidity_bucket(E[i], Z[i], st[i]);
+            b = key(i);
             r = atomicAdd(&h[b], 1u);
         }
         __syncthreads();
@@ -123,18 +143,27 @@ hipError_t launch_fill_u64(unsigned long long *dst, unsigned long long v, int co
     return hipGetLastError();
 }
 
-hipError_t launch_order_by_rigidity(const double *energy, const int32_t *charge, const int32_t *status,
-                                    int64_t n, int32_t *order, unsigned int *buckets, hipStream_t s) {
+template <class Key>
+hipError_t bucket_order(Key key, int64_t n, int32_t *order, unsigned int *buckets, hipStream_t s) {
     unsigned int *counts = buckets;
     unsigned int *cursors = buckets + NBUCKET;
     hipError_t e = launch_fill_u64(reinterpret_cast<unsigned long long *>(counts), 0ull, NBUCKET / 2, s);
     if (e != hipSuccess) return e;
     int64_t nb = (n + 255) / 256;
     int blocks = (int)(nb < 2048 ? nb : 2048);
-    hipLaunchKernelGGL(k_bucket_count, dim3(blocks), dim3(256), 0, s, energy, charge, status, n, counts);
+    hipLaunchKernelGGL((k_bucket_count<Key>), dim3(blocks), dim3(256), 0, s, key, n, counts);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(NBUCKET), 0, s, counts, cursors);
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(blocks), dim3(256), 0, s, energy, charge, status, n, cursors, order);
+    hipLaunchKernelGGL((k_bucket_scatter<Key>), dim3(blocks), dim3(256), 0, s, key, n, cursors, order);
     return hipGetLastError();
+}
+
+hipError_t launch_order_by_rigidity(const double *energy, const int32_t *charge, const int32_t *status,
+                                    int64_t n, int32_t *order, unsigned int *buckets, hipStream_t s) {
+    return bucket_order(RigidityKey{energy, charge, status}, n, order, buckets, s);
+}
+
+hipError_t launch_order_by_steps(const double *fin, int64_t n, int32_t *order, unsigned int *buckets, hipStream_t s) {
+    return bucket_order(StepsKey{fin}, n, order, buckets, s);
 }
 
 hipError_t launch_selftest(const double *in, double *out, int64_t n, int op, hipStream_t s) {

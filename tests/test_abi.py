@@ -73,7 +73,7 @@ def test_workspace_bytes(crp):
 
 def _call(crp, fields, nf, params, np_, parts, n, prec=0, ws=None, wsb=0):
     L = crp.lib()
-    return L.crp_propagate(fields, nf, params, np_, parts, n, prec, None, None, ws, wsb, None)
+    return L.crp_propagate(fields, nf, params, np_, parts, n, None, prec, None, None, ws, wsb, None)
 
 
 def test_propagate_rejects_bad_arguments_without_device(crp):

@@ -1,0 +1,319 @@
+"""GPU adjoint (crp_propagate_adjoint and the autograd function) against the
+FP64 CPU adjoint of the oracle, central finite differences, an analytic
+rotation in a uniform field and the tape's edge cases.
+
+The derivative is that of the replayed map (accepted step sizes frozen, the
+sphere crossing differentiated through its defining equation).  The GPU
+replays from checkpoints with the forward kernel's step logic, so its states
+are those of the forward run bit for bit; its reverse sweep sums in another
+order than the oracle's, so gradients agree to a relative tolerance:
+1e-8 of the gradient's norm per particle (direction and position), 1e-8 of
+the norm for the grid gradient (which the GPU accumulates with atomics).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import crp_inputs as ci
+from gpu_common import require_gpu, workload
+
+pytestmark = pytest.mark.gpu
+
+SEC_PER_MPC = 102927125054339.0
+GRAD_TOL = 1e-8
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+def _gpu_adjoint(crp, torch, B, spacing, prm, pos, dirs, energy, charge, gdir, gtime, every_k=64,
+                 layout="linear", tape_counts=None):
+    dt = "f64" if B.dtype == np.float64 else "f32"
+    f = crp.make_field(B, spacing, dtype=dt, layout=layout)
+    init = crp.particles_to_device(pos, dirs, energy, charge)
+    n = len(energy)
+    if tape_counts is None:
+        probe = crp.clone_particles(init)
+        crp.crp_propagate([f], [prm], probe)
+        tape_counts = probe["n_accepted"]
+    tape = crp.Tape(tape_counts, every_k=every_k)
+    st = crp.clone_particles(init)
+    crp.crp_propagate([f], [prm], st, tape=tape)
+    gu = torch.full((n, 3), np.nan, dtype=torch.float64, device="cuda")
+    gx = torch.full((n, 3), np.nan, dtype=torch.float64, device="cuda")
+    gg = torch.zeros(B.shape, dtype=torch.float64, device="cuda")
+    gd = torch.from_numpy(np.ascontiguousarray(gdir, dtype=np.float64)).cuda()
+    gt = torch.from_numpy(np.ascontiguousarray(gtime, dtype=np.float64)).cuda()
+    crp.crp_propagate_adjoint(f, prm, init, tape, gd, gt, gu, gg, grad_x0=gx)
+    torch.cuda.synchronize()
+    return {"state": crp.particles_to_host(st), "gu": gu.cpu().numpy(), "gx": gx.cpu().numpy(),
+            "gg": gg.cpu().numpy(), "flags": tape.flags().cpu().numpy(),
+            "finals": tape.finals.view(-1, 4).cpu().numpy()}
+
+
+def _oracle_adjoint(O, B, spacing, prm_arr, pos, dirs, energy, charge, gdir, gtime, center, radius):
+    g = O.Grid(B, spacing)
+    gbar = np.zeros(B.shape, dtype=np.float64)
+    gu, gx, steps = [], [], []
+    for i in range(len(energy)):
+        t = O.propagate_taped(g, prm_arr, pos[i], dirs[i], energy[i], charge[i])
+        assert t["status"] in (1, 2)
+        a = O.replay_adjoint(g, O.kappa(charge[i], energy[i]), pos[i], dirs[i], t["tape"], t["event"], gdir[i],
+                             gtime[i] * SEC_PER_MPC, center=center, radius=radius, gbar=gbar)
+        gu.append(a["u0bar"])
+        gx.append(a["x0bar"])
+        steps.append(t["n_steps"])
+    return np.array(gu), np.array(gx), gbar, np.array(steps)
+
+
+def _rel(a, b):
+    """Relative difference of rows (or of whole arrays with axis=None), with
+    the norms taken after scaling by max |b| so huge gradients do not overflow."""
+    sc = np.maximum(np.max(np.abs(b), axis=-1, keepdims=True), 1e-300)
+    return np.linalg.norm((a - b) / sc, axis=-1) / np.maximum(np.linalg.norm(b / sc, axis=-1), 1e-300)
+
+
+def _rel_all(a, b):
+    return float(_rel(a.reshape(1, -1), b.reshape(1, -1))[0])
+
+
+def _check_against_oracle(O, r, B, spacing, prm_arr, P, sel, gdir, gtime, center, radius, label):
+    gu, gx, gbar, steps = _oracle_adjoint(O, B, spacing, prm_arr, P["pos"][sel], P["dir"][sel], P["energy"][sel],
+                                          P["charge"][sel], gdir, gtime, center, radius)
+    assert np.array_equal(r["finals"][:, 0].astype(np.int64), steps), f"{label}: accepted-step counts differ"
+    eu, ex = _rel(r["gu"], gu), _rel(r["gx"], gx)
+    eg = _rel_all(r["gg"], gbar)
+    _say(f"{label}: steps {steps.min()}..{steps.max()}, max rel err grad_u0 {eu.max():.2e}, "
+         f"grad_x0 {ex.max():.2e}, grid {eg:.2e}")
+    assert eu.max() <= GRAD_TOL and ex.max() <= GRAD_TOL and eg <= GRAD_TOL
+
+
+def test_adjoint_matches_oracle_small_grid(dev, oracle_mod):
+    """32^3 FP64 grid, protons and iron, sphere (r = 2 Mpc) and length stops,
+    both layouts and several checkpoint intervals."""
+    torch, crp = dev
+    O = oracle_mod
+    w, B, _ = workload(0, n=1, grid_dtype="f64")
+    fs, ps, _ = ci.config_seeds(0)
+    P = ci.isotropic_particles(96, 3e18, 3e19, (1, 26), ps)
+    rng = np.random.default_rng(21)
+    gdir = rng.standard_normal((96, 3))
+    gtime = rng.standard_normal(96) * 1e-14
+    prm = crp.make_params(1e-6, 1e-7, 0.2, obs_radius=2.0, l_max=4.0)
+    prm_arr = O.params_array(1e-6, 1e-7, 0.2, radius=2.0, l_max=4.0)
+    sel = np.arange(96)
+    for layout, k in (("linear", 64), ("cell8", 7), ("linear", 1)):
+        _say(f"case: small grid adjoint, layout {layout}, K={k}")
+        r = _gpu_adjoint(crp, torch, B, w.spacing, prm, P["pos"], P["dir"], P["energy"], P["charge"], gdir, gtime,
+                         every_k=k, layout=layout)
+        assert np.all(r["flags"] & 8) and not np.any(r["flags"] & 2)
+        assert np.any(r["flags"] & 1) and not np.all(r["flags"] & 1), "want both sphere and length stops"
+        _check_against_oracle(O, r, B, w.spacing, prm_arr, P, sel, gdir, gtime, (0.0, 0.0, 0.0), 2.0,
+                              f"{layout} K={k}")
+
+
+def test_checkpoint_interval_does_not_change_gradients(dev):
+    torch, crp = dev
+    w, B, P = workload(0, n=200, grid_dtype="f64")
+    rng = np.random.default_rng(22)
+    gdir = rng.standard_normal((200, 3))
+    gtime = np.zeros(200)
+    prm = crp.make_params(1e-5, 1e-6, 0.2, obs_radius=1.5, l_max=20.0)
+    out = {}
+    for k in (1, 5, 64, 4096):
+        _say(f"case: checkpoint interval K={k}")
+        out[k] = _gpu_adjoint(crp, torch, B, w.spacing, prm, P["pos"], P["dir"], P["energy"], P["charge"], gdir,
+                              gtime, every_k=k)
+    for k in (1, 5, 4096):
+        assert np.array_equal(out[k]["gu"], out[64]["gu"]), k
+        assert np.array_equal(out[k]["gx"], out[64]["gx"]), k
+        eg = _rel_all(out[k]["gg"], out[64]["gg"])
+        assert eg <= 1e-12, (k, eg)
+
+
+def test_uniform_field_rotation(dev):
+    """Uniform field, length stop: the direction map is a rotation by -kappa|B|L
+    about B applied to the normalised input; the time gradient vanishes."""
+    torch, crp = dev
+    Bv = np.array([0.3, -0.5, 0.8])
+    grid = np.empty((4, 4, 4, 3))
+    grid[...] = Bv
+    E, Z, L = 2e18, 1, 3.0
+    kap = Z * 9.250628667507923e17 / E
+    u0 = np.array([0.6, 0.0, 0.8])
+    prm = crp.make_params(1e-10, 1e-8, 0.05, l_max=L)
+    _say("case: uniform field rotation")
+    r = _gpu_adjoint(crp, torch, grid, 1.0, prm, np.zeros((4, 3)), np.tile(u0, (4, 1)), np.full(4, E),
+                     np.full(4, Z), np.vstack([np.eye(3), np.zeros((1, 3))]), np.array([0.0, 0.0, 0.0, 1.0]))
+    assert np.all(r["state"]["status"] == 2) and not np.any(r["flags"] & 1)
+    bh = Bv / np.linalg.norm(Bv)
+    ang = -kap * np.linalg.norm(Bv) * L
+    Km = np.array([[0, -bh[2], bh[1]], [bh[2], 0, -bh[0]], [-bh[1], bh[0], 0]])
+    Rm = np.eye(3) + math.sin(ang) * Km + (1 - math.cos(ang)) * Km @ Km
+    J = Rm @ (np.eye(3) - np.outer(u0, u0))
+    assert np.max(np.abs(r["gu"][:3] - J)) < 1e-7  # row a of J is J^T e_a
+    assert np.all(r["gu"][3] == 0.0) and np.all(r["gx"][3] == 0.0)
+
+
+def test_edge_cases(dev):
+    torch, crp = dev
+    w, B, P = workload(0, n=6, grid_dtype="f64")
+    prm = crp.make_params(1e-4, 1e-5, 0.2, obs_radius=2.0, l_max=10.0)
+    _say("case: empty adjoint call")
+    r0 = _gpu_adjoint(crp, torch, B, w.spacing, prm, np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0),
+                      np.zeros(0, np.int32), np.zeros((0, 3)), np.zeros(0))
+    assert r0["gu"].shape == (0, 3) and not np.any(r0["gg"])
+    _say("case: particles starting outside the sphere (no step)")
+    u0 = np.array([[1.0, 2.0, 2.0], [0.0, -3.0, 4.0]])
+    lam = np.array([[0.3, -1.0, 0.5], [1.0, 1.0, 1.0]])
+    r = _gpu_adjoint(crp, torch, B, w.spacing, prm, np.array([[5.0, 0, 0], [0, 0, -9.0]]), u0, np.full(2, 1e18),
+                     np.ones(2, np.int32), lam, np.ones(2))
+    assert np.all(r["state"]["status"] == 1) and np.all(r["finals"][:, 0] == 0)
+    for i in range(2):
+        nu = np.linalg.norm(u0[i])
+        uh = u0[i] / nu
+        assert np.allclose(r["gu"][i], (lam[i] - (lam[i] @ uh) * uh) / nu, rtol=1e-15, atol=1e-15)
+        assert np.all(r["gx"][i] == 0.0)
+    assert not np.any(r["gg"])
+    _say("case: tape too small (overflow) gives zero gradients")
+    counts = torch.zeros(6, dtype=torch.int64, device="cuda")
+    r = _gpu_adjoint(crp, torch, B, w.spacing, prm, P["pos"], P["dir"], P["energy"], P["charge"],
+                     np.ones((6, 3)), np.zeros(6), every_k=4, tape_counts=counts)
+    over = (r["flags"] & 2) != 0
+    # the record after step 4 is needed only if the particle goes on after it
+    assert np.array_equal(over, r["finals"][:, 0] > 4)
+    assert np.all(r["gu"][over] == 0.0) and np.all(r["gx"][over] == 0.0)
+    assert over.any()
+
+
+def _affine_grid():
+    """B = B0 + G x on a 64^3 grid (spacing 0.1 Mpc) centred on the origin.
+    Trilinear interpolation reproduces an affine field exactly, so the field
+    has no kinks where the particles go (the periodic seam is 3.2 Mpc away)
+    and the adaptive forward map is smooth in its inputs: its central
+    differences then match the derivative of the replayed map."""
+    n, sp, org = 64, 0.1, -3.2
+    x = org + np.arange(n) * sp
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    B0 = np.array([0.3, -0.4, 0.6])
+    G = np.array([[0.2, -0.5, 0.1], [0.4, 0.1, -0.3], [-0.2, 0.3, 0.25]])
+    return B0 + np.stack([X, Y, Z], -1) @ G.T, sp, (org, org, org)
+
+
+def test_autograd_against_central_differences(dev):
+    """loss = sum(w . direction) + sum(v * time) through PropagateFunction; its
+    gradients in u0 and in grid values against central differences of the
+    GPU forward in a kink-free (affine) field, sphere stop at 1 Mpc."""
+    torch, crp = dev
+    from paper_1410_5323_amd.autograd import propagate
+    B, sp, org = _affine_grid()
+    fs, ps, _ = ci.config_seeds(0)
+    n = 32
+    P = ci.isotropic_particles(n, 3e18, 1e19, (1,), ps)
+    rng = np.random.default_rng(23)
+    wd = torch.from_numpy(rng.standard_normal((n, 3))).cuda()
+    wt = torch.from_numpy(rng.standard_normal(n) / SEC_PER_MPC).cuda()
+    prm = crp.make_params(1e-8, 1e-9, 0.02, obs_radius=1.0, l_max=3.0)
+    grid = torch.from_numpy(B).cuda().requires_grad_(True)
+    u0 = torch.from_numpy(P["dir"]).cuda().requires_grad_(True)
+    x0 = torch.from_numpy(P["pos"]).cuda()
+    E = torch.from_numpy(P["energy"]).cuda()
+    Zt = torch.from_numpy(P["charge"].astype(np.int32)).cuda()
+    _say("case: autograd forward/backward, affine field")
+    d, t, e, st = propagate(u0, grid, x0, E, Zt, sp, prm, origin=org)
+    loss_i = (d * wd).sum(1) + t * wt
+    loss_i.sum().backward()
+    assert torch.all(st == 1)
+    assert torch.equal(e, E)
+    gu = u0.grad.cpu().numpy()
+    gg = grid.grad.cpu().numpy()
+
+    def losses(u, Bg):
+        f = crp.make_field(Bg, sp, origin=org, dtype="f64")
+        s = crp.particles_to_device(P["pos"], u, P["energy"], P["charge"])
+        crp.crp_propagate([f], [prm], s)
+        dd = torch.stack([s["ux"], s["uy"], s["uz"]], 1)
+        return ((dd * wd).sum(1) + s["time"] * wt).cpu().numpy()
+
+    _say("case: central differences in u0")
+    v = np.cross(P["dir"], rng.standard_normal((n, 3)))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+
+    def fd(eps):
+        return (losses(P["dir"] + eps * v, B) - losses(P["dir"] - eps * v, B)) / (2 * eps)
+
+    d1, d2 = fd(1e-6), fd(2e-6)
+    assert np.max(np.abs(d1 - d2) / np.abs(d1)) <= 1e-6  # smooth at this scale
+    jv = np.sum(gu * v, axis=1)
+    err = np.abs(d1 - jv) / np.abs(jv)
+    _say(f"u0 directional derivatives: max rel err {err.max():.2e}")
+    assert err.max() <= 1e-6
+
+    _say("case: central differences in grid values")
+    for fi in np.argsort(-np.abs(gg).ravel())[:4]:
+        def fdg(eps):
+            Bp, Bm = B.copy(), B.copy()
+            Bp.ravel()[fi] += eps
+            Bm.ravel()[fi] -= eps
+            return (losses(P["dir"], Bp).sum() - losses(P["dir"], Bm).sum()) / (2 * eps)
+
+        g1 = fdg(1e-5)
+        _say(f"grid entry {fi}: fd {g1:.10e} adjoint {gg.ravel()[fi]:.10e}")
+        assert abs(g1 - gg.ravel()[fi]) <= 1e-6 * abs(g1)
+
+
+def test_full_adjoint_workload_sampled(dev, oracle_mod):
+    """The 1e5-particle, 128^3 FP32-grid workload with K = 64 in full on the GPU;
+    sampled particles' direction gradients against the oracle's adjoint, and
+    the grid gradient of a separate run of the sample."""
+    torch, crp = dev
+    O = oracle_mod
+    w, B, P = workload(4)
+    n = len(P["energy"])
+    rng = np.random.default_rng(24)
+    gdir = rng.standard_normal((n, 3))
+    gtime = rng.standard_normal(n) * 1e-14
+    prm = crp.make_params(w.tol, w.h_min, w.h_max, obs_radius=w.obs_radius, l_max=w.max_length)
+    prm_arr = O.params_array(w.tol, w.h_min, w.h_max, radius=w.obs_radius, l_max=w.max_length)
+    _say(f"case: full adjoint workload, {n} particles, 128^3 f32 linear, K={w.checkpoint_every}")
+    r = _gpu_adjoint(crp, torch, B, w.spacing, prm, P["pos"], P["dir"], P["energy"], P["charge"], gdir, gtime,
+                     every_k=w.checkpoint_every)
+    steps = r["finals"][:, 0]
+    _say(f"accepted steps: mean {steps.mean():.0f} max {steps.max():.0f}; sphere stops {np.mean(r['flags'] & 1):.3f}")
+    assert np.all(r["flags"] & 8) and not np.any(r["flags"] & 2)
+    # Deflected trajectories are chaotic: the derivative of the step map grows
+    # exponentially with the number of gyrations, and for the longest ones it
+    # leaves the FP64 range (inf), as the oracle's does.  Short ones stay small.
+    gn = np.max(np.abs(r["gu"]), axis=1)
+    fin = np.isfinite(gn)
+    _say("log10 max|grad_u0| percentiles 10/50/90/99: "
+         + " ".join(f"{v:.1f}" for v in np.percentile(np.log10(gn[fin]), [10, 50, 90, 99]))
+         + f"; non-finite {np.mean(~fin):.4f}")
+    order = np.argsort(steps)
+    assert np.all(fin[order[: n // 2]])
+    # sample: a few short trajectories and a few long ones with finite gradients
+    long_ok = order[n // 2:][fin[order[n // 2:]]]
+    sel = np.sort(np.concatenate([order[rng.choice(n // 2, 6, replace=False)],
+                                  long_ok[rng.choice(len(long_ok), 4, replace=False)]]))
+    gu, gx, gbar, ost = _oracle_adjoint(O, B, w.spacing, prm_arr, P["pos"][sel], P["dir"][sel], P["energy"][sel],
+                                        P["charge"][sel], gdir[sel], gtime[sel], (0.0, 0.0, 0.0), w.obs_radius)
+    assert np.array_equal(steps[sel].astype(np.int64), ost)
+    eu = _rel(r["gu"][sel], gu)
+    _say(f"sampled steps {ost.min()}..{ost.max()}, max rel err grad_u0 {eu.max():.2e}")
+    assert eu.max() <= GRAD_TOL
+    sub = {k: v[sel] for k, v in P.items() if isinstance(v, np.ndarray) and len(v) == n}
+    rs = _gpu_adjoint(crp, torch, B, w.spacing, prm, sub["pos"], sub["dir"], sub["energy"], sub["charge"],
+                      gdir[sel], gtime[sel], every_k=w.checkpoint_every)
+    assert np.array_equal(rs["gu"], r["gu"][sel])
+    eg = _rel_all(rs["gg"], gbar)
+    _say(f"sample grid gradient rel err {eg:.2e}")
+    assert eg <= GRAD_TOL
