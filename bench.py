@@ -116,6 +116,102 @@ def cpu_baseline(grids, radii, w, P, sample: int):
                       f"{evals} evaluations, {dt:.1f} s)"}, out
 
 
+def gather_ceiling(field, lanes: int = 262144, per_lane: int = 200, reps: int = 3) -> dict:
+    """Achievable lookup rate of the grid: the gather microbenchmark (same
+    field, dtype, layout and FP64 trilinear arithmetic as the propagation
+    kernel; independent lookups at uniformly random positions, so no cache
+    locality), best of `reps` launches timed with HIP events."""
+    import torch
+
+    from paper_1410_5323_amd import crp
+    sink = torch.empty(lanes, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    crp.crp_bench_gather(field, lanes, per_lane, 0.0, 1, sink)
+    best = float("inf")
+    for r in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        crp.crp_bench_gather(field, lanes, per_lane, 0.0, 2 + r, sink)
+        b.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b) / 1e3)
+    return {"lookups_per_s": lanes * per_lane / best, "lanes": lanes, "lookups_per_lane": per_lane}
+
+
+def adjoint_leg(reps: int = 2):
+    """Adjoint/forward cost on the differentiation workload (1e5 protons and
+    iron, 128^3 FP32 grid, sphere at 10 Mpc, checkpoints every 64 steps): the
+    plain forward, the taped forward and the adjoint (grid-gradient zeroing
+    included), each timed with HIP events on the launch stream."""
+    import numpy as np
+    import torch
+
+    import crp_inputs as ci
+    from paper_1410_5323_amd import crp
+    w = ci.get_config("adjoint_128cube")
+    grids, radii, P = build_inputs(w, None)
+    n = len(P["energy"])
+    layout = "cell8"
+    f = crp.make_field(grids[0], w.spacing, dtype="f32", layout=layout)
+    prm = crp.make_params(w.tol, w.h_min, w.h_max, obs_radius=w.obs_radius, l_max=w.max_length)
+    init = crp.particles_to_device(P["pos"], P["dir"], P["energy"], P["charge"])
+    ws = torch.empty(crp.crp_workspace_bytes(n, 1, 1), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def ev_time(fn):
+        out = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            out.append(a.elapsed_time(b))
+        return float(np.mean(out))
+
+    st = crp.clone_particles(init)
+    crp.crp_propagate([f], [prm], st, workspace=ws)  # warm-up, and the step counts for the tape
+    torch.cuda.synchronize()
+    tape = crp.Tape(st["n_accepted"], every_k=w.checkpoint_every)
+    steps = int(st["n_accepted"].sum())
+
+    # state copies happen outside the timed region: time only the launches
+    def timed_fwd(tp):
+        times = []
+        for _ in range(reps):
+            s = crp.clone_particles(init)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            crp.crp_propagate([f], [prm], s, workspace=ws, tape=tp)
+            b.record(stream)
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        return float(np.mean(times))
+
+    t_fwd = timed_fwd(None)
+    t_tape = timed_fwd(tape)
+    rng = np.random.default_rng(5)
+    gd = torch.from_numpy(rng.standard_normal((n, 3))).cuda()
+    gt = torch.from_numpy(rng.standard_normal(n) * 1e-14).cuda()
+    gu = torch.empty(n, 3, dtype=torch.float64, device="cuda")
+    gg = torch.zeros(grids[0].shape, dtype=torch.float64, device="cuda")
+    aws = torch.empty(crp.crp_adjoint_workspace_bytes(n, w.checkpoint_every), dtype=torch.uint8, device="cuda")
+
+    def adj():
+        gg.zero_()
+        crp.crp_propagate_adjoint(f, prm, init, tape, gd, gt, gu, gg, workspace=aws)
+
+    t_adj = ev_time(adj)
+    fin = torch.isfinite(gu).all(dim=1)
+    return {"workload": w.name, "particles": n, "layout": layout, "accepted_steps": steps,
+            "forward_ms": t_fwd, "taped_forward_ms": t_tape, "adjoint_ms": t_adj,
+            "adjoint_over_forward": t_adj / t_fwd,
+            "gradient_over_forward": (t_fwd + t_tape + t_adj) / t_fwd,
+            "tape_bytes": int(tape.checkpoints.numel() * 8 + tape.finals.numel() * 8 + tape.offsets.numel() * 8),
+            "finite_gradient_fraction": float(fin.float().mean()),
+            "note": "gradient = counting forward + taped forward + adjoint (the autograd path)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +234,9 @@ def main():
     ap.add_argument("--graph", type=int, default=None, help="1: replay a captured hipGraph (default on for batches)")
     ap.add_argument("--cpu-sample", type=int, default=200000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB twice with the streaming kernel (known bytes, to scale HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -157,6 +256,17 @@ def main():
     crp.lib()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        nb = 1 << 30
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            crp.crp_bench_stream(src, dst, nb, None, 4096)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst)
+        print(json.dumps({"copy_calibration": {"bytes_read_per_launch": nb, "bytes_written_per_launch": nb,
+                                               "launches": 2, "kernel": "k_stream_copy"}}), flush=True)
+        return
 
     w = ci.get_config(args.workload)
     batched = w.n_realisations > 0
@@ -239,6 +349,11 @@ def main():
     achieved = bytes_per_eval * evals_per_launch / avg_launch_s / 1e9
     traffic = measured_traffic(w.name, layout) if prec == 0 else None
     host = head["host"]
+    gc = gather_ceiling(fields[0])
+    lookup_bytes = bytes_per_eval / 6
+    gc["algorithmic_GB_per_s"] = gc["lookups_per_s"] * lookup_bytes / 1e9
+    gc["kernel_fraction"] = achieved / gc["algorithmic_GB_per_s"]
+    log(f"bench: gather ceiling {gc}")
     statuses = {k: int(np.sum(host["status"] == v)) for k, v in crp.STATUS.items() if np.any(host["status"] == v)}
     del fields
     torch.cuda.empty_cache()
@@ -277,6 +392,7 @@ def main():
                    "avg_launch_ms": avg_launch_s * 1e3,
                    "algorithmic_bytes_per_evaluation": bytes_per_eval,
                    "statuses": statuses,
+                   "gather_ceiling": gc,
                    "kernel_source_sha": kernel_source_hash()},
     }
 
@@ -292,6 +408,14 @@ def main():
         result["mixed"] = {"precision": "mixed_f64acc", "grid": f"{w.grid_n}^3 {mdt}", "layout": layout,
                            "avg_launch_ms": mavg, "speedup_vs_fp64": avg_launch_s * 1e3 / mavg,
                            "accepted_steps_per_s": int(mix["counters"][1]) / mix["elapsed"]}
+
+    if not args.no_adjoint:
+        del state, pristine, ws
+        torch.cuda.empty_cache()
+        log("bench: adjoint/forward leg (adjoint_128cube)")
+        result["adjoint"] = adjoint_leg()
+        log(f"bench: adjoint leg {result['adjoint']}")
+        torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         m = min(args.cpu_sample, n)
