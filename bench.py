@@ -388,6 +388,8 @@ def main():
                    "floor_hits_per_launch": int(c[4]) / args.steps,
                    "cell_loads_per_launch": int(c[6]) / args.steps,
                    "cell_cache_hit_rate": 1.0 - int(c[6]) / max(1, 6 * evals),
+                   "wave_iterations_per_launch": int(c[7]) / args.steps,
+                   "lane_utilisation": evals / max(1, 64 * int(c[7])),
                    "evaluations_per_s": evals / elapsed,
                    "avg_launch_ms": avg_launch_s * 1e3,
                    "algorithmic_bytes_per_evaluation": bytes_per_eval,

@@ -161,6 +161,7 @@ enum {
     CRP_CNT_FLOOR_HITS = 4,   /* steps accepted at h_min with error above tolerance */
     CRP_CNT_PARTICLES = 5,    /* particles taken from the queue */
     CRP_CNT_CELL_LOADS = 6,   /* field lookups that read grid memory (the others hit the cell cache) */
+    CRP_CNT_WAVE_ITERS = 7,   /* wavefront loop iterations (lane utilisation = EVALS / (64 x this)) */
     CRP_NCOUNTERS = 8
 };
 

@@ -21,7 +21,7 @@ CRP_LAYOUT_LINEAR, CRP_LAYOUT_CELL8 = 0, 1
 CRP_PREC_FP64, CRP_PREC_MIXED_F64ACC, CRP_PREC_MIXED_DFACC = 0, 1, 2
 STATUS = {"ACTIVE": 0, "ARRIVED": 1, "MAX_LENGTH": 2, "MAX_STEPS": 3, "NONFINITE": 4,
           "CANCELLED": 5, "BAD_INPUT": 6}
-COUNTERS = ["evals", "accepted", "rejected", "event_evals", "floor_hits", "particles", "cell_loads"]
+COUNTERS = ["evals", "accepted", "rejected", "event_evals", "floor_hits", "particles", "cell_loads", "wave_iters"]
 NCOUNTERS = 8
 DTYPES = {"f64": CRP_F64, "f32": CRP_F32, "f16": CRP_F16, "bf16": CRP_BF16}
 LAYOUTS = {"linear": CRP_LAYOUT_LINEAR, "cell8": CRP_LAYOUT_CELL8}

@@ -318,8 +318,15 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
     return CRP_ST_ARRIVED;
 }
 
+// Minimum resident waves per SIMD the register allocation must allow (the
+// kernel is bound by gather latency, so occupancy is what hides it).
+#ifndef CRP_FP64_MIN_WAVES
+#define CRP_FP64_MIN_WAVES 2
+#endif
+
 template <class T, int LAYOUT, bool MULTI, bool CACHE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) k_propagate_fp64(PropArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CRP_FP64_MIN_WAVES, 8)))
+k_propagate_fp64(PropArgs a) {
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
     int64_t pid = -1;  // >= 0 working, -1 wants work, -2 queue exhausted
@@ -329,7 +336,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     CellCache<T> cache;
     cache_reset(cache, cache_lds, threadIdx.x);
     // wave-uniform counters, summed from ballots (scalar registers)
-    unsigned long long n_eval = 0, n_acc = 0, n_rej = 0, n_ev = 0, n_fl = 0, n_taken = 0;
+    unsigned long long n_eval = 0, n_acc = 0, n_rej = 0, n_ev = 0, n_fl = 0, n_taken = 0, n_iter = 0;
 
     for (;;) {
         // refill idle lanes from the work queue
@@ -360,6 +367,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
             if (__ballot(pid == -1) == 0ull) break;
             continue;
         }
+        n_iter++;
         int flags = 0;
         if (pid >= 0) {
             int st = advance<T, LAYOUT, MULTI, CACHE>(a, pid, s, cache, ev, flags);
@@ -378,9 +386,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) m += __shfl_xor(m, off, 64);
         if (lane == 0) {
-            unsigned long long v[7] = {n_eval, n_acc, n_rej, n_ev, n_fl, n_taken, m};
+            unsigned long long v[8] = {n_eval, n_acc, n_rej, n_ev, n_fl, n_taken, m, n_iter};
 #pragma unroll
-            for (int i = 0; i < 7; ++i)
+            for (int i = 0; i < 8; ++i)
                 if (v[i]) atomicAdd(a.counters + i, v[i]);
         }
     }

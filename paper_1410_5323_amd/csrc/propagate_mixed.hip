@@ -516,7 +516,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     CellCache<T> cache;
     cache_reset(cache, cache_lds, threadIdx.x);
     Lane<ACC> s;
-    unsigned long long n_eval = 0, n_acc = 0, n_rej = 0, n_ev = 0, n_fl = 0, n_taken = 0;
+    unsigned long long n_eval = 0, n_acc = 0, n_rej = 0, n_ev = 0, n_fl = 0, n_taken = 0, n_iter = 0;
 
     for (;;) {
         for (;;) {
@@ -546,6 +546,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
             if (__ballot(pid == -1) == 0ull) break;
             continue;
         }
+        n_iter++;
         int flags = 0;
         if (pid >= 0) {
             int st = advance<T, LAYOUT, MULTI, ACC, CACHE>(a, pid, s, cache, ev, flags);
@@ -562,9 +563,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) m += __shfl_xor(m, off, 64);
         if (lane == 0) {
-            unsigned long long v[7] = {n_eval, n_acc, n_rej, n_ev, n_fl, n_taken, m};
+            unsigned long long v[8] = {n_eval, n_acc, n_rej, n_ev, n_fl, n_taken, m, n_iter};
 #pragma unroll
-            for (int i = 0; i < 7; ++i)
+            for (int i = 0; i < 8; ++i)
                 if (v[i]) atomicAdd(a.counters + i, v[i]);
         }
     }
