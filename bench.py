@@ -138,6 +138,44 @@ def gather_ceiling(field, lanes: int = 262144, per_lane: int = 200, reps: int = 
     return {"lookups_per_s": lanes * per_lane / best, "lanes": lanes, "lookups_per_lane": per_lane}
 
 
+def rotate_directions(u, eps: float):
+    """Rotate each unit vector by eps radians about an axis normal to it (a fixed
+    recipe, so the perturbed inputs are reproducible)."""
+    import numpy as np
+    ax = np.cross(u, np.array([0.3, 0.5, 0.81]))
+    ax /= np.linalg.norm(ax, axis=1)[:, None]
+    return u * np.cos(eps) + np.cross(ax, u) * np.sin(eps)
+
+
+def error_report(test: dict, ref: dict, probe: dict, rigidity, radius: float) -> dict:
+    """Angular and time errors of `test` against the FP64 results `ref`, per
+    rigidity decile, next to the FP64 path's own noise floor (`probe`: the FP64
+    path with every initial direction rotated by 1e-7 rad)."""
+    import numpy as np
+    a = angle(test["dir"], ref["dir"])
+    fl = angle(probe["dir"], ref["dir"])
+    dl = np.abs(test["length"] - ref["length"]) / ref["length"]
+    fdl = np.abs(probe["length"] - ref["length"]) / ref["length"]
+    delay = np.maximum(ref["length"] - radius, 1e-300)
+    dd = np.abs(test["length"] - ref["length"]) / delay
+    edges = np.quantile(rigidity, np.linspace(0, 1, 11))
+    dec = np.clip(np.searchsorted(edges, rigidity, side="right") - 1, 0, 9)
+    rows = []
+    for d in range(10):
+        k = dec == d
+        rows.append({"rigidity_V": [float(edges[d]), float(edges[d + 1])],
+                     "angle_p50_rad": float(np.median(a[k])), "noise_floor_angle_p50_rad": float(np.median(fl[k])),
+                     "angle_ratio_to_floor": float(np.median(a[k]) / max(np.median(fl[k]), 1e-300)),
+                     "time_rel_p50": float(np.median(dl[k])), "noise_floor_time_rel_p50": float(np.median(fdl[k]))})
+    return {"angle_rad": {"p50": float(np.median(a)), "p95": float(np.percentile(a, 95)),
+                          "frac_below_1e-4": float(np.mean(a <= 1e-4))},
+            "noise_floor_angle_rad": {"p50": float(np.median(fl)), "p95": float(np.percentile(fl, 95)),
+                                      "frac_below_1e-4": float(np.mean(fl <= 1e-4))},
+            "time_rel": {"p50": float(np.median(dl)), "p95": float(np.percentile(dl, 95))},
+            "time_delay_rel": {"p50": float(np.median(dd)), "p95": float(np.percentile(dd, 95))},
+            "per_rigidity_decile": rows, "particles": int(len(a))}
+
+
 def adjoint_leg(reps: int = 2):
     """Adjoint/forward cost on the differentiation workload (1e5 protons and
     iron, 128^3 FP32 grid, sphere at 10 Mpc, checkpoints every 64 steps): the
@@ -410,6 +448,23 @@ def main():
         result["mixed"] = {"precision": "mixed_f64acc", "grid": f"{w.grid_n}^3 {mdt}", "layout": layout,
                            "avg_launch_ms": mavg, "speedup_vs_fp64": avg_launch_s * 1e3 / mavg,
                            "accepted_steps_per_s": int(mix["counters"][1]) / mix["elapsed"]}
+        # noise floor of the FP64 path on the error sample: the same run with each
+        # initial direction rotated by 1e-7 rad
+        m = min(args.cpu_sample, n)
+        pf = [crp.make_field(g, w.spacing, dtype=gdt_name, layout=layout) for g in grids]
+        probe = crp.particles_to_device(P["pos"][:m], rotate_directions(P["dir"][:m], 1e-7), P["energy"][:m],
+                                        P["charge"][:m])
+        crp.crp_propagate(pf, params[:1], probe, tuning=tuning)
+        torch.cuda.synchronize()
+        probe_host = crp.particles_to_host(probe)
+        del pf, probe
+        torch.cuda.empty_cache()
+        rig = P["energy"][:m] / P["charge"][:m]
+        ref64 = {k: v[:m] for k, v in host.items()}
+        result["mixed"]["error_vs_fp64"] = error_report({k: v[:m] for k, v in mixed_host.items()}, ref64,
+                                                        probe_host, rig, radii[0])
+        result["mixed"]["error_vs_fp64"]["reference"] = ("FP64 path on the FP32 grid (bitwise equal to the oracle "
+                                                         "on this sample)")
 
     if not args.no_adjoint:
         del state, pristine, ws

@@ -310,6 +310,14 @@ def test_full_adjoint_workload_sampled(dev, oracle_mod):
     eu = _rel(r["gu"][sel], gu)
     _say(f"sampled steps {ost.min()}..{ost.max()}, max rel err grad_u0 {eu.max():.2e}")
     assert eu.max() <= GRAD_TOL
+    # the gradients that overflow on the GPU overflow in the oracle's adjoint too
+    bad = np.nonzero(~fin)[0]
+    if len(bad):
+        pick = bad[np.argsort(steps[bad])[:2]]
+        bu, _, _, _ = _oracle_adjoint(O, B, w.spacing, prm_arr, P["pos"][pick], P["dir"][pick], P["energy"][pick],
+                                      P["charge"][pick], gdir[pick], gtime[pick], (0.0, 0.0, 0.0), w.obs_radius)
+        _say(f"overflowing gradients: steps {steps[pick]}, oracle max|grad_u0| {np.max(np.abs(bu), axis=1)}")
+        assert np.all(~np.isfinite(bu).all(axis=1) | (np.max(np.abs(bu), axis=1) > 1e300))
     sub = {k: v[sel] for k, v in P.items() if isinstance(v, np.ndarray) and len(v) == n}
     rs = _gpu_adjoint(crp, torch, B, w.spacing, prm, sub["pos"], sub["dir"], sub["energy"], sub["charge"],
                       gdir[sel], gtime[sel], every_k=w.checkpoint_every)
