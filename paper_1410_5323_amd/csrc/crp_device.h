@@ -231,8 +231,7 @@ __device__ __forceinline__ void lookup_cached(const FieldDev &F, int fid, const 
 // Right-hand side in path length: k = (U, kappa * U x B(X)) for Y = (X, U).
 template <class T, int LAYOUT, bool CACHE>
 __device__ __forceinline__ void rhs(const FieldDev &F, int fid, CellCache<T> &cache, double kap, const double Y[6],
-                                    double k[6]) {
-    double B[3];
+                                    double k[6], double B[3]) {
     lookup_cached<T, LAYOUT, CACHE>(F, fid, Y, B, cache);
     k[0] = Y[3];
     k[1] = Y[4];
@@ -247,35 +246,55 @@ __device__ __forceinline__ void rhs(const FieldDev &F, int fid, CellCache<T> &ca
 
 __device__ __forceinline__ double norm3(double a, double b, double c) { return sqrt(a * a + b * b + c * c); }
 
+// Stage recorder of ck_eval: receives each stage state Y_i (i = 1..5; Y_0 is
+// y itself) and each stage's field value B_i (i = 0..5).  The default records
+// nothing and compiles away.
+struct NoStageRecord {
+    __device__ __forceinline__ void stage(int, const double *) const {}
+    __device__ __forceinline__ void field(int, const double *) const {}
+};
+
 // One Cash-Karp evaluation of step h from y: fifth-order solution y5 and the
 // norms of the embedded error vector delta = h * sum_i e_i k_i split into
 // position (ex) and direction (eu) parts.  Stage sums accumulate over j in
 // increasing order with fma starting from zero; terms with a zero weight are
 // omitted (they only add a signed zero).
-template <class T, int LAYOUT, bool CACHE>
+template <class T, int LAYOUT, bool CACHE, class Rec = NoStageRecord>
 __device__ __forceinline__ void ck_eval(const FieldDev &F, int fid, CellCache<T> &cache, double kap,
-                                        const double y[6], double h, double y5[6], double &ex, double &eu) {
-    double k1[6], k2[6], k3[6], k4[6], k5[6], k6[6], Y[6];
-    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, y, k1);
+                                        const double y[6], double h, double y5[6], double &ex, double &eu,
+                                        const Rec &rec = Rec()) {
+    double k1[6], k2[6], k3[6], k4[6], k5[6], k6[6], Y[6], B[3];
+    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, y, k1, B);
+    rec.field(0, B);
 #pragma unroll
     for (int c = 0; c < 6; ++c) Y[c] = fma(h, fma(A21, k1[c], 0.0), y[c]);
-    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k2);
+    rec.stage(1, Y);
+    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k2, B);
+    rec.field(1, B);
 #pragma unroll
     for (int c = 0; c < 6; ++c) Y[c] = fma(h, fma(A32, k2[c], fma(A31, k1[c], 0.0)), y[c]);
-    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k3);
+    rec.stage(2, Y);
+    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k3, B);
+    rec.field(2, B);
 #pragma unroll
     for (int c = 0; c < 6; ++c)
         Y[c] = fma(h, fma(A43, k3[c], fma(A42, k2[c], fma(A41, k1[c], 0.0))), y[c]);
-    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k4);
+    rec.stage(3, Y);
+    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k4, B);
+    rec.field(3, B);
 #pragma unroll
     for (int c = 0; c < 6; ++c)
         Y[c] = fma(h, fma(A54, k4[c], fma(A53, k3[c], fma(A52, k2[c], fma(A51, k1[c], 0.0)))), y[c]);
-    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k5);
+    rec.stage(4, Y);
+    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k5, B);
+    rec.field(4, B);
 #pragma unroll
     for (int c = 0; c < 6; ++c)
         Y[c] = fma(h, fma(A65, k5[c], fma(A64, k4[c], fma(A63, k3[c], fma(A62, k2[c], fma(A61, k1[c], 0.0))))),
                    y[c]);
-    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k6);
+    rec.stage(5, Y);
+    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k6, B);
+    rec.field(5, B);
     double d[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {

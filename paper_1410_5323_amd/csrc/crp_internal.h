@@ -100,19 +100,25 @@ struct AdjArgs {
     int32_t pad_;
     const double *gbar_dir, *gbar_time;
     double *grad_u0, *grad_x0, *grad_field;
-    double *segbuf;                  // [step j][7][lane] replay records
+    double *segbuf;                  // [step j][55][lane] replay records, then [36][lane] scratch
     int64_t lanes;                   // threads launched (segbuf stride)
     unsigned long long *queue;
     const int32_t *order;            // NULL: index order
     int64_t n;
 };
 
+// Adjoint replay record: doubles per accepted step (pre-step state 6, step 1,
+// stage states 30, stage fields 18), and the crossing-derivative scratch.
+constexpr int ADJ_RECORD_DOUBLES = 55;
+constexpr int ADJ_SCRATCH_DOUBLES = 36;
+
 inline size_t adjoint_ws_bytes(int64_t n, int32_t K, int64_t lanes) {
     auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
     size_t b = 256;                                  // queue head
     b = up(b + 4 * size_t(n > 0 ? n : 0));           // order
     b = up(b + 8 * size_t(NBUCKET + 1));             // bucket counters
-    b = up(b + 8 * 7 * size_t(K) * size_t(lanes));   // replay records
+    b = up(b + 8 * ADJ_RECORD_DOUBLES * size_t(K) * size_t(lanes));  // replay records
+    b = up(b + 8 * ADJ_SCRATCH_DOUBLES * size_t(lanes));             // crossing-derivative scratch
     return b;
 }
 

@@ -415,25 +415,71 @@ hipError_t launch_layout(const PropArgs &a, int layout, bool multi, bool cache, 
 // ============================ adjoint ======================================
 //
 // The derivative is that of the replayed map: the accepted step sizes of the
-// taped forward run are held fixed and the sphere crossing in the last step
-// is differentiated through its defining equation (implicit function theorem).
+// taped forward run are held fixed and the sphere crossing in the last step is
+// differentiated through its defining equation (implicit function theorem).
 // Each lane takes one particle; from its last checkpoint segment to its first
 // it replays the segment's accepted steps with the forward kernel's own step
-// logic (so the states are bit-identical), then sweeps them in reverse.
-// Grid-gradient contributions go to a natural-layout FP64 array by atomics.
+// logic (so the states are bit-identical), recording every accepted step's
+// stage states and stage field values in its own column of the workspace,
+// then sweeps the records in reverse.  The reverse sweep reads the recorded
+// stages instead of recomputing them, so it gathers each stage's cell once
+// (for the field gradient) and scatters the grid-gradient contributions to a
+// natural-layout FP64 array with atomics.
+
+// Record of one accepted step, one column per thread (stride = lanes): the
+// pre-step state y (6), the step size (1), the stage states Y_1..Y_5 (30) and
+// the stage field values B_0..B_5 (18).
+constexpr int REC_Y = 0, REC_H = 6, REC_STAGE = 7, REC_FIELD = 37, REC_SIZE = ADJ_RECORD_DOUBLES;
+static_assert(REC_FIELD + 18 == REC_SIZE, "record layout");
+
+struct RecordWriter {
+    double *r;       // field 0 of the record in this thread's column
+    int64_t stride;  // threads in the launch
+    __device__ __forceinline__ void stage(int i, const double *Y) const {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) r[(REC_STAGE + 6 * (i - 1) + c) * stride] = Y[c];
+    }
+    __device__ __forceinline__ void field(int i, const double *B) const {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r[(REC_FIELD + 3 * i + c) * stride] = B[c];
+    }
+};
+
+// Stage i's state (i = 0 is the pre-step state) and field value from a record.
+__device__ __forceinline__ void rec_stage(const double *r, int64_t stride, int i, double Y[6]) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) Y[c] = r[(i == 0 ? REC_Y + c : REC_STAGE + 6 * (i - 1) + c) * stride];
+}
+__device__ __forceinline__ void rec_field(const double *r, int64_t stride, int i, double B[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) B[c] = r[(REC_FIELD + 3 * i + c) * stride];
+}
+
+// Component c of the stage derivative k_i = (U_i, kappa U_i x B_i), evaluated
+// exactly as the forward right-hand side does.
+__device__ __forceinline__ double stage_k(double kap, const double Y[6], const double B[3], int c) {
+    switch (c) {
+        case 0: return Y[3];
+        case 1: return Y[4];
+        case 2: return Y[5];
+        case 3: return kap * (Y[4] * B[2] - Y[5] * B[1]);
+        case 4: return kap * (Y[5] * B[0] - Y[3] * B[2]);
+        default: return kap * (Y[3] * B[1] - Y[4] * B[0]);
+    }
+}
 
 // Replay m accepted steps from lane state s exactly as advance() takes them,
-// writing (state before the step, step size) into the lane's record column.
+// recording each accepted step.  buf: record 0 in this thread's column.
 template <class T, int LAYOUT>
-__device__ void replay_segment(const FieldDev &F, const ParamsDev &P, Lane &s, int m, double *buf, int64_t stride,
-                               int64_t lane) {
+__device__ void replay_segment(const FieldDev &F, const ParamsDev &P, Lane &s, int m, double *buf, int64_t stride) {
     CellCache<T> cache;
     cache_reset(cache, (T(*)[CACHE_BLOCK]) nullptr, 0);
     for (int j = 0; j < m; ++j) {
         bid(P, s);
+        const RecordWriter rec{buf + (int64_t)j * REC_SIZE * stride, stride};
         double y5[6], ex, eu, err;
         for (;;) {
-            ck_eval<T, LAYOUT, false>(F, 0, cache, s.kap, s.y, s.h, y5, ex, eu);
+            ck_eval<T, LAYOUT, false, RecordWriter>(F, 0, cache, s.kap, s.y, s.h, y5, ex, eu, rec);
             double exh = ex / s.h;
             double em = eu > exh ? eu : exh;
             err = em / P.tol;
@@ -448,10 +494,9 @@ __device__ void replay_segment(const FieldDev &F, const ParamsDev &P, Lane &s, i
             }
             break;
         }
-        double *r = buf + (int64_t)j * 7 * stride + lane;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) r[c * stride] = s.y[c];
-        r[6 * stride] = s.h;
+        for (int c = 0; c < 6; ++c) rec.r[(REC_Y + c) * stride] = s.y[c];
+        rec.r[REC_H * stride] = s.h;
         double g;
         if (err > 1.0) {
             g = 1.0;
@@ -477,176 +522,230 @@ __device__ void replay_segment(const FieldDev &F, const ParamsDev &P, Lane &s, i
     }
 }
 
-// Trilinear stencil of the cell containing X: weights w, their gradients dw
-// (per Mpc), corner values v[corner][c] and flat node indices (natural layout).
+// Cell of X with its trilinear fractions and the cell's stored corner values.
 template <class T, int LAYOUT>
-__device__ __forceinline__ void stencil(const FieldDev &F, const double X[3], double w[8], double dw[3][8],
-                                        double v[8][3], int64_t node[8]) {
-    double t[3];
-    int ci[3];
+__device__ __forceinline__ void cell_of(const FieldDev &F, const double X[3], int ci[3], double t[3], T (&raw)[24]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) ci[a] = cell_axis(X[a], F.origin[a], F.inv_spacing, F.n[a], F.pow2, t[a]);
-    T raw[24];
     load_corners<T, LAYOUT>(F, ci[0], ci[1], ci[2], raw);
-    int i1[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) i1[a] = ci[a] + 1 == F.n[a] ? 0 : ci[a] + 1;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
-        double wx = dx ? t[0] : 1.0 - t[0], wy = dy ? t[1] : 1.0 - t[1], wz = dz ? t[2] : 1.0 - t[2];
-        double sx = dx ? 1.0 : -1.0, sy = dy ? 1.0 : -1.0, sz = dz ? 1.0 : -1.0;
-        w[k] = wx * wy * wz;
-        dw[0][k] = sx * wy * wz * F.inv_spacing;
-        dw[1][k] = wx * sy * wz * F.inv_spacing;
-        dw[2][k] = wx * wy * sz * F.inv_spacing;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) v[k][c] = to_f64<T>(raw[k * 3 + c]) * F.value_scale;
-        node[k] = ((int64_t)(dx ? i1[0] : ci[0]) * F.n[1] + (dy ? i1[1] : ci[1])) * F.n[2] + (dz ? i1[2] : ci[2]);
-    }
 }
 
-// Step map and its derivative in the step size at s: z = Phi(y, s), zs = dPhi/ds.
-template <class T, int LAYOUT>
-__device__ void ck_eval_ds(const FieldDev &F, double kap, const double y[6], double s, double z[6], double zs[6]) {
-    CellCache<T> cache;
-    cache_reset(cache, (T(*)[CACHE_BLOCK]) nullptr, 0);
-    constexpr double A[6][5] = {{0, 0, 0, 0, 0},
+// Corner q (bit 0: +x, bit 1: +y, bit 2: +z) of the cell: its trilinear
+// weight, the weight's gradient (per Mpc) and the node's index in the natural
+// [n0][n1][n2] layout.
+__device__ __forceinline__ double corner_weight(const FieldDev &F, const int ci[3], const double t[3], int q,
+                                                double dw[3], int64_t &node) {
+    const int dx = q & 1, dy = (q >> 1) & 1, dz = (q >> 2) & 1;
+    const double wx = dx ? t[0] : 1.0 - t[0], wy = dy ? t[1] : 1.0 - t[1], wz = dz ? t[2] : 1.0 - t[2];
+    const double sx = dx ? 1.0 : -1.0, sy = dy ? 1.0 : -1.0, sz = dz ? 1.0 : -1.0;
+    dw[0] = sx * wy * wz * F.inv_spacing;
+    dw[1] = wx * sy * wz * F.inv_spacing;
+    dw[2] = wx * wy * sz * F.inv_spacing;
+    const int ix = dx ? (ci[0] + 1 == F.n[0] ? 0 : ci[0] + 1) : ci[0];
+    const int iy = dy ? (ci[1] + 1 == F.n[1] ? 0 : ci[1] + 1) : ci[1];
+    const int iz = dz ? (ci[2] + 1 == F.n[2] ? 0 : ci[2] + 1) : ci[2];
+    node = ((int64_t)ix * F.n[1] + iy) * F.n[2] + iz;
+    return wx * wy * wz;
+}
+
+constexpr double ADJ_A[6][5] = {{0, 0, 0, 0, 0},
                                 {A21, 0, 0, 0, 0},
                                 {A31, A32, 0, 0, 0},
                                 {A41, A42, A43, 0, 0},
                                 {A51, A52, A53, A54, 0},
                                 {A61, A62, A63, A64, A65}};
-    constexpr double Bw[6] = {B51, 0.0, B53, B54, 0.0, B56};
-    double k[6][6], kd[6][6];
+constexpr double ADJ_B5[6] = {B51, 0.0, B53, B54, 0.0, B56};
+
+// Unnormalised output z = Phi(y, h) of a recorded step: the fifth-order sum
+// over the recorded stages, evaluated as the forward step does.
+__device__ __forceinline__ void rec_output(double kap, const double *r, int64_t stride, double z[6]) {
+    double a5[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
     for (int i = 0; i < 6; ++i) {
-        double Y[6], Yd[6];
+        double Y[6], B[3];
+        rec_stage(r, stride, i, Y);
+        rec_field(r, stride, i, B);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) a5[c] = fma(ADJ_B5[i], stage_k(kap, Y, B, c), a5[c]);
+    }
+    const double h = r[REC_H * stride];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) z[c] = fma(h, a5[c], r[(REC_Y + c) * stride]);
+}
+
+// Derivative in the step size of the recorded step's output, dz/ds at s = h
+// (forward mode through the stages; dB/ds from the trilinear gradient of the
+// stage's cell).  kd: scratch column of 36 values for the stage derivatives.
+template <class T, int LAYOUT>
+__device__ void rec_output_ds(const FieldDev &F, double kap, const double *r, int64_t stride, double *kd,
+                              double zs[6]) {
+    const double s = r[REC_H * stride];
+    double a5[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, a5d[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < 6; ++i) {
+        double Yd[6];
         for (int c = 0; c < 6; ++c) {
             if (i == 0) {
-                Y[c] = y[c];
                 Yd[c] = 0.0;
                 continue;
             }
             double acc = 0.0, accd = 0.0;
             for (int j = 0; j < i; ++j) {
-                acc = fma(A[i][j], k[j][c], acc);
-                accd = A[i][j] * kd[j][c] + accd;
+                double Yj[6], Bj[3];
+                rec_stage(r, stride, j, Yj);
+                rec_field(r, stride, j, Bj);
+                acc = fma(ADJ_A[i][j], stage_k(kap, Yj, Bj, c), acc);
+                accd = ADJ_A[i][j] * kd[(6 * j + c) * stride] + accd;
             }
-            Y[c] = fma(s, acc, y[c]);
             Yd[c] = acc + s * accd;
         }
-        rhs<T, LAYOUT, false>(F, 0, cache, kap, Y, k[i]);
-        double w[8], dw[3][8], v[8][3];
-        int64_t node[8];
-        stencil<T, LAYOUT>(F, Y, w, dw, v, node);
-        double B[3], Bd[3];
+        double Y[6];
+        rec_stage(r, stride, i, Y);
+        int ci[3];
+        double t[3];
+        T raw[24];
+        cell_of<T, LAYOUT>(F, Y, ci, t, raw);
+        double Bs[3] = {0.0, 0.0, 0.0}, Bd[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < 8; ++q) {
+            double dw[3];
+            int64_t node;
+            const double w = corner_weight(F, ci, t, q, dw, node);
+            const double gd = dw[0] * Yd[0] + dw[1] * Yd[1] + dw[2] * Yd[2];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double b = 0.0, bd = 0.0;
-            for (int q = 0; q < 8; ++q) {
-                b += w[q] * v[q][c];
-                bd += (dw[0][q] * Yd[0] + dw[1][q] * Yd[1] + dw[2][q] * Yd[2]) * v[q][c];
+            for (int c = 0; c < 3; ++c) {
+                const double v = to_f64<T>(raw[q * 3 + c]) * F.value_scale;
+                Bs[c] += w * v;
+                Bd[c] += gd * v;
             }
-            B[c] = b;
-            Bd[c] = bd;
         }
-        const double *U = Y + 3;
-        const double *Ud = Yd + 3;
-        kd[i][0] = Ud[0];
-        kd[i][1] = Ud[1];
-        kd[i][2] = Ud[2];
-        kd[i][3] = kap * ((Ud[1] * B[2] + U[1] * Bd[2]) - (Ud[2] * B[1] + U[2] * Bd[1]));
-        kd[i][4] = kap * ((Ud[2] * B[0] + U[2] * Bd[0]) - (Ud[0] * B[2] + U[0] * Bd[2]));
-        kd[i][5] = kap * ((Ud[0] * B[1] + U[0] * Bd[1]) - (Ud[1] * B[0] + U[1] * Bd[0]));
-    }
-    for (int c = 0; c < 6; ++c) {
-        double a5 = 0.0, a5d = 0.0;
-        for (int i = 0; i < 6; ++i) {
-            a5 = fma(Bw[i], k[i][c], a5);
-            a5d = Bw[i] * kd[i][c] + a5d;
+        const double *U = Y + 3, *Ud = Yd + 3;
+        double kdi[6] = {Ud[0], Ud[1], Ud[2],
+                         kap * ((Ud[1] * Bs[2] + U[1] * Bd[2]) - (Ud[2] * Bs[1] + U[2] * Bd[1])),
+                         kap * ((Ud[2] * Bs[0] + U[2] * Bd[0]) - (Ud[0] * Bs[2] + U[0] * Bd[2])),
+                         kap * ((Ud[0] * Bs[1] + U[0] * Bd[1]) - (Ud[1] * Bs[0] + U[1] * Bd[0]))};
+        double B[3];
+        rec_field(r, stride, i, B);
+        for (int c = 0; c < 6; ++c) {
+            kd[(6 * i + c) * stride] = kdi[c];
+            a5[c] = fma(ADJ_B5[i], stage_k(kap, Y, B, c), a5[c]);
+            a5d[c] = ADJ_B5[i] * kdi[c] + a5d[c];
         }
-        z[c] = fma(s, a5, y[c]);
-        zs[c] = a5 + s * a5d;
     }
+    for (int c = 0; c < 6; ++c) zs[c] = a5[c] + s * a5d[c];
 }
 
-// Reverse sweep of one step y -> normalise(Phi(y, s)).  lam: in, cotangent of
-// the normalised output; out, cotangent of y.  comb: optional extra cotangent
-// of the unnormalised output (the crossing term).
+// Grid-gradient accumulator of one lane: the contributions to the 8 corners of
+// the last cell touched, held in LDS (one column per lane, so no two lanes
+// share a slot) and added to the global gradient with atomics only when the
+// lane moves to another cell or finishes its particle.  Small steps visit the
+// same cell for many stages in a row, so most contributions never leave LDS.
+struct GradAccum {
+    double (*v)[64];  // LDS [24][64]: corner q, component c at row 3 q + c
+    int t;            // lane within the wavefront
+    uint32_t key;     // cell (i n1 + j) n2 + k, 0xffffffff when empty
+    int ci[3];
+};
+
+__device__ __forceinline__ void grad_flush(const FieldDev &F, GradAccum &g, double *gbar) {
+    if (g.key == 0xffffffffu) return;
+    const double t0[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        double dw[3];
+        int64_t node;
+        corner_weight(F, g.ci, t0, q, dw, node);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) unsafeAtomicAdd(gbar + 3 * node + c, g.v[3 * q + c][g.t]);
+    }
+    g.key = 0xffffffffu;
+}
+
+// Make ci the accumulator's cell, flushing and clearing the slots when it
+// changes.
+__device__ __forceinline__ void grad_select(const FieldDev &F, GradAccum &g, const int ci[3], double *gbar) {
+    const uint32_t key = ((uint32_t)ci[0] * (uint32_t)F.n[1] + (uint32_t)ci[1]) * (uint32_t)F.n[2] + (uint32_t)ci[2];
+    if (key == g.key) return;
+    grad_flush(F, g, gbar);
+    g.key = key;
+    g.ci[0] = ci[0];
+    g.ci[1] = ci[1];
+    g.ci[2] = ci[2];
+#pragma unroll
+    for (int r = 0; r < 24; ++r) g.v[r][g.t] = 0.0;
+}
+
+// Reverse sweep of one recorded step y -> normalise(Phi(y, h)).  lam: in, the
+// cotangent of the normalised output; out, the cotangent of y.  comb (three
+// values or NULL): extra cotangent of the unnormalised output position (the
+// crossing term).  Grid-gradient contributions go to gbar.
 template <class T, int LAYOUT>
-__device__ void step_vjp(const FieldDev &F, double kap, const double y[6], double s, double lam[6],
-                         const double *comb, double *gbar) {
-    CellCache<T> cache;
-    cache_reset(cache, (T(*)[CACHE_BLOCK]) nullptr, 0);
-    constexpr double A[6][5] = {{0, 0, 0, 0, 0},
-                                {A21, 0, 0, 0, 0},
-                                {A31, A32, 0, 0, 0},
-                                {A41, A42, A43, 0, 0},
-                                {A51, A52, A53, A54, 0},
-                                {A61, A62, A63, A64, A65}};
-    constexpr double Bw[6] = {B51, 0.0, B53, B54, 0.0, B56};
-    double k[6][6], Y[6][6];
-    for (int i = 0; i < 6; ++i) {
-        for (int c = 0; c < 6; ++c) {
-            if (i == 0) {
-                Y[i][c] = y[c];
-                continue;
-            }
-            double acc = 0.0;
-            for (int j = 0; j < i; ++j) acc = fma(A[i][j], k[j][c], acc);
-            Y[i][c] = fma(s, acc, y[c]);
-        }
-        rhs<T, LAYOUT, false>(F, 0, cache, kap, Y[i], k[i]);
-    }
+__device__ void reverse_step(const FieldDev &F, double kap, const double *r, int64_t stride, double lam[6],
+                             const double *comb, GradAccum &acc, double *gbar) {
+    const double s = r[REC_H * stride];
     double z[6];
-    for (int c = 0; c < 6; ++c) {
-        double a5 = 0.0;
-        for (int i = 0; i < 6; ++i) a5 = fma(Bw[i], k[i][c], a5);
-        z[c] = fma(s, a5, y[c]);
-    }
-    double zn = sqrt(z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
-    double u[3] = {z[3] / zn, z[4] / zn, z[5] / zn};
-    double lu = lam[3] * u[0] + lam[4] * u[1] + lam[5] * u[2];
+    rec_output(kap, r, stride, z);
+    const double zn = sqrt(z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
+    const double u[3] = {z[3] / zn, z[4] / zn, z[5] / zn};
+    const double lu = lam[3] * u[0] + lam[4] * u[1] + lam[5] * u[2];
     double zb[6] = {lam[0], lam[1], lam[2], (lam[3] - lu * u[0]) / zn, (lam[4] - lu * u[1]) / zn,
                     (lam[5] - lu * u[2]) / zn};
     if (comb)
-        for (int c = 0; c < 6; ++c) zb[c] += comb[c];
+        for (int c = 0; c < 3; ++c) zb[c] += comb[c];
     double Yb[6][6];
     double yb[6];
+#pragma unroll
     for (int c = 0; c < 6; ++c) yb[c] = zb[c];
+#pragma unroll
     for (int i = 5; i >= 0; --i) {
         double kb[6];
+#pragma unroll
         for (int c = 0; c < 6; ++c) {
-            double v = s * Bw[i] * zb[c];
-            for (int j = i + 1; j < 6; ++j) v += s * A[j][i] * Yb[j][c];
+            double v = s * ADJ_B5[i] * zb[c];
+#pragma unroll
+            for (int j = i + 1; j < 6; ++j) v += s * ADJ_A[j][i] * Yb[j][c];
             kb[c] = v;
         }
-        double w[8], dw[3][8], v[8][3];
-        int64_t node[8];
-        stencil<T, LAYOUT>(F, Y[i], w, dw, v, node);
-        double B[3];
-        lookup<T, LAYOUT>(F, Y[i], B);
-        const double *U = Y[i] + 3;
-        double Bb[3] = {kap * (kb[4] * U[2] - kb[5] * U[1]), kap * (kb[5] * U[0] - kb[3] * U[2]),
-                        kap * (kb[3] * U[1] - kb[4] * U[0])};
+        double Y[6], B[3];
+        rec_stage(r, stride, i, Y);
+        rec_field(r, stride, i, B);
+        const double *U = Y + 3;
+        const double Bb[3] = {kap * (kb[4] * U[2] - kb[5] * U[1]), kap * (kb[5] * U[0] - kb[3] * U[2]),
+                              kap * (kb[3] * U[1] - kb[4] * U[0])};
         Yb[i][3] = kb[0] + kap * (B[1] * kb[5] - B[2] * kb[4]);
         Yb[i][4] = kb[1] + kap * (B[2] * kb[3] - B[0] * kb[5]);
         Yb[i][5] = kb[2] + kap * (B[0] * kb[4] - B[1] * kb[3]);
         Yb[i][0] = Yb[i][1] = Yb[i][2] = 0.0;
+        int ci[3];
+        double t[3];
+        T raw[24];
+        cell_of<T, LAYOUT>(F, Y, ci, t, raw);
+        grad_select(F, acc, ci, gbar);
+#pragma unroll
         for (int q = 0; q < 8; ++q) {
+            double dw[3];
+            int64_t node;
+            const double w = corner_weight(F, ci, t, q, dw, node);
+#pragma unroll
             for (int c = 0; c < 3; ++c) {
-                for (int a = 0; a < 3; ++a) Yb[i][a] += dw[a][q] * v[q][c] * Bb[c];
-                unsafeAtomicAdd(gbar + 3 * node[q] + c, w[q] * Bb[c]);
+                const double v = to_f64<T>(raw[q * 3 + c]) * F.value_scale;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) Yb[i][a] += dw[a] * v * Bb[c];
+                acc.v[3 * q + c][acc.t] += w * Bb[c];
             }
         }
+#pragma unroll
         for (int c = 0; c < 6; ++c) yb[c] += Yb[i][c];
     }
+#pragma unroll
     for (int c = 0; c < 6; ++c) lam[c] = yb[c];
 }
 
 template <class T, int LAYOUT>
 __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
     const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    __shared__ double acc_lds[24][64];
+    GradAccum acc{acc_lds, (int)threadIdx.x, 0xffffffffu, {0, 0, 0}};
+    double *col = a.segbuf + lane;
+    double *kdcol = a.segbuf + (int64_t)a.K * REC_SIZE * a.lanes + lane;
     for (;;) {
         unsigned long long q = atomicAdd(a.queue, 1ull);
         if (q >= (unsigned long long)a.n) break;
@@ -667,24 +766,33 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
         const double Lbar = a.gbar_time ? a.gbar_time[p] * SEC_PER_MPC : 0.0;
         const int64_t nseg = N > 0 ? (N + a.K - 1) / a.K : 0;
         for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-            const double *r = a.ckpt + 8 * (a.off[p] + seg);
+            const double *ck = a.ckpt + 8 * (a.off[p] + seg);
             Lane s;
-            for (int c = 0; c < 6; ++c) s.y[c] = r[c];
-            s.L = r[6];
-            s.hctrl = r[7];
+            for (int c = 0; c < 6; ++c) s.y[c] = ck[c];
+            s.L = ck[6];
+            s.hctrl = ck[7];
             s.kap = kap;
             const int m = (int)(seg == nseg - 1 ? N - seg * a.K : a.K);
-            replay_segment<T, LAYOUT>(a.F, a.P, s, m, a.segbuf, a.lanes, lane);
+            replay_segment<T, LAYOUT>(a.F, a.P, s, m, col, a.lanes);
+            const bool event = seg == nseg - 1 && (flags & CRP_TAPE_EVENT);
+            if (event) {
+                // record the last step again, taken to the located crossing s*
+                double *r = col + (int64_t)(m - 1) * REC_SIZE * a.lanes;
+                double y[6], y5[6], ex, eu;
+                for (int c = 0; c < 6; ++c) y[c] = r[(REC_Y + c) * a.lanes];
+                CellCache<T> cache;
+                cache_reset(cache, (T(*)[CACHE_BLOCK]) nullptr, 0);
+                ck_eval<T, LAYOUT, false, RecordWriter>(a.F, 0, cache, kap, y, fin[1], y5, ex, eu,
+                                                        RecordWriter{r, a.lanes});
+                r[REC_H * a.lanes] = fin[1];
+            }
             for (int j = m - 1; j >= 0; --j) {
-                const double *rj = a.segbuf + (int64_t)j * 7 * a.lanes + lane;
-                double y[6];
-                for (int c = 0; c < 6; ++c) y[c] = rj[c * a.lanes];
-                double h = rj[6 * a.lanes];
-                if (seg == nseg - 1 && j == m - 1 && (flags & CRP_TAPE_EVENT)) {
+                const double *r = col + (int64_t)j * REC_SIZE * a.lanes;
+                if (event && j == m - 1) {
                     // crossing: psi = zbar . Phi_s + Lbar, cotangent zbar - (psi / g_s) dg/dz
-                    const double sstar = fin[1];
                     double z[6], zs[6];
-                    ck_eval_ds<T, LAYOUT>(a.F, kap, y, sstar, z, zs);
+                    rec_output(kap, r, a.lanes, z);
+                    rec_output_ds<T, LAYOUT>(a.F, kap, r, a.lanes, kdcol, zs);
                     double zn = sqrt(z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
                     double u[3] = {z[3] / zn, z[4] / zn, z[5] / zn};
                     double lu = lam[3] * u[0] + lam[4] * u[1] + lam[5] * u[2];
@@ -696,13 +804,14 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
                         dg[c] = 2.0 * (z[c] - a.P.center[c]);
                         gs += dg[c] * zs[c];
                     }
-                    double comb[6] = {-(psi / gs) * dg[0], -(psi / gs) * dg[1], -(psi / gs) * dg[2], 0.0, 0.0, 0.0};
-                    step_vjp<T, LAYOUT>(a.F, kap, y, sstar, lam, comb, a.grad_field);
+                    double comb[3] = {-(psi / gs) * dg[0], -(psi / gs) * dg[1], -(psi / gs) * dg[2]};
+                    reverse_step<T, LAYOUT>(a.F, kap, r, a.lanes, lam, comb, acc, a.grad_field);
                 } else {
-                    step_vjp<T, LAYOUT>(a.F, kap, y, h, lam, nullptr, a.grad_field);
+                    reverse_step<T, LAYOUT>(a.F, kap, r, a.lanes, lam, nullptr, acc, a.grad_field);
                 }
             }
         }
+        grad_flush(a.F, acc, a.grad_field);
         // the direction entering the map: normalised on a fresh start
         if (flags & CRP_TAPE_FRESH) {
             double un = sqrt(u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2]);
