@@ -100,7 +100,7 @@ struct AdjArgs {
     int32_t pad_;
     const double *gbar_dir, *gbar_time;
     double *grad_u0, *grad_x0, *grad_field;
-    double *segbuf;                  // [step j][55][lane] replay records, then [36][lane] scratch
+    double *segbuf;                  // [step j][58][lane] replay records, then [36][lane] scratch
     int64_t lanes;                   // threads launched (segbuf stride)
     unsigned long long *queue;
     const int32_t *order;            // NULL: index order
@@ -108,8 +108,9 @@ struct AdjArgs {
 };
 
 // Adjoint replay record: doubles per accepted step (pre-step state 6, step 1,
-// stage states 30, stage fields 18), and the crossing-derivative scratch.
-constexpr int ADJ_RECORD_DOUBLES = 55;
+// stage states 30, stage fields 18, output direction 3), and the
+// crossing-derivative scratch.
+constexpr int ADJ_RECORD_DOUBLES = 58;
 constexpr int ADJ_SCRATCH_DOUBLES = 36;
 
 inline size_t adjoint_ws_bytes(int64_t n, int32_t K, int64_t lanes) {

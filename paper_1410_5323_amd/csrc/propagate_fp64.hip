@@ -427,10 +427,11 @@ hipError_t launch_layout(const PropArgs &a, int layout, bool multi, bool cache, 
 // natural-layout FP64 array with atomics.
 
 // Record of one accepted step, one column per thread (stride = lanes): the
-// pre-step state y (6), the step size (1), the stage states Y_1..Y_5 (30) and
-// the stage field values B_0..B_5 (18).
-constexpr int REC_Y = 0, REC_H = 6, REC_STAGE = 7, REC_FIELD = 37, REC_SIZE = ADJ_RECORD_DOUBLES;
-static_assert(REC_FIELD + 18 == REC_SIZE, "record layout");
+// pre-step state y (6), the step size (1), the stage states Y_1..Y_5 (30),
+// the stage field values B_0..B_5 (18) and the unnormalised output
+// direction (3).
+constexpr int REC_Y = 0, REC_H = 6, REC_STAGE = 7, REC_FIELD = 37, REC_ZU = 55, REC_SIZE = ADJ_RECORD_DOUBLES;
+static_assert(REC_ZU + 3 == REC_SIZE, "record layout");
 
 struct RecordWriter {
     double *r;       // field 0 of the record in this thread's column
@@ -468,58 +469,58 @@ __device__ __forceinline__ double stage_k(double kap, const double Y[6], const d
     }
 }
 
-// Replay m accepted steps from lane state s exactly as advance() takes them,
-// recording each accepted step.  buf: record 0 in this thread's column.
+// One attempt of the replay of a step from lane state s, exactly as advance()
+// takes it (the caller bids before a step's first attempt): one Cash-Karp
+// evaluation recorded at r (this thread's column), then either a rejection
+// (smaller step, returns false) or the acceptance (controller, normalisation,
+// the pre-step state and step size recorded; returns true).
 template <class T, int LAYOUT>
-__device__ void replay_segment(const FieldDev &F, const ParamsDev &P, Lane &s, int m, double *buf, int64_t stride) {
+__device__ bool replay_attempt(const FieldDev &F, const ParamsDev &P, Lane &s, double *r, int64_t stride) {
     CellCache<T> cache;
     cache_reset(cache, (T(*)[CACHE_BLOCK]) nullptr, 0);
-    for (int j = 0; j < m; ++j) {
-        bid(P, s);
-        const RecordWriter rec{buf + (int64_t)j * REC_SIZE * stride, stride};
-        double y5[6], ex, eu, err;
-        for (;;) {
-            ck_eval<T, LAYOUT, false, RecordWriter>(F, 0, cache, s.kap, s.y, s.h, y5, ex, eu, rec);
-            double exh = ex / s.h;
-            double em = eu > exh ? eu : exh;
-            err = em / P.tol;
-            if (err > 1.0 && s.h > P.h_min) {
-                double fac = 0.9 * (1.0 / sqrt(sqrt(err)));
-                if (fac < 0.1) fac = 0.1;
-                double h = s.h * fac;
-                if (h < P.h_min) h = P.h_min;
-                s.h = h;
-                s.binding = 0;
-                continue;
-            }
-            break;
-        }
-#pragma unroll
-        for (int c = 0; c < 6; ++c) rec.r[(REC_Y + c) * stride] = s.y[c];
-        rec.r[REC_H * stride] = s.h;
-        double g;
-        if (err > 1.0) {
-            g = 1.0;
-        } else if (err == 0.0) {
-            g = 5.0;
-        } else {
-            g = 0.9 * inv_fifth_root(err);
-            if (g > 5.0) g = 5.0;
-        }
-        double hc = s.h * g;
-        if (hc < P.h_min) hc = P.h_min;
-        if (hc > P.h_max) hc = P.h_max;
-        s.hctrl = hc;
-        double Lnew = s.binding ? P.l_max : s.L + s.h;
-        double un = sqrt(y5[3] * y5[3] + y5[4] * y5[4] + y5[5] * y5[5]);
-        s.y[0] = y5[0];
-        s.y[1] = y5[1];
-        s.y[2] = y5[2];
-        s.y[3] = y5[3] / un;
-        s.y[4] = y5[4] / un;
-        s.y[5] = y5[5] / un;
-        s.L = Lnew;
+    const RecordWriter rec{r, stride};
+    double y5[6], ex, eu;
+    ck_eval<T, LAYOUT, false, RecordWriter>(F, 0, cache, s.kap, s.y, s.h, y5, ex, eu, rec);
+    double exh = ex / s.h;
+    double em = eu > exh ? eu : exh;
+    double err = em / P.tol;
+    if (err > 1.0 && s.h > P.h_min) {
+        double fac = 0.9 * (1.0 / sqrt(sqrt(err)));
+        if (fac < 0.1) fac = 0.1;
+        double h = s.h * fac;
+        if (h < P.h_min) h = P.h_min;
+        s.h = h;
+        s.binding = 0;
+        return false;
     }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) r[(REC_Y + c) * stride] = s.y[c];
+    r[REC_H * stride] = s.h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[(REC_ZU + c) * stride] = y5[3 + c];
+    double g;
+    if (err > 1.0) {
+        g = 1.0;
+    } else if (err == 0.0) {
+        g = 5.0;
+    } else {
+        g = 0.9 * inv_fifth_root(err);
+        if (g > 5.0) g = 5.0;
+    }
+    double hc = s.h * g;
+    if (hc < P.h_min) hc = P.h_min;
+    if (hc > P.h_max) hc = P.h_max;
+    s.hctrl = hc;
+    double Lnew = s.binding ? P.l_max : s.L + s.h;
+    double un = sqrt(y5[3] * y5[3] + y5[4] * y5[4] + y5[5] * y5[5]);
+    s.y[0] = y5[0];
+    s.y[1] = y5[1];
+    s.y[2] = y5[2];
+    s.y[3] = y5[3] / un;
+    s.y[4] = y5[4] / un;
+    s.y[5] = y5[5] / un;
+    s.L = Lnew;
+    return true;
 }
 
 // Cell of X with its trilinear fractions and the cell's stored corner values.
@@ -682,7 +683,8 @@ __device__ void reverse_step(const FieldDev &F, double kap, const double *r, int
                              const double *comb, GradAccum &acc, double *gbar) {
     const double s = r[REC_H * stride];
     double z[6];
-    rec_output(kap, r, stride, z);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) z[3 + c] = r[(REC_ZU + c) * stride];
     const double zn = sqrt(z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
     const double u[3] = {z[3] / zn, z[4] / zn, z[5] / zn};
     const double lu = lam[3] * u[0] + lam[4] * u[1] + lam[5] * u[2];
@@ -729,7 +731,9 @@ __device__ void reverse_step(const FieldDev &F, double kap, const double *r, int
                 const double v = to_f64<T>(raw[q * 3 + c]) * F.value_scale;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) Yb[i][a] += dw[a] * v * Bb[c];
-                acc.v[3 * q + c][acc.t] += w * Bb[c];
+                // the lane owns its slot: an LDS add without return, no wait on a read
+                __hip_atomic_fetch_add(&acc.v[3 * q + c][acc.t], w * Bb[c], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
 #pragma unroll
@@ -739,6 +743,49 @@ __device__ void reverse_step(const FieldDev &F, double kap, const double *r, int
     for (int c = 0; c < 6; ++c) lam[c] = yb[c];
 }
 
+// Wavefront-wide maximum of a lane value (inactive lanes contribute 0).
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        int o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Adjoint state of the particle a lane works on.
+struct AdjLane {
+    int64_t p;        // particle, -1 none
+    int64_t N;        // accepted steps of the forward run
+    int64_t seg;      // segment being processed (from the last down to 0)
+    int flags;
+    double kap, Lbar;
+    double lam[6];    // cotangent of the state after the segment being processed
+};
+
+// Gradients of the lane's finished particle: the direction entering the map
+// is normalised on a fresh start.
+__device__ __forceinline__ void adj_finish(const AdjArgs &a, const AdjLane &L) {
+    const int64_t p = L.p;
+    if (L.flags & CRP_TAPE_FRESH) {
+        const double u0[3] = {a.ux0[p], a.uy0[p], a.uz0[p]};
+        double un = sqrt(u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2]);
+        double uh[3] = {u0[0] / un, u0[1] / un, u0[2] / un};
+        double lu = L.lam[3] * uh[0] + L.lam[4] * uh[1] + L.lam[5] * uh[2];
+        for (int c = 0; c < 3; ++c) a.grad_u0[3 * p + c] = (L.lam[3 + c] - lu * uh[c]) / un;
+    } else {
+        for (int c = 0; c < 3; ++c) a.grad_u0[3 * p + c] = L.lam[3 + c];
+    }
+    if (a.grad_x0)
+        for (int c = 0; c < 3; ++c) a.grad_x0[3 * p + c] = L.lam[c];
+}
+
+// One lane per particle; the lanes of a wavefront move through their
+// particles' segments in lockstep: every lane replays its current segment
+// (one attempt per loop iteration, lanes that are done idle), then every lane
+// sweeps its records in reverse, so no lane replays while another one is in
+// the reverse sweep.  Finished lanes take the next particle from a queue
+// ordered by step count, longest first.
 template <class T, int LAYOUT>
 __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
     const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -746,83 +793,107 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
     GradAccum acc{acc_lds, (int)threadIdx.x, 0xffffffffu, {0, 0, 0}};
     double *col = a.segbuf + lane;
     double *kdcol = a.segbuf + (int64_t)a.K * REC_SIZE * a.lanes + lane;
+    const int64_t rstride = (int64_t)REC_SIZE * a.lanes;  // doubles between consecutive records
+    AdjLane L;
+    L.p = -1;
+    bool exhausted = false;
     for (;;) {
-        unsigned long long q = atomicAdd(a.queue, 1ull);
-        if (q >= (unsigned long long)a.n) break;
-        const int64_t p = a.order ? (int64_t)a.order[q] : (int64_t)q;
-        const double *fin = a.fin + 4 * p;
-        const int flags = (int)fin[3];
-        const int64_t N = (int64_t)fin[0];
-        double u0[3] = {a.ux0[p], a.uy0[p], a.uz0[p]};
-        double lam[6] = {0.0, 0.0, 0.0, a.gbar_dir[3 * p], a.gbar_dir[3 * p + 1], a.gbar_dir[3 * p + 2]};
-        if (!(flags & CRP_TAPE_COMPLETE) || (flags & CRP_TAPE_OVERFLOW)) {
-            for (int c = 0; c < 3; ++c) {
-                a.grad_u0[3 * p + c] = 0.0;
-                if (a.grad_x0) a.grad_x0[3 * p + c] = 0.0;
+        // take particles until one needs a sweep (or the queue is empty)
+        while (L.p < 0 && !exhausted) {
+            unsigned long long q = atomicAdd(a.queue, 1ull);
+            if (q >= (unsigned long long)a.n) {
+                exhausted = true;
+                break;
             }
-            continue;
+            const int64_t p = a.order ? (int64_t)a.order[q] : (int64_t)q;
+            const double *fin = a.fin + 4 * p;
+            L.p = p;
+            L.flags = (int)fin[3];
+            L.N = (int64_t)fin[0];
+            for (int c = 0; c < 3; ++c) L.lam[c] = 0.0;
+            for (int c = 0; c < 3; ++c) L.lam[3 + c] = a.gbar_dir[3 * p + c];
+            if (!(L.flags & CRP_TAPE_COMPLETE) || (L.flags & CRP_TAPE_OVERFLOW)) {
+                for (int c = 0; c < 3; ++c) {
+                    a.grad_u0[3 * p + c] = 0.0;
+                    if (a.grad_x0) a.grad_x0[3 * p + c] = 0.0;
+                }
+                L.p = -1;
+                continue;
+            }
+            if (L.N == 0) {
+                adj_finish(a, L);
+                L.p = -1;
+                continue;
+            }
+            L.kap = ((double)a.charge[p] * K_LORENTZ) / a.energy[p];
+            L.Lbar = a.gbar_time ? a.gbar_time[p] * SEC_PER_MPC : 0.0;
+            L.seg = (L.N + a.K - 1) / a.K - 1;
         }
-        const double kap = ((double)a.charge[p] * K_LORENTZ) / a.energy[p];
-        const double Lbar = a.gbar_time ? a.gbar_time[p] * SEC_PER_MPC : 0.0;
-        const int64_t nseg = N > 0 ? (N + a.K - 1) / a.K : 0;
-        for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-            const double *ck = a.ckpt + 8 * (a.off[p] + seg);
-            Lane s;
+        const bool busy = L.p >= 0;
+        if (__ballot(busy) == 0ull) break;
+
+        // replay the current segment from its checkpoint
+        const int64_t nseg = busy ? (L.N + a.K - 1) / a.K : 0;
+        const int m = busy ? (int)(L.seg == nseg - 1 ? L.N - L.seg * a.K : a.K) : 0;
+        const bool event = busy && L.seg == nseg - 1 && (L.flags & CRP_TAPE_EVENT);
+        Lane s;
+        if (busy) {
+            const double *ck = a.ckpt + 8 * (a.off[L.p] + L.seg);
             for (int c = 0; c < 6; ++c) s.y[c] = ck[c];
             s.L = ck[6];
             s.hctrl = ck[7];
-            s.kap = kap;
-            const int m = (int)(seg == nseg - 1 ? N - seg * a.K : a.K);
-            replay_segment<T, LAYOUT>(a.F, a.P, s, m, col, a.lanes);
-            const bool event = seg == nseg - 1 && (flags & CRP_TAPE_EVENT);
-            if (event) {
-                // record the last step again, taken to the located crossing s*
-                double *r = col + (int64_t)(m - 1) * REC_SIZE * a.lanes;
-                double y[6], y5[6], ex, eu;
-                for (int c = 0; c < 6; ++c) y[c] = r[(REC_Y + c) * a.lanes];
-                CellCache<T> cache;
-                cache_reset(cache, (T(*)[CACHE_BLOCK]) nullptr, 0);
-                ck_eval<T, LAYOUT, false, RecordWriter>(a.F, 0, cache, kap, y, fin[1], y5, ex, eu,
-                                                        RecordWriter{r, a.lanes});
-                r[REC_H * a.lanes] = fin[1];
+            s.kap = L.kap;
+        }
+        // one attempt per loop iteration, so a lane's rejections cost the others nothing
+        int j = 0;
+        if (m > 0) bid(a.P, s);
+        while (__ballot(j < m) != 0ull) {
+            if (j < m && replay_attempt<T, LAYOUT>(a.F, a.P, s, col + (int64_t)j * rstride, a.lanes))
+                if (++j < m) bid(a.P, s);
+        }
+        const int mmax = wave_max(m);
+        if (event) {
+            // record the last step again, taken to the located crossing s*
+            double *r = col + (int64_t)(m - 1) * rstride;
+            const double sstar = a.fin[4 * L.p + 1];
+            double y[6], y5[6], ex, eu;
+            for (int c = 0; c < 6; ++c) y[c] = r[(REC_Y + c) * a.lanes];
+            CellCache<T> cache;
+            cache_reset(cache, (T(*)[CACHE_BLOCK]) nullptr, 0);
+            ck_eval<T, LAYOUT, false, RecordWriter>(a.F, 0, cache, L.kap, y, sstar, y5, ex, eu,
+                                                    RecordWriter{r, a.lanes});
+            r[REC_H * a.lanes] = sstar;
+            for (int c = 0; c < 3; ++c) r[(REC_ZU + c) * a.lanes] = y5[3 + c];
+            // crossing: psi = zbar . Phi_s + Lbar, cotangent zbar - (psi / g_s) dg/dz
+            double z[6], zs[6];
+            rec_output(L.kap, r, a.lanes, z);
+            rec_output_ds<T, LAYOUT>(a.F, L.kap, r, a.lanes, kdcol, zs);
+            double zn = sqrt(z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
+            double u[3] = {z[3] / zn, z[4] / zn, z[5] / zn};
+            double lu = L.lam[3] * u[0] + L.lam[4] * u[1] + L.lam[5] * u[2];
+            double zb[6] = {L.lam[0], L.lam[1], L.lam[2], (L.lam[3] - lu * u[0]) / zn, (L.lam[4] - lu * u[1]) / zn,
+                            (L.lam[5] - lu * u[2]) / zn};
+            double psi = L.Lbar, gs = 0.0, dg[3];
+            for (int c = 0; c < 6; ++c) psi += zb[c] * zs[c];
+            for (int c = 0; c < 3; ++c) {
+                dg[c] = 2.0 * (z[c] - a.P.center[c]);
+                gs += dg[c] * zs[c];
             }
-            for (int j = m - 1; j >= 0; --j) {
-                const double *r = col + (int64_t)j * REC_SIZE * a.lanes;
-                if (event && j == m - 1) {
-                    // crossing: psi = zbar . Phi_s + Lbar, cotangent zbar - (psi / g_s) dg/dz
-                    double z[6], zs[6];
-                    rec_output(kap, r, a.lanes, z);
-                    rec_output_ds<T, LAYOUT>(a.F, kap, r, a.lanes, kdcol, zs);
-                    double zn = sqrt(z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
-                    double u[3] = {z[3] / zn, z[4] / zn, z[5] / zn};
-                    double lu = lam[3] * u[0] + lam[4] * u[1] + lam[5] * u[2];
-                    double zb[6] = {lam[0], lam[1], lam[2], (lam[3] - lu * u[0]) / zn, (lam[4] - lu * u[1]) / zn,
-                                    (lam[5] - lu * u[2]) / zn};
-                    double psi = Lbar, gs = 0.0, dg[3];
-                    for (int c = 0; c < 6; ++c) psi += zb[c] * zs[c];
-                    for (int c = 0; c < 3; ++c) {
-                        dg[c] = 2.0 * (z[c] - a.P.center[c]);
-                        gs += dg[c] * zs[c];
-                    }
-                    double comb[3] = {-(psi / gs) * dg[0], -(psi / gs) * dg[1], -(psi / gs) * dg[2]};
-                    reverse_step<T, LAYOUT>(a.F, kap, r, a.lanes, lam, comb, acc, a.grad_field);
-                } else {
-                    reverse_step<T, LAYOUT>(a.F, kap, r, a.lanes, lam, nullptr, acc, a.grad_field);
-                }
+            double comb[3] = {-(psi / gs) * dg[0], -(psi / gs) * dg[1], -(psi / gs) * dg[2]};
+            reverse_step<T, LAYOUT>(a.F, L.kap, r, a.lanes, L.lam, comb, acc, a.grad_field);
+        }
+        // reverse sweep (the crossing step, if any, is done above)
+        const int mrev = event ? m - 1 : m;
+        for (int j = mmax - 1; j >= 0; --j)
+            if (j < mrev) reverse_step<T, LAYOUT>(a.F, L.kap, col + (int64_t)j * rstride, a.lanes, L.lam, nullptr, acc,
+                                                  a.grad_field);
+        if (busy) {
+            if (--L.seg < 0) {
+                grad_flush(a.F, acc, a.grad_field);
+                adj_finish(a, L);
+                L.p = -1;
             }
         }
-        grad_flush(a.F, acc, a.grad_field);
-        // the direction entering the map: normalised on a fresh start
-        if (flags & CRP_TAPE_FRESH) {
-            double un = sqrt(u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2]);
-            double uh[3] = {u0[0] / un, u0[1] / un, u0[2] / un};
-            double lu = lam[3] * uh[0] + lam[4] * uh[1] + lam[5] * uh[2];
-            for (int c = 0; c < 3; ++c) a.grad_u0[3 * p + c] = (lam[3 + c] - lu * uh[c]) / un;
-        } else {
-            for (int c = 0; c < 3; ++c) a.grad_u0[3 * p + c] = lam[3 + c];
-        }
-        if (a.grad_x0)
-            for (int c = 0; c < 3; ++c) a.grad_x0[3 * p + c] = lam[c];
     }
 }
 
