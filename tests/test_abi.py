@@ -134,3 +134,43 @@ def test_selftest_rejects_bad_op(crp):
     L = crp.lib()
     assert L.crp_selftest_arith(0x1000, 0x2000, 4, 99, None) == crp.CRP_ERR_INVALID
     assert L.crp_selftest_arith(None, None, 4, 0, None) == crp.CRP_ERR_INVALID
+
+
+def test_tape_and_adjoint_reject_bad_arguments_without_device(crp):
+    L = crp.lib()
+    f = _field(crp)
+    f.data = 0x1000
+    farr = (crp.crp_field * 1)(f)
+    p = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0)
+    parr = (crp.crp_params * 1)(p)
+    parts = crp.crp_particles(**{k: 0x2000 for k in crp._PARTICLE_FIELDS})
+    tape = crp.crp_tape(0x3000, 0x4000, 0x5000, 64, 0)
+
+    def prop(t, prec=0):
+        return L.crp_propagate(farr, 1, parr, 1, C.byref(parts), 10, C.byref(t), prec, None, None, None, 0, None)
+
+    assert prop(crp.crp_tape(0x3000, 0x4000, 0x5000, 0, 0)) == crp.CRP_ERR_INVALID
+    assert prop(crp.crp_tape(0x3000, 0x4000, 0x5000, 5000, 0)) == crp.CRP_ERR_INVALID
+    assert prop(crp.crp_tape(None, 0x4000, 0x5000, 64, 0)) == crp.CRP_ERR_INVALID
+    assert prop(tape, prec=crp.CRP_PREC_MIXED_F64ACC) == crp.CRP_ERR_UNSUPPORTED
+    assert prop(tape) == crp.CRP_ERR_WORKSPACE  # arguments fine, no workspace
+
+    assert crp.crp_adjoint_workspace_bytes(-1, 64) == 0
+    assert crp.crp_adjoint_workspace_bytes(100, 0) == 0
+    assert crp.crp_adjoint_workspace_bytes(1000, 64) > crp.crp_adjoint_workspace_bytes(1000, 8) > 0
+
+    def adj(field=f, params=p, t=tape, n=10, g=0x6000, gu=0x7000, gf=0x8000, ws=None, wsb=0):
+        return L.crp_propagate_adjoint(C.byref(field), C.byref(params), C.byref(parts), n, C.byref(t), g, None, None,
+                                       gu, None, gf, ws, wsb, None)
+
+    assert adj(n=-1) == crp.CRP_ERR_INVALID
+    assert adj(t=crp.crp_tape(0x3000, 0x4000, 0x5000, 0, 0)) == crp.CRP_ERR_INVALID
+    assert adj(g=None) == crp.CRP_ERR_INVALID
+    assert adj(gu=None) == crp.CRP_ERR_INVALID
+    assert adj(gf=None) == crp.CRP_ERR_INVALID
+    half = _field(crp, dtype=crp.CRP_F16)
+    half.data = 0x1000
+    assert adj(field=half) == crp.CRP_ERR_UNSUPPORTED
+    assert adj(params=crp.make_params(0.0, 0.01, 1.0, l_max=10.0)) == crp.CRP_ERR_INVALID
+    assert adj() == crp.CRP_ERR_WORKSPACE
+    assert adj(n=0) == crp.CRP_OK
