@@ -115,28 +115,33 @@ typedef struct {
     int64_t *n_rejected;      /* in/out rejected attempts (cumulative) */
 } crp_particles;
 
-/* Tape of a forward run for the adjoint (checkpointed replay).  The forward
- * kernel writes, per particle i, a checkpoint record every K accepted steps
- * into checkpoints[offsets[i] + c] (c = 0 is the state at the start of the
- * call): 8 doubles (x, y, z, ux, uy, uz, length, controller bid).  Particle i
- * needs ceil(N_i / K) + 1 records for N_i accepted steps; a particle that
- * runs out sets the overflow flag.  For every particle it writes finals[4 i ..]:
- * accepted steps N, the located crossing step s* (0 without one), the last
- * accepted step size, and flags (CRP_TAPE_* bits, stored as a double); all
- * zero for a particle that was not ACTIVE on entry or did not complete.
+/* Tape of a forward run for the adjoint (checkpointed replay).  Every K
+ * accepted steps (and at the start of the call) the forward kernel takes the
+ * next record of a shared pool (an atomic on *head) and writes the
+ * particle's state into it: 8 doubles (x, y, z, ux, uy, uz, length,
+ * controller bid), with links[record] = the particle's previous record (-1
+ * for its first).  The head keeps counting past the capacity, so after a run
+ * it holds the number of records the run needed; a particle that found the
+ * pool exhausted sets the overflow flag.  For every particle the kernel writes
+ * finals[4 i ..]: accepted steps N, the located crossing step s* (0 without
+ * one), the index of its last record (as a double, -1 for none) and flags
+ * (CRP_TAPE_* bits, as a double); all zero (last record -1) for a particle
+ * that was not ACTIVE on entry.  The caller zeroes *head before the call.
  * The tape is valid only for crp_propagate_adjoint on the same particles,
  * field and parameters. */
 typedef struct {
-    double *checkpoints;      /* [dev] pool of 8-double records */
-    const int64_t *offsets;   /* [dev] n + 1 record offsets */
-    double *finals;           /* [dev] 4 n doubles */
-    int32_t every_k;          /* checkpoint interval K, 1 .. 4096 */
+    double *checkpoints;          /* [dev] capacity records of 8 doubles */
+    int64_t *links;               /* [dev] capacity previous-record indices */
+    unsigned long long *head;     /* [dev] records handed out (caller zeroes) */
+    double *finals;               /* [dev] 4 n doubles */
+    int64_t capacity;             /* records in the pool, >= 1 */
+    int32_t every_k;              /* checkpoint interval K, 1 .. 4096 */
     int32_t reserved;
 } crp_tape;
 
 enum {
     CRP_TAPE_EVENT = 1,       /* ended by a located sphere crossing */
-    CRP_TAPE_OVERFLOW = 2,    /* more checkpoints than records: no adjoint */
+    CRP_TAPE_OVERFLOW = 2,    /* the record pool ran out: no adjoint */
     CRP_TAPE_FRESH = 4,       /* started fresh (direction normalised on entry) */
     CRP_TAPE_COMPLETE = 8     /* ended ARRIVED or MAX_LENGTH in this call */
 };

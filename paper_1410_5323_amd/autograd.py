@@ -9,11 +9,10 @@ position and the grid values.
 
 The derivative is that of the replayed map: the accepted step sizes of the
 forward run are held fixed and the sphere crossing of the last step is
-differentiated through its defining equation.  The forward runs twice: once
-to count each particle's accepted steps (which sizes its checkpoint
-records), then again recording a checkpoint every ``every_k`` accepted steps.
-The backward pass replays each segment from its checkpoint on the GPU and
-sweeps it in reverse.  The energy is unchanged by the propagation, so its
+differentiated through its defining equation.  The forward records a
+checkpoint every ``every_k`` accepted steps into a pool of records (run a
+second time only if the pool was too small).  The backward pass replays each
+segment from its checkpoint on the GPU and sweeps it in reverse.  The energy is unchanged by the propagation, so its
 cotangent contributes nothing; no gradient with respect to the input energy
 is computed (asking for one raises).
 """
@@ -40,7 +39,7 @@ def _initial_state(u0, x0, energy, charge):
 
 class PropagateFunction(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, u0, grid, x0, energy, charge, spacing, origin, params, layout, every_k):
+    def forward(ctx, u0, grid, x0, energy, charge, spacing, origin, params, layout, every_k, tape_capacity):
         if ctx.needs_input_grad[3]:
             raise NotImplementedError("no gradient with respect to the particle energy")
         if u0.dtype != torch.float64 or x0.dtype != torch.float64 or energy.dtype != torch.float64:
@@ -51,12 +50,14 @@ class PropagateFunction(torch.autograd.Function):
         field = crp.make_field(grid.detach(), spacing, origin=origin, dtype=dt, layout=layout)
         u0d, x0d, charge = u0.detach(), x0.detach(), charge.to(torch.int32)
         init = _initial_state(u0d, x0d, energy.detach(), charge)
-        probe = crp.clone_particles(init)
-        crp.crp_propagate([field], [params], probe)
-        tape = crp.Tape(probe["n_accepted"], every_k=every_k, device=u0.device)
-        del probe
+        n = u0.shape[0]
+        tape = crp.Tape(n, every_k=every_k, capacity=tape_capacity, device=u0.device)
         st = crp.clone_particles(init)
         crp.crp_propagate([field], [params], st, tape=tape)
+        if tape.overflowed():  # run again with exactly the records the run asked for
+            tape = crp.Tape(n, every_k=every_k, capacity=tape.records_needed(), device=u0.device)
+            st = crp.clone_particles(init)
+            crp.crp_propagate([field], [params], st, tape=tape)
         ctx.field, ctx.params, ctx.init, ctx.tape = field, params, init, tape
         ctx.grid_shape, ctx.grid_dtype = tuple(grid.shape), grid.dtype
         direction = torch.stack([st["ux"], st["uy"], st["uz"]], dim=1)
@@ -79,11 +80,11 @@ class PropagateFunction(torch.autograd.Function):
         gu = grad_u0 if ctx.needs_input_grad[0] else None
         gg = grad_field.to(ctx.grid_dtype) if ctx.needs_input_grad[1] else None
         gx = grad_x0 if ctx.needs_input_grad[2] else None
-        return gu, gg, gx, None, None, None, None, None, None, None
+        return gu, gg, gx, None, None, None, None, None, None, None, None
 
 
 def propagate(u0, grid, x0, energy, charge, spacing: float, params, layout: str = "linear", every_k: int = 64,
-              origin=(0.0, 0.0, 0.0)):
+              origin=(0.0, 0.0, 0.0), tape_capacity: int | None = None):
     """Differentiable propagation of n particles from a fresh start.
 
     u0, x0: (n, 3) float64 device tensors (direction need not be normalised;
@@ -92,6 +93,8 @@ def propagate(u0, grid, x0, energy, charge, spacing: float, params, layout: str 
     ``origin``; energy: (n,) float64
     eV; charge: (n,) integer charge numbers; params: a crp_params.
     Returns (direction (n, 3), time (n,) s, energy (n,) eV, status (n,)).
+    tape_capacity: checkpoint records to allocate (default 64 per particle);
+    a run that needs more is repeated once with the exact number.
     """
     return PropagateFunction.apply(u0, grid, x0, energy, charge, float(spacing), tuple(float(o) for o in origin),
-                                   params, layout, int(every_k))
+                                   params, layout, int(every_k), tape_capacity)

@@ -54,8 +54,8 @@ class crp_particles(C.Structure):
 
 
 class crp_tape(C.Structure):
-    _fields_ = [("checkpoints", C.c_void_p), ("offsets", C.c_void_p), ("finals", C.c_void_p),
-                ("every_k", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("checkpoints", C.c_void_p), ("links", C.c_void_p), ("head", C.c_void_p), ("finals", C.c_void_p),
+                ("capacity", C.c_int64), ("every_k", C.c_int32), ("reserved", C.c_int32)]
 
 
 CRP_TAPE_EVENT, CRP_TAPE_OVERFLOW, CRP_TAPE_FRESH, CRP_TAPE_COMPLETE = 1, 2, 4, 8
@@ -168,22 +168,43 @@ def crp_field_upload(desc: crp_field, src, stream=None):
 
 
 class Tape:
-    """Device tape of a forward run: checkpoints every `every_k` accepted steps."""
+    """Device tape of a forward run: a pool of `capacity` checkpoint records,
+    taken every `every_k` accepted steps, plus per-particle finals."""
 
-    def __init__(self, n_accepted, every_k: int = 64, device="cuda"):
+    def __init__(self, n: int, every_k: int = 64, capacity: int | None = None, device="cuda"):
         torch = _torch()
-        per = (n_accepted.to(torch.int64) + every_k - 1) // every_k + 1
-        self.offsets = torch.zeros(len(per) + 1, dtype=torch.int64, device=device)
-        self.offsets[1:] = torch.cumsum(per, 0)
-        total = int(self.offsets[-1].item())
-        self.checkpoints = torch.empty(max(total, 1) * 8, dtype=torch.float64, device=device)
-        self.finals = torch.zeros(4 * len(per), dtype=torch.float64, device=device)
+        n = int(n)
+        self.capacity = int(capacity) if capacity is not None else 64 * n + 1024
+        if self.capacity < 1:
+            raise ValueError("a tape needs at least one record")
+        self.checkpoints = torch.empty(self.capacity * 8, dtype=torch.float64, device=device)
+        self.links = torch.empty(self.capacity, dtype=torch.int64, device=device)
+        self.head = torch.zeros(1, dtype=torch.int64, device=device)
+        self.finals = torch.zeros(4 * n, dtype=torch.float64, device=device)
         self.every_k = int(every_k)
-        self.desc = crp_tape(self.checkpoints.data_ptr(), self.offsets.data_ptr(), self.finals.data_ptr(),
-                             self.every_k, 0)
+        self.desc = crp_tape(self.checkpoints.data_ptr(), self.links.data_ptr(), self.head.data_ptr(),
+                             self.finals.data_ptr(), self.capacity, self.every_k, 0)
+
+    def reset(self):
+        """Zero the pool head before recording another run into this tape."""
+        self.head.zero_()
+
+    def records_needed(self) -> int:
+        """Records the last run asked for (more than capacity after an overflow)."""
+        return int(self.head.item())
+
+    def overflowed(self) -> bool:
+        return self.records_needed() > self.capacity
 
     def flags(self):
         return self.finals.view(-1, 4)[:, 3].to(_torch().int32)
+
+    def steps(self):
+        return self.finals.view(-1, 4)[:, 0].to(_torch().int64)
+
+    @property
+    def nbytes(self) -> int:
+        return self.capacity * 72 + self.finals.numel() * 8 + 8
 
 
 def crp_propagate(fields, params, particles: dict, precision=CRP_PREC_FP64, tuning=None,

@@ -210,7 +210,8 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
         if (precision != CRP_PREC_FP64) return fail(CRP_ERR_UNSUPPORTED, "%s: a tape needs FP64 precision", fn);
         if (tape->every_k < 1 || tape->every_k > 4096)
             return fail(CRP_ERR_INVALID, "%s: tape interval must be in [1, 4096]", fn);
-        if (n > 0 && (!tape->checkpoints || !tape->offsets || !tape->finals))
+        if (tape->capacity < 1) return fail(CRP_ERR_INVALID, "%s: the tape needs at least one record", fn);
+        if (n > 0 && (!tape->head || !tape->finals || !tape->checkpoints || !tape->links))
             return fail(CRP_ERR_INVALID, "%s: tape arrays must not be null", fn);
     }
     crp_tuning t = {256, 4, 32, 1, 0, 0, 0, 0};
@@ -279,8 +280,10 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
     a.refill_threshold = t.refill_threshold;
     a.n_params = n_params;
     a.tape_ckpt = tape ? tape->checkpoints : nullptr;
-    a.tape_off = tape ? tape->offsets : nullptr;
+    a.tape_link = tape ? tape->links : nullptr;
+    a.tape_head = tape ? tape->head : nullptr;
     a.tape_fin = tape ? tape->finals : nullptr;
+    a.tape_cap = tape ? tape->capacity : 0;
     a.tape_k = tape ? tape->every_k : 1;
 
     int64_t need_blocks = (n + t.block_size - 1) / t.block_size;
@@ -322,8 +325,9 @@ crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *param
     if (n < 0 || n > (int64_t)0x7fffffff) return fail(CRP_ERR_INVALID, "%s: n out of range", fn);
     if (tape->every_k < 1 || tape->every_k > 4096) return fail(CRP_ERR_INVALID, "%s: bad tape interval", fn);
     if (n == 0) return ok();
-    if (!initial->ux || !initial->uy || !initial->uz || !initial->energy || !initial->charge || !tape->checkpoints ||
-        !tape->offsets || !tape->finals || !gbar_dir || !grad_u0 || !grad_field)
+    if (tape->capacity < 1) return fail(CRP_ERR_INVALID, "%s: the tape needs at least one record", fn);
+    if (!initial->ux || !initial->uy || !initial->uz || !initial->energy || !initial->charge || !tape->finals ||
+        !tape->checkpoints || !tape->links || !gbar_dir || !grad_u0 || !grad_field)
         return fail(CRP_ERR_INVALID, "%s: a required array is null", fn);
     int64_t lanes = adjoint_lanes(n);
     size_t need = crp::adjoint_ws_bytes(n, tape->every_k, lanes);
@@ -348,8 +352,9 @@ crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *param
     a.energy = initial->energy;
     a.charge = initial->charge;
     a.ckpt = tape->checkpoints;
-    a.off = tape->offsets;
+    a.link = tape->links;
     a.fin = tape->finals;
+    a.cap = tape->capacity;
     a.K = tape->every_k;
     a.gbar_dir = gbar_dir;
     a.gbar_time = gbar_time;

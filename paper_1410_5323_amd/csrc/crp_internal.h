@@ -79,9 +79,11 @@ struct PropArgs {
     const int32_t *order;            // NULL: particles in index order
     unsigned long long *queue;       // work-queue head
     unsigned long long *counters;    // NULL or CRP_NCOUNTERS accumulators
-    double *tape_ckpt;               // NULL: no tape; else 8-double checkpoint records
-    const int64_t *tape_off;         // n + 1 record offsets
+    double *tape_ckpt;               // NULL: no tape; else the pool of 8-double records
+    int64_t *tape_link;              // previous record of the same particle
+    unsigned long long *tape_head;   // pool head
     double *tape_fin;                // 4 doubles per particle
+    int64_t tape_cap;                // records in the pool
     int32_t tape_k;                  // checkpoint interval
     int32_t refill_threshold;
     int32_t n_params;
@@ -94,8 +96,9 @@ struct AdjArgs {
     const double *x0, *y0, *z0, *ux0, *uy0, *uz0, *energy;
     const int32_t *charge;
     const double *ckpt;
-    const int64_t *off;
+    const int64_t *link;
     const double *fin;
+    int64_t cap;
     int32_t K;
     int32_t pad_;
     const double *gbar_dir, *gbar_time;

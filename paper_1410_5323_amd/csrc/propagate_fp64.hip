@@ -31,16 +31,19 @@ struct Lane {
     int32_t dacc, drej;   // accepted / rejected attempts of this call
     int32_t mode, binding, pidx;
     int32_t tflags;       // tape flags of this particle (fresh start, overflow)
+    int64_t tlast;        // the particle's last tape record, -1 none
 };
 
-// Tape: checkpoint c of particle p (state before accepted step c*K).
-__device__ __forceinline__ void tape_checkpoint(const PropArgs &a, int64_t p, Lane &s, int64_t c) {
-    int64_t base = a.tape_off[p], cap = a.tape_off[p + 1] - base;
-    if (c >= cap) {
+// Tape: take the next record of the pool for the lane's current state (the
+// state before its next accepted step) and link it to the particle's previous
+// record.
+__device__ __forceinline__ void tape_checkpoint(const PropArgs &a, Lane &s) {
+    const unsigned long long slot = atomicAdd(a.tape_head, 1ull);
+    if (slot >= (unsigned long long)a.tape_cap) {
         s.tflags |= CRP_TAPE_OVERFLOW;
         return;
     }
-    double *r = a.tape_ckpt + 8 * (base + c);
+    double *r = a.tape_ckpt + 8 * (int64_t)slot;
     r[0] = s.y[0];
     r[1] = s.y[1];
     r[2] = s.y[2];
@@ -49,14 +52,15 @@ __device__ __forceinline__ void tape_checkpoint(const PropArgs &a, int64_t p, La
     r[5] = s.y[5];
     r[6] = s.L;
     r[7] = s.hctrl;
+    a.tape_link[slot] = s.tlast;
+    s.tlast = (int64_t)slot;
 }
 
-__device__ __forceinline__ void tape_final(const PropArgs &a, int64_t p, const Lane &s, double sstar, double hlast,
-                                           int flags) {
+__device__ __forceinline__ void tape_final(const PropArgs &a, int64_t p, const Lane &s, double sstar, int flags) {
     double *f = a.tape_fin + 4 * p;
     f[0] = (double)s.dacc;
     f[1] = sstar;
-    f[2] = hlast;
+    f[2] = (double)s.tlast;
     f[3] = (double)(s.tflags | flags);
 }
 
@@ -135,8 +139,10 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
     int st = a.status[p];
     if (a.tape_ckpt) {
         double *f = a.tape_fin + 4 * p;  // overwritten when the particle completes
-        f[0] = f[1] = f[2] = f[3] = 0.0;
+        f[0] = f[1] = f[3] = 0.0;
+        f[2] = -1.0;
     }
+    s.tlast = -1;
     if (st != CRP_ST_ACTIVE) return false;
     s.pidx = MULTI && a.param_index ? a.param_index[p] : 0;
     if (MULTI && (s.pidx < 0 || s.pidx >= a.n_params)) {
@@ -177,18 +183,18 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
     s.tflags = hn == 0.0 ? CRP_TAPE_FRESH : 0;
     if (P.sphere_on && sphere_g(P, s.y) >= 0.0) {
         store(a, p, s, hn, CRP_ST_ARRIVED);
-        if (a.tape_ckpt) tape_final(a, p, s, 0.0, 0.0, CRP_TAPE_COMPLETE);
+        if (a.tape_ckpt) tape_final(a, p, s, 0.0, CRP_TAPE_COMPLETE);
         return false;
     }
     if (P.lmax_on && s.L >= P.l_max) {
         store(a, p, s, hn, CRP_ST_MAX_LENGTH);
-        if (a.tape_ckpt) tape_final(a, p, s, 0.0, 0.0, CRP_TAPE_COMPLETE);
+        if (a.tape_ckpt) tape_final(a, p, s, 0.0, CRP_TAPE_COMPLETE);
         return false;
     }
     s.hctrl = hn == 0.0 ? P.h_max : hn;
     s.kap = ((double)Z * K_LORENTZ) / E;
     s.mode = MODE_NORMAL;
-    if (a.tape_ckpt) tape_checkpoint(a, p, s, 0);
+    if (a.tape_ckpt) tape_checkpoint(a, s);
     bid(P, s);
     return true;
 }
@@ -210,7 +216,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
         double exh = ex / s.h;
         if (!isfinite(eu) || !isfinite(exh)) {
             store(a, p, s, s.hctrl, CRP_ST_NONFINITE);
-            if (a.tape_ckpt) tape_final(a, p, s, 0.0, 0.0, 0);
+            if (a.tape_ckpt) tape_final(a, p, s, 0.0, 0);
             return CRP_ST_NONFINITE;
         }
         double em = eu > exh ? eu : exh;
@@ -267,15 +273,15 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
         s.L = Lnew;
         if (P.lmax_on && s.L >= P.l_max) {
             store(a, p, s, s.hctrl, CRP_ST_MAX_LENGTH);
-            if (a.tape_ckpt) tape_final(a, p, s, 0.0, s.h, CRP_TAPE_COMPLETE);
+            if (a.tape_ckpt) tape_final(a, p, s, 0.0, CRP_TAPE_COMPLETE);
             return CRP_ST_MAX_LENGTH;
         }
         if (P.max_steps > 0 && s.dacc >= P.max_steps) {
             store(a, p, s, s.hctrl, CRP_ST_MAX_STEPS);
-            if (a.tape_ckpt) tape_final(a, p, s, 0.0, s.h, 0);
+            if (a.tape_ckpt) tape_final(a, p, s, 0.0, 0);
             return CRP_ST_MAX_STEPS;
         }
-        if (a.tape_ckpt && s.dacc % a.tape_k == 0) tape_checkpoint(a, p, s, s.dacc / a.tape_k);
+        if (a.tape_ckpt && s.dacc % a.tape_k == 0) tape_checkpoint(a, s);
         bid(P, s);
         return CRP_ST_ACTIVE;
     }
@@ -285,7 +291,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
         double gs = sphere_g(P, y5);
         if (!isfinite(gs)) {
             store(a, p, s, s.hctrl, CRP_ST_NONFINITE);
-            if (a.tape_ckpt) tape_final(a, p, s, 0.0, 0.0, 0);
+            if (a.tape_ckpt) tape_final(a, p, s, 0.0, 0);
             return CRP_ST_NONFINITE;
         }
         if (gs >= 0.0) {
@@ -314,7 +320,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
     s.y[5] = y5[5] / sn;
     s.L = e.hi[t] == e.hacc[t] ? e.lacc[t] : s.L + e.hi[t];
     store(a, p, s, s.hctrl, CRP_ST_ARRIVED);
-    if (a.tape_ckpt) tape_final(a, p, s, e.hi[t], e.hacc[t], CRP_TAPE_COMPLETE | CRP_TAPE_EVENT);
+    if (a.tape_ckpt) tape_final(a, p, s, e.hi[t], CRP_TAPE_COMPLETE | CRP_TAPE_EVENT);
     return CRP_ST_ARRIVED;
 }
 
@@ -758,6 +764,7 @@ struct AdjLane {
     int64_t p;        // particle, -1 none
     int64_t N;        // accepted steps of the forward run
     int64_t seg;      // segment being processed (from the last down to 0)
+    int64_t slot;     // tape record of that segment's first state
     int flags;
     double kap, Lbar;
     double lam[6];    // cotangent of the state after the segment being processed
@@ -825,6 +832,15 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
                 L.p = -1;
                 continue;
             }
+            L.slot = (int64_t)fin[2];
+            if (L.slot < 0 || L.slot >= a.cap) {  // no record although steps were taken: no adjoint
+                for (int c = 0; c < 3; ++c) {
+                    a.grad_u0[3 * p + c] = 0.0;
+                    if (a.grad_x0) a.grad_x0[3 * p + c] = 0.0;
+                }
+                L.p = -1;
+                continue;
+            }
             L.kap = ((double)a.charge[p] * K_LORENTZ) / a.energy[p];
             L.Lbar = a.gbar_time ? a.gbar_time[p] * SEC_PER_MPC : 0.0;
             L.seg = (L.N + a.K - 1) / a.K - 1;
@@ -838,7 +854,7 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
         const bool event = busy && L.seg == nseg - 1 && (L.flags & CRP_TAPE_EVENT);
         Lane s;
         if (busy) {
-            const double *ck = a.ckpt + 8 * (a.off[L.p] + L.seg);
+            const double *ck = a.ckpt + 8 * L.slot;
             for (int c = 0; c < 6; ++c) s.y[c] = ck[c];
             s.L = ck[6];
             s.hctrl = ck[7];
@@ -892,6 +908,16 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
                 grad_flush(a.F, acc, a.grad_field);
                 adj_finish(a, L);
                 L.p = -1;
+            } else {
+                L.slot = a.link[L.slot];
+                if (L.slot < 0 || L.slot >= a.cap) {  // a broken chain: no adjoint for this particle
+                    grad_flush(a.F, acc, a.grad_field);
+                    for (int c = 0; c < 3; ++c) {
+                        a.grad_u0[3 * L.p + c] = 0.0;
+                        if (a.grad_x0) a.grad_x0[3 * L.p + c] = 0.0;
+                    }
+                    L.p = -1;
+                }
             }
         }
     }

@@ -144,14 +144,16 @@ def test_tape_and_adjoint_reject_bad_arguments_without_device(crp):
     p = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0)
     parr = (crp.crp_params * 1)(p)
     parts = crp.crp_particles(**{k: 0x2000 for k in crp._PARTICLE_FIELDS})
-    tape = crp.crp_tape(0x3000, 0x4000, 0x5000, 64, 0)
+    tape = crp.crp_tape(0x3000, 0x4000, 0x5000, 0x5800, 100, 64, 0)
 
     def prop(t, prec=0):
         return L.crp_propagate(farr, 1, parr, 1, C.byref(parts), 10, C.byref(t), prec, None, None, None, 0, None)
 
-    assert prop(crp.crp_tape(0x3000, 0x4000, 0x5000, 0, 0)) == crp.CRP_ERR_INVALID
-    assert prop(crp.crp_tape(0x3000, 0x4000, 0x5000, 5000, 0)) == crp.CRP_ERR_INVALID
-    assert prop(crp.crp_tape(None, 0x4000, 0x5000, 64, 0)) == crp.CRP_ERR_INVALID
+    assert prop(crp.crp_tape(0x3000, 0x4000, 0x5000, 0x5800, 100, 0, 0)) == crp.CRP_ERR_INVALID
+    assert prop(crp.crp_tape(0x3000, 0x4000, 0x5000, 0x5800, 100, 5000, 0)) == crp.CRP_ERR_INVALID
+    assert prop(crp.crp_tape(0x3000, 0x4000, 0x5000, 0x5800, 0, 64, 0)) == crp.CRP_ERR_INVALID
+    assert prop(crp.crp_tape(None, 0x4000, 0x5000, 0x5800, 100, 64, 0)) == crp.CRP_ERR_INVALID
+    assert prop(crp.crp_tape(0x3000, 0x4000, None, 0x5800, 100, 64, 0)) == crp.CRP_ERR_INVALID
     assert prop(tape, prec=crp.CRP_PREC_MIXED_F64ACC) == crp.CRP_ERR_UNSUPPORTED
     assert prop(tape) == crp.CRP_ERR_WORKSPACE  # arguments fine, no workspace
 
@@ -164,7 +166,8 @@ def test_tape_and_adjoint_reject_bad_arguments_without_device(crp):
                                        gu, None, gf, ws, wsb, None)
 
     assert adj(n=-1) == crp.CRP_ERR_INVALID
-    assert adj(t=crp.crp_tape(0x3000, 0x4000, 0x5000, 0, 0)) == crp.CRP_ERR_INVALID
+    assert adj(t=crp.crp_tape(0x3000, 0x4000, 0x5000, 0x5800, 100, 0, 0)) == crp.CRP_ERR_INVALID
+    assert adj(t=crp.crp_tape(0x3000, None, 0x5000, 0x5800, 100, 64, 0)) == crp.CRP_ERR_INVALID
     assert adj(g=None) == crp.CRP_ERR_INVALID
     assert adj(gu=None) == crp.CRP_ERR_INVALID
     assert adj(gf=None) == crp.CRP_ERR_INVALID

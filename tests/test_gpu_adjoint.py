@@ -36,18 +36,18 @@ def dev():
 
 
 def _gpu_adjoint(crp, torch, B, spacing, prm, pos, dirs, energy, charge, gdir, gtime, every_k=64,
-                 layout="linear", tape_counts=None):
+                 layout="linear", capacity=None):
     dt = "f64" if B.dtype == np.float64 else "f32"
     f = crp.make_field(B, spacing, dtype=dt, layout=layout)
     init = crp.particles_to_device(pos, dirs, energy, charge)
     n = len(energy)
-    if tape_counts is None:
-        probe = crp.clone_particles(init)
-        crp.crp_propagate([f], [prm], probe)
-        tape_counts = probe["n_accepted"]
-    tape = crp.Tape(tape_counts, every_k=every_k)
+    tape = crp.Tape(n, every_k=every_k, capacity=capacity)
     st = crp.clone_particles(init)
     crp.crp_propagate([f], [prm], st, tape=tape)
+    if capacity is None and tape.overflowed():
+        tape = crp.Tape(n, every_k=every_k, capacity=tape.records_needed())
+        st = crp.clone_particles(init)
+        crp.crp_propagate([f], [prm], st, tape=tape)
     gu = torch.full((n, 3), np.nan, dtype=torch.float64, device="cuda")
     gx = torch.full((n, 3), np.nan, dtype=torch.float64, device="cuda")
     gg = torch.zeros(B.shape, dtype=torch.float64, device="cuda")
@@ -185,9 +185,9 @@ def test_edge_cases(dev):
         assert np.all(r["gx"][i] == 0.0)
     assert not np.any(r["gg"])
     _say("case: tape too small (overflow) gives zero gradients")
-    counts = torch.zeros(6, dtype=torch.int64, device="cuda")
+    # one record per particle: the start state; the next checkpoint finds the pool empty
     r = _gpu_adjoint(crp, torch, B, w.spacing, prm, P["pos"], P["dir"], P["energy"], P["charge"],
-                     np.ones((6, 3)), np.zeros(6), every_k=4, tape_counts=counts)
+                     np.ones((6, 3)), np.zeros(6), every_k=4, capacity=6)
     over = (r["flags"] & 2) != 0
     # the record after step 4 is needed only if the particle goes on after it
     assert np.array_equal(over, r["finals"][:, 0] > 4)
