@@ -189,7 +189,8 @@ size_t crp_workspace_bytes(int64_t n, int32_t n_fields, int32_t n_params);
  * is stepped until it arrives at its observer sphere, reaches l_max, uses up
  * max_steps, or fails.  fields[n_fields] and params[n_params] are host
  * arrays; every field of one call must share dtype and layout.  tape: NULL,
- * or a tape to record for crp_propagate_adjoint (FP64 precision only).
+ * or a tape to record for crp_propagate_adjoint (FP64 precision, one F64
+ * or F32 field and one parameter group; else CRP_ERR_UNSUPPORTED).
  * precision is a crp_precision.  counters: optional [dev]
  * int64[CRP_NCOUNTERS], accumulated (caller zeroes).  workspace: [dev],
  * crp_workspace_bytes long, 256-byte aligned; its contents are scratch.

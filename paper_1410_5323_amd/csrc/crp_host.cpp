@@ -208,6 +208,10 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
         return fail(CRP_ERR_INVALID, "%s: unknown precision %d", fn, precision);
     if (tape) {
         if (precision != CRP_PREC_FP64) return fail(CRP_ERR_UNSUPPORTED, "%s: a tape needs FP64 precision", fn);
+        if (n_params > 1 || (n > 0 && p->param_index) || n_fields > 1)
+            return fail(CRP_ERR_UNSUPPORTED, "%s: a tape is recorded for one field and one parameter group", fn);
+        if (fields[0].dtype != CRP_F64 && fields[0].dtype != CRP_F32)
+            return fail(CRP_ERR_UNSUPPORTED, "%s: a tape needs an F64 or F32 field", fn);
         if (tape->every_k < 1 || tape->every_k > 4096)
             return fail(CRP_ERR_INVALID, "%s: tape interval must be in [1, 4096]", fn);
         if (tape->capacity < 1) return fail(CRP_ERR_INVALID, "%s: the tape needs at least one record", fn);

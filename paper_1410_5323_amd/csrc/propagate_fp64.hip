@@ -13,6 +13,8 @@
 // a device work queue (one atomic per wavefront), so waves stay full while
 // trajectories of very different lengths (tens to tens of thousands of
 // steps) run side by side; the grid is persistent (a few blocks per CU).
+#include <type_traits>
+
 #include "crp_device.h"
 
 namespace crp {
@@ -134,15 +136,15 @@ enum { F_EVAL = 1, F_ACC = 2, F_REJ = 4, F_EVENT = 8, F_FLOOR = 16 };
 
 // Start particle p in lane state s.  Returns true if it needs steps; false if
 // it was skipped (not ACTIVE) or finished at once (its result is stored).
-template <bool MULTI>
+template <bool MULTI, bool TAPE>
 __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
     int st = a.status[p];
-    if (a.tape_ckpt) {
+    if (TAPE) {
         double *f = a.tape_fin + 4 * p;  // overwritten when the particle completes
         f[0] = f[1] = f[3] = 0.0;
         f[2] = -1.0;
+        s.tlast = -1;
     }
-    s.tlast = -1;
     if (st != CRP_ST_ACTIVE) return false;
     s.pidx = MULTI && a.param_index ? a.param_index[p] : 0;
     if (MULTI && (s.pidx < 0 || s.pidx >= a.n_params)) {
@@ -183,25 +185,25 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
     s.tflags = hn == 0.0 ? CRP_TAPE_FRESH : 0;
     if (P.sphere_on && sphere_g(P, s.y) >= 0.0) {
         store(a, p, s, hn, CRP_ST_ARRIVED);
-        if (a.tape_ckpt) tape_final(a, p, s, 0.0, CRP_TAPE_COMPLETE);
+        if (TAPE) tape_final(a, p, s, 0.0, CRP_TAPE_COMPLETE);
         return false;
     }
     if (P.lmax_on && s.L >= P.l_max) {
         store(a, p, s, hn, CRP_ST_MAX_LENGTH);
-        if (a.tape_ckpt) tape_final(a, p, s, 0.0, CRP_TAPE_COMPLETE);
+        if (TAPE) tape_final(a, p, s, 0.0, CRP_TAPE_COMPLETE);
         return false;
     }
     s.hctrl = hn == 0.0 ? P.h_max : hn;
     s.kap = ((double)Z * K_LORENTZ) / E;
     s.mode = MODE_NORMAL;
-    if (a.tape_ckpt) tape_checkpoint(a, s);
+    if (TAPE) tape_checkpoint(a, s);
     bid(P, s);
     return true;
 }
 
 // One loop iteration of a working lane.  Returns a status != ACTIVE when the
 // particle ended (its result already stored).
-template <class T, int LAYOUT, bool MULTI, bool CACHE>
+template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE>
 __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, CellCache<T> &cache, EventLDS &e,
                                        int &flags) {
     const int t = threadIdx.x;
@@ -216,7 +218,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
         double exh = ex / s.h;
         if (!isfinite(eu) || !isfinite(exh)) {
             store(a, p, s, s.hctrl, CRP_ST_NONFINITE);
-            if (a.tape_ckpt) tape_final(a, p, s, 0.0, 0);
+            if (TAPE) tape_final(a, p, s, 0.0, 0);
             return CRP_ST_NONFINITE;
         }
         double em = eu > exh ? eu : exh;
@@ -273,15 +275,15 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
         s.L = Lnew;
         if (P.lmax_on && s.L >= P.l_max) {
             store(a, p, s, s.hctrl, CRP_ST_MAX_LENGTH);
-            if (a.tape_ckpt) tape_final(a, p, s, 0.0, CRP_TAPE_COMPLETE);
+            if (TAPE) tape_final(a, p, s, 0.0, CRP_TAPE_COMPLETE);
             return CRP_ST_MAX_LENGTH;
         }
         if (P.max_steps > 0 && s.dacc >= P.max_steps) {
             store(a, p, s, s.hctrl, CRP_ST_MAX_STEPS);
-            if (a.tape_ckpt) tape_final(a, p, s, 0.0, 0);
+            if (TAPE) tape_final(a, p, s, 0.0, 0);
             return CRP_ST_MAX_STEPS;
         }
-        if (a.tape_ckpt && s.dacc % a.tape_k == 0) tape_checkpoint(a, s);
+        if (TAPE && s.dacc % a.tape_k == 0) tape_checkpoint(a, s);
         bid(P, s);
         return CRP_ST_ACTIVE;
     }
@@ -291,7 +293,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
         double gs = sphere_g(P, y5);
         if (!isfinite(gs)) {
             store(a, p, s, s.hctrl, CRP_ST_NONFINITE);
-            if (a.tape_ckpt) tape_final(a, p, s, 0.0, 0);
+            if (TAPE) tape_final(a, p, s, 0.0, 0);
             return CRP_ST_NONFINITE;
         }
         if (gs >= 0.0) {
@@ -320,7 +322,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
     s.y[5] = y5[5] / sn;
     s.L = e.hi[t] == e.hacc[t] ? e.lacc[t] : s.L + e.hi[t];
     store(a, p, s, s.hctrl, CRP_ST_ARRIVED);
-    if (a.tape_ckpt) tape_final(a, p, s, e.hi[t], CRP_TAPE_COMPLETE | CRP_TAPE_EVENT);
+    if (TAPE) tape_final(a, p, s, e.hi[t], CRP_TAPE_COMPLETE | CRP_TAPE_EVENT);
     return CRP_ST_ARRIVED;
 }
 
@@ -330,7 +332,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
 #define CRP_FP64_MIN_WAVES 2
 #endif
 
-template <class T, int LAYOUT, bool MULTI, bool CACHE>
+template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CRP_FP64_MIN_WAVES, 8)))
 k_propagate_fp64(PropArgs a) {
     const int lane = threadIdx.x & 63;
@@ -362,7 +364,7 @@ k_propagate_fp64(PropArgs a) {
                 if (q < (unsigned long long)a.n) {
                     int64_t p = a.order ? (int64_t)a.order[q] : (int64_t)q;
                     got = 1;
-                    pid = start<MULTI>(a, p, s) ? p : -1;
+                    pid = start<MULTI, TAPE>(a, p, s) ? p : -1;
                 } else {
                     pid = -2;
                 }
@@ -376,7 +378,7 @@ k_propagate_fp64(PropArgs a) {
         n_iter++;
         int flags = 0;
         if (pid >= 0) {
-            int st = advance<T, LAYOUT, MULTI, CACHE>(a, pid, s, cache, ev, flags);
+            int st = advance<T, LAYOUT, MULTI, CACHE, TAPE>(a, pid, s, cache, ev, flags);
             if (st != CRP_ST_ACTIVE) pid = -1;
         }
         n_eval += __popcll(__ballot(flags & F_EVAL));
@@ -402,10 +404,22 @@ k_propagate_fp64(PropArgs a) {
 
 template <class T, int LAYOUT, bool MULTI>
 hipError_t launch_c(const PropArgs &a, bool cache, int blocks, int bs, hipStream_t s) {
+    if (a.tape_ckpt) {
+        // taped runs (for the adjoint): one field, FP64 or FP32 storage
+        if constexpr (!MULTI && (std::is_same<T, double>::value || std::is_same<T, float>::value)) {
+            if (cache)
+                hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, false, true, true>), dim3(blocks), dim3(bs), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, false, false, true>), dim3(blocks), dim3(bs), 0, s,
+                                   a);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (cache)
-        hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, MULTI, true>), dim3(blocks), dim3(bs), 0, s, a);
+        hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, MULTI, true, false>), dim3(blocks), dim3(bs), 0, s, a);
     else
-        hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, MULTI, false>), dim3(blocks), dim3(bs), 0, s, a);
+        hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, MULTI, false, false>), dim3(blocks), dim3(bs), 0, s, a);
     return hipGetLastError();
 }
 

@@ -144,6 +144,7 @@ def test_tape_and_adjoint_reject_bad_arguments_without_device(crp):
     p = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0)
     parr = (crp.crp_params * 1)(p)
     parts = crp.crp_particles(**{k: 0x2000 for k in crp._PARTICLE_FIELDS})
+    parts.param_index = None  # one parameter group
     tape = crp.crp_tape(0x3000, 0x4000, 0x5000, 0x5800, 100, 64, 0)
 
     def prop(t, prec=0):
@@ -155,6 +156,13 @@ def test_tape_and_adjoint_reject_bad_arguments_without_device(crp):
     assert prop(crp.crp_tape(None, 0x4000, 0x5000, 0x5800, 100, 64, 0)) == crp.CRP_ERR_INVALID
     assert prop(crp.crp_tape(0x3000, 0x4000, None, 0x5800, 100, 64, 0)) == crp.CRP_ERR_INVALID
     assert prop(tape, prec=crp.CRP_PREC_MIXED_F64ACC) == crp.CRP_ERR_UNSUPPORTED
+    multi = crp.crp_particles(**{k: 0x2000 for k in crp._PARTICLE_FIELDS})
+    assert L.crp_propagate(farr, 1, parr, 1, C.byref(multi), 10, C.byref(tape), 0, None, None, None, 0,
+                           None) == crp.CRP_ERR_UNSUPPORTED  # per-particle parameter groups
+    half = _field(crp, dtype=crp.CRP_F16)
+    half.data = 0x1000
+    assert L.crp_propagate((crp.crp_field * 1)(half), 1, parr, 1, C.byref(parts), 10, C.byref(tape), 0, None, None,
+                           None, 0, None) == crp.CRP_ERR_UNSUPPORTED
     assert prop(tape) == crp.CRP_ERR_WORKSPACE  # arguments fine, no workspace
 
     assert crp.crp_adjoint_workspace_bytes(-1, 64) == 0
@@ -171,8 +179,6 @@ def test_tape_and_adjoint_reject_bad_arguments_without_device(crp):
     assert adj(g=None) == crp.CRP_ERR_INVALID
     assert adj(gu=None) == crp.CRP_ERR_INVALID
     assert adj(gf=None) == crp.CRP_ERR_INVALID
-    half = _field(crp, dtype=crp.CRP_F16)
-    half.data = 0x1000
     assert adj(field=half) == crp.CRP_ERR_UNSUPPORTED
     assert adj(params=crp.make_params(0.0, 0.01, 1.0, l_max=10.0)) == crp.CRP_ERR_INVALID
     assert adj() == crp.CRP_ERR_WORKSPACE
