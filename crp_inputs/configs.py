@@ -47,6 +47,15 @@ class Workload:
     count_range: tuple = (0, 0)
     radius_range: tuple = (0.0, 0.0)
     checkpoint_every: int = 0
+    mod_n: int = 0               # modulation grid nodes per axis (0: no modulation)
+    mod_spacing: float = 0.0     # Mpc
+    mod_l_corr: float = 0.0      # correlation length of the log-normal modulation, Mpc
+    mod_sigma: float = 0.0       # standard deviation of log m
+
+    @property
+    def mod_origin(self) -> float:
+        """The modulation grid is centred on the origin (where the particles start)."""
+        return -0.5 * self.mod_n * self.mod_spacing
 
     @property
     def box(self) -> float:
@@ -73,6 +82,11 @@ CONFIGS = (
     # 1e5 protons and iron, 128^3 FP32 grid; band, tol, step limits and L_max chosen.
     Workload("adjoint_128cube", 4, 100_000, (1, 26), 1e18, 1e19, 128, 0.05, 0.1, 3.2, 1.0, "f32",
              1e-4, 0.001, 1.0, 10.0, 1000.0, charge_rule="alternate", checkpoint_every=64),
+    # Modulated field as in the paper's example: the production vector grid (256^3 at 50 kpc,
+    # periodic every 12.8 Mpc) times a 132 Mpc modulation grid at 300 kpc (440^3); the
+    # log-normal modulation (correlation length 2 Mpc, sigma 1) is chosen.
+    Workload("modulated_256cube", 5, 1_000_000, MIXED, 1e18, 1e20, 256, 0.05, 0.1, 5.0, 1.0, "f32",
+             1e-4, 0.001, 1.0, 20.0, 1000.0, mod_n=440, mod_spacing=0.3, mod_l_corr=2.0, mod_sigma=1.0),
 )
 
 

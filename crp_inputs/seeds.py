@@ -2,13 +2,15 @@
 
 One root ``SeedSequence(14105323)`` (the arXiv number of the paper) spawns one
 child per workload; each child spawns three streams: field, particles and
-realisation parameters.  ``SeedSequence.spawn`` is stateful, so the tree is
-rebuilt from the root on every call to keep results reproducible.
+realisation parameters (the modulated workload draws its modulation grid from
+the third).  A child depends only on its index, not on how many children are
+spawned.  ``SeedSequence.spawn`` is stateful, so the tree is rebuilt from the
+root on every call to keep results reproducible.
 """
 import numpy as np
 
 ROOT_SEED = 14105323
-N_WORKLOADS = 5
+N_WORKLOADS = 6
 
 
 def config_seeds(index: int):

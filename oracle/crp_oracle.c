@@ -88,12 +88,25 @@ enum { ST_ACTIVE = 0, ST_ARRIVED = 1, ST_MAX_LENGTH = 2, ST_MAX_STEPS = 3,
        ST_NONFINITE = 4, ST_CANCELLED = 5, ST_BAD_INPUT = 6 };
 
 /* ---- the periodic vector grid ----------------------------------------- */
+/* Optional modulation (section 3.2, modulated grids): a low-resolution scalar
+ * grid m, itself periodic over its own extent, that multiplies the vector
+ * grid's value: B(x) = b(x) * m(x). */
+typedef struct {
+    int present;
+    int64_t n[3];
+    double origin[3];
+    double inv_spacing;
+    const double *v64;       /* [n0][n1][n2], dimensionless; exactly one of v64/v32 set */
+    const float *v32;
+} modgrid_t;
+
 typedef struct {
     int64_t n[3];
     double origin[3];
     double inv_spacing;      /* 1.0 / spacing, one FP64 division */
     const double *v64;       /* [n0][n1][n2][3], nG; exactly one of v64/v32 set */
     const float *v32;
+    modgrid_t mod;
 } grid_t;
 
 static double grid_value(const grid_t *g, int64_t i, int64_t j, int64_t k, int c)
@@ -149,12 +162,49 @@ static void field_at(const grid_t *g, const double X[3], double B[3])
     }
 }
 
+/* Trilinear interpolation of the periodic modulation grid at X, in the same
+ * order as the vector grid (x, then y, then z).  NaN for an absurd position. */
+static double mod_at(const modgrid_t *m, const double X[3])
+{
+    int64_t i0[3], i1[3];
+    double t[3];
+    for (int a = 0; a < 3; ++a) {
+        double f = (X[a] - m->origin[a]) * m->inv_spacing;
+        if (!(fabs(f) < 4.0e15))
+            return NAN;
+        double fl = floor(f);
+        t[a] = f - fl;
+        i0[a] = pmod((int64_t)fl, m->n[a]);
+        i1[a] = pmod(i0[a] + 1, m->n[a]);
+    }
+#define MODV(i, j, k) (m->v64 ? m->v64[((i) * m->n[1] + (j)) * m->n[2] + (k)] \
+                              : (double)m->v32[((i) * m->n[1] + (j)) * m->n[2] + (k)])
+    double c00 = lerp(MODV(i0[0], i0[1], i0[2]), MODV(i1[0], i0[1], i0[2]), t[0]);
+    double c10 = lerp(MODV(i0[0], i1[1], i0[2]), MODV(i1[0], i1[1], i0[2]), t[0]);
+    double c01 = lerp(MODV(i0[0], i0[1], i1[2]), MODV(i1[0], i0[1], i1[2]), t[0]);
+    double c11 = lerp(MODV(i0[0], i1[1], i1[2]), MODV(i1[0], i1[1], i1[2]), t[0]);
+#undef MODV
+    return lerp(lerp(c00, c10, t[1]), lerp(c01, c11, t[1]), t[2]);
+}
+
+/* The field at X: the vector grid's value times the modulation, if any. */
+static void field_total(const grid_t *g, const double X[3], double B[3])
+{
+    field_at(g, X, B);
+    if (g->mod.present) {
+        double m = mod_at(&g->mod, X);
+        B[0] = B[0] * m;
+        B[1] = B[1] * m;
+        B[2] = B[2] * m;
+    }
+}
+
 /* Right-hand side of the Lorentz-force system in path length:
  * y = (x, u) -> (u, kappa * u x B(x)). */
 static void rhs(const grid_t *g, double kappa, const double Y[6], double k[6])
 {
     double B[3];
-    field_at(g, Y, B);
+    field_total(g, Y, B);
     k[0] = Y[3];
     k[1] = Y[4];
     k[2] = Y[5];
@@ -436,11 +486,31 @@ static int propagate_one(const grid_t *g, const params_t *p, double y[6], double
 
 /* ======================= exported C interface ============================ */
 
+/* mod: NULL for no modulation, else the modulation values ([n0][n1][n2],
+ * dtype mod_desc[3]); mod_desc = {n0, n1, n2, dtype, origin x, y, z, spacing}. */
 static int make_grid(grid_t *g, const void *data, int dtype, int64_t n0, int64_t n1, int64_t n2,
-                     const double origin[3], double spacing)
+                     const double origin[3], double spacing, const void *mod, const double *mod_desc)
 {
     if (!data || n0 < 2 || n1 < 2 || n2 < 2 || !(spacing > 0.0) || (dtype != 0 && dtype != 1))
         return -1;
+    g->mod.present = 0;
+    if (mod) {
+        if (!mod_desc)
+            return -1;
+        int64_t m0 = (int64_t)mod_desc[0], m1 = (int64_t)mod_desc[1], m2 = (int64_t)mod_desc[2];
+        int mdt = (int)mod_desc[3];
+        if (m0 < 2 || m1 < 2 || m2 < 2 || !(mod_desc[7] > 0.0) || (mdt != 0 && mdt != 1))
+            return -1;
+        g->mod.present = 1;
+        g->mod.n[0] = m0;
+        g->mod.n[1] = m1;
+        g->mod.n[2] = m2;
+        for (int a = 0; a < 3; ++a)
+            g->mod.origin[a] = mod_desc[4 + a];
+        g->mod.inv_spacing = 1.0 / mod_desc[7];
+        g->mod.v64 = mdt == 0 ? (const double *)mod : NULL;
+        g->mod.v32 = mdt == 1 ? (const float *)mod : NULL;
+    }
     g->n[0] = n0;
     g->n[1] = n1;
     g->n[2] = n2;
@@ -474,23 +544,23 @@ double oracle_inv_fifth_root(double err) { return inv_fifth_root(err); }
 
 /* Field at n points X[n][3] -> B[n][3]. Returns 0 or -1 on bad arguments. */
 int oracle_field_at(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2,
-                    const double *origin, double spacing, const double *X, double *B, int64_t n)
+                    const double *origin, double spacing, const void *mod, const double *mod_desc, const double *X, double *B, int64_t n)
 {
     grid_t g;
-    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing))
+    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing, mod, mod_desc))
         return -1;
     for (int64_t i = 0; i < n; ++i)
-        field_at(&g, X + 3 * i, B + 3 * i);
+        field_total(&g, X + 3 * i, B + 3 * i);
     return 0;
 }
 
 /* One Cash-Karp evaluation (no control): y[6], h -> y5[6], delta[6]. */
 int oracle_ck_eval(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2,
-                   const double *origin, double spacing, double kappa, const double *y, double h,
+                   const double *origin, double spacing, const void *mod, const double *mod_desc, double kappa, const double *y, double h,
                    double *y5, double *delta)
 {
     grid_t g;
-    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing))
+    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing, mod, mod_desc))
         return -1;
     ck_eval(&g, kappa, y, h, y5, delta);
     return 0;
@@ -498,11 +568,11 @@ int oracle_ck_eval(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t 
 
 /* Fixed-step integration (no controller, no normalisation): nsteps of size h. */
 int oracle_fixed_steps(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2,
-                       const double *origin, double spacing, double kappa, double *y, double h,
+                       const double *origin, double spacing, const void *mod, const double *mod_desc, double kappa, double *y, double h,
                        int64_t nsteps)
 {
     grid_t g;
-    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing))
+    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing, mod, mod_desc))
         return -1;
     for (int64_t s = 0; s < nsteps; ++s) {
         double y5[6], d[6];
@@ -516,13 +586,13 @@ int oracle_fixed_steps(const void *grid, int dtype, int64_t n0, int64_t n1, int6
  * Arrays of length n (pos/dir are n x 3).  counters (may be NULL): 5 int64 summed
  * [evals, accepted, rejected, event_evals, floor_hits].  Returns 0 or -1. */
 int oracle_propagate(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2,
-                     const double *origin, double spacing, const double *prm, int64_t max_steps,
+                     const double *origin, double spacing, const void *mod, const double *mod_desc, const double *prm, int64_t max_steps,
                      int64_t n, double *pos, double *dir, const double *energy,
                      const int32_t *charge, double *length, double *h_next, int32_t *status,
                      int64_t *n_acc, int64_t *n_rej, int64_t *counters, int nthreads)
 {
     grid_t g;
-    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing) || n < 0 || !prm)
+    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing, mod, mod_desc) || n < 0 || !prm)
         return -1;
     params_t p;
     p.tol = prm[0];
@@ -583,12 +653,12 @@ int oracle_propagate(const void *grid, int dtype, int64_t n0, int64_t n1, int64_
  * steps (may exceed cap, then the tape is truncated) or -1.  info[0] = status,
  * info[1] = event flag, info[2] = s* of the event, info[3] = length-bound flag. */
 int64_t oracle_propagate_taped(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2,
-                               const double *origin, double spacing, const double *prm,
+                               const double *origin, double spacing, const void *mod, const double *mod_desc, const double *prm,
                                double *y, double energy, int32_t charge, double *length,
                                double *h_next, double *h_tape, int64_t cap, double *info)
 {
     grid_t g;
-    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing))
+    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing, mod, mod_desc))
         return -1;
     params_t p;
     p.tol = prm[0];
@@ -828,12 +898,14 @@ static int crossing_newton(const grid_t *g, double kappa, const double y[6], con
  * step map continued to small negative s).  out: [u_N(3), L, du_N(3), dL,
  * x_N(3), s*].  Returns 0, or -1 on bad arguments or no root. */
 int oracle_replay_tangent(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2, const double *origin,
-                          double spacing, double kappa, const double *x0, const double *u0, const double *du0,
+                          double spacing, const void *mod, const double *mod_desc, double kappa, const double *x0, const double *u0, const double *du0,
                           const double *vg, const double *h, int64_t n, int event, const double *c, double R,
                           double *out)
 {
     grid_t g;
-    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing) || n < 1)
+    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing, mod, mod_desc) || n < 1)
+        return -1;
+    if (g.mod.present) /* derivatives of modulated fields are not provided */
         return -1;
     dual y[6];
     for (int a = 0; a < 3; ++a) {
@@ -973,12 +1045,14 @@ static void step_vjp(const grid_t *g, double kappa, const double y[6], double s,
  * of the raw initial direction), x0bar; gbar (3 n0 n1 n2, FP64) accumulated if
  * not NULL.  Returns 0 or -1. */
 int oracle_replay_adjoint(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2, const double *origin,
-                          double spacing, double kappa, const double *x0, const double *u0, const double *h,
+                          double spacing, const void *mod, const double *mod_desc, double kappa, const double *x0, const double *u0, const double *h,
                           int64_t n, int event, const double *c, double R, const double *ubar, double Lbar,
                           double *u0bar, double *x0bar, double *gbar)
 {
     grid_t g;
-    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing) || n < 1)
+    if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing, mod, mod_desc) || n < 1)
+        return -1;
+    if (g.mod.present) /* derivatives of modulated fields are not provided */
         return -1;
     double *ys = (double *)malloc(sizeof(double) * 6 * (size_t)n);
     if (!ys)

@@ -22,7 +22,7 @@ STATUS = {"ACTIVE": 0, "ARRIVED": 1, "MAX_LENGTH": 2, "MAX_STEPS": 3, "NONFINITE
 _pd = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _pi32 = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _pi64 = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
-_GRID_ARGS = [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_int64, _pd, C.c_double]
+_GRID_ARGS = [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_int64, _pd, C.c_double, C.c_void_p, C.c_void_p]
 
 
 def lib():
@@ -57,12 +57,26 @@ def lib():
     return _lib
 
 
+class Modulation:
+    """A periodic scalar modulation grid (section 3.2, modulated grids): values
+    [n0][n1][n2], float64 or float32, node (0, 0, 0) at ``origin``."""
+
+    def __init__(self, values: np.ndarray, spacing: float, origin=(0.0, 0.0, 0.0)):
+        v = np.ascontiguousarray(values)
+        if v.dtype not in (np.float64, np.float32) or v.ndim != 3:
+            raise ValueError("modulation must be float64/float32 of shape (n0, n1, n2)")
+        self.values = v
+        self.desc = np.array([v.shape[0], v.shape[1], v.shape[2], 0 if v.dtype == np.float64 else 1,
+                              origin[0], origin[1], origin[2], spacing], dtype=np.float64)
+
+
 class Grid:
-    """A periodic vector grid as the oracle reads it: values [n0][n1][n2][3] in nG.
+    """A periodic vector grid as the oracle reads it: values [n0][n1][n2][3] in nG,
+    optionally multiplied by a Modulation.
 
     Accepts float64 or float32 values (each read exactly as FP64)."""
 
-    def __init__(self, values: np.ndarray, spacing: float, origin=(0.0, 0.0, 0.0)):
+    def __init__(self, values: np.ndarray, spacing: float, origin=(0.0, 0.0, 0.0), modulation=None):
         v = np.ascontiguousarray(values)
         if v.dtype not in (np.float64, np.float32) or v.ndim != 4 or v.shape[3] != 3:
             raise ValueError("grid must be float64/float32 of shape (n0, n1, n2, 3)")
@@ -71,10 +85,13 @@ class Grid:
         self.shape = v.shape[:3]
         self.spacing = float(spacing)
         self.origin = np.asarray(origin, dtype=np.float64).copy()
+        self.modulation = modulation
 
     def args(self):
+        m = self.modulation
         return (self.values.ctypes.data, self.dtype_code, self.shape[0], self.shape[1],
-                self.shape[2], self.origin, self.spacing)
+                self.shape[2], self.origin, self.spacing, None if m is None else m.values.ctypes.data,
+                None if m is None else m.desc.ctypes.data)
 
 
 def constants() -> dict:
