@@ -75,6 +75,19 @@ enum {
 /* One periodic vector grid (section 3.2: regular grids; section 4: a vector
  * grid with a random Kolmogorov realisation).  Node (i,j,k) sits at
  * origin + spacing*(i,j,k); the field repeats with period n*spacing. */
+/* A periodic scalar modulation grid (section 3.2, modulated grids: a small
+ * high-resolution vector grid repeated periodically, times a large
+ * low-resolution grid that carries the large-scale structure).  The field at
+ * x becomes b(x) * m(x), m interpolated trilinearly on this grid (x, then y,
+ * then z) and repeated with period n * spacing. */
+typedef struct {
+    int32_t n[3];          /* nodes per axis, each >= 2 */
+    int32_t dtype;         /* CRP_F64 or CRP_F32 storage */
+    double origin[3];      /* Mpc, position of node (0, 0, 0) */
+    double spacing;        /* Mpc, > 0 */
+    void *data;            /* [dev] crp_modulation_bytes(this) bytes, written by crp_modulation_upload */
+} crp_modulation;
+
 typedef struct {
     int32_t n[3];          /* nodes per axis, each >= 2 */
     int32_t dtype;         /* crp_dtype of the stored values */
@@ -84,6 +97,7 @@ typedef struct {
     double spacing;        /* Mpc, > 0 */
     double value_scale;    /* nG per stored unit (1 for F64/F32 grids) */
     void *data;            /* [dev] crp_field_bytes(this) bytes, written by crp_field_upload */
+    const crp_modulation *modulation;  /* host pointer, NULL for none; FP64 precision only, no tape */
 } crp_field;
 
 /* Bidding and stopping parameters of one particle group (section 3.1). */
@@ -180,6 +194,15 @@ size_t crp_field_bytes(const crp_field *f);
  * even into f->dtype, then written in f->layout.  src and f->data must not
  * overlap.  Stream s (hipStream_t, may be NULL for the default stream). */
 crp_status crp_field_upload(const crp_field *f, const void *src, int32_t src_dtype, void *stream);
+
+/* Bytes of device storage for a modulation grid; 0 if the descriptor is invalid. */
+size_t crp_modulation_bytes(const crp_modulation *m);
+
+/* Fill m->data from src: [dev] C-order [n0][n1][n2] values of src_dtype F64
+ * or F32 (section 3.2, modulated grids), rounded to nearest even into
+ * m->dtype and stored with the periodic wrap (one extra plane per axis).
+ * src and m->data must not overlap.  Stream s may be NULL. */
+crp_status crp_modulation_upload(const crp_modulation *m, const void *src, int32_t src_dtype, void *stream);
 
 /* Device workspace needed by crp_propagate for n particles and the given
  * table sizes (field and parameter descriptors, work queue, ordering keys). */

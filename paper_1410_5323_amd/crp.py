@@ -33,10 +33,15 @@ class CRPError(RuntimeError):
         self.status = status
 
 
+class crp_modulation(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("dtype", C.c_int32), ("origin", C.c_double * 3), ("spacing", C.c_double),
+                ("data", C.c_void_p)]
+
+
 class crp_field(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("dtype", C.c_int32), ("layout", C.c_int32),
                 ("reserved", C.c_int32), ("origin", C.c_double * 3), ("spacing", C.c_double),
-                ("value_scale", C.c_double), ("data", C.c_void_p)]
+                ("value_scale", C.c_double), ("data", C.c_void_p), ("modulation", C.POINTER(crp_modulation))]
 
 
 class crp_params(C.Structure):
@@ -80,6 +85,10 @@ def lib():
         L.crp_field_bytes.argtypes = [C.POINTER(crp_field)]
         L.crp_field_bytes.restype = C.c_size_t
         L.crp_field_upload.argtypes = [C.POINTER(crp_field), C.c_void_p, C.c_int32, C.c_void_p]
+        L.crp_modulation_bytes.argtypes = [C.POINTER(crp_modulation)]
+        L.crp_modulation_bytes.restype = C.c_size_t
+        L.crp_modulation_upload.argtypes = [C.POINTER(crp_modulation), C.c_void_p, C.c_int32, C.c_void_p]
+        L.crp_modulation_upload.restype = C.c_int
         L.crp_workspace_bytes.argtypes = [C.c_int64, C.c_int32, C.c_int32]
         L.crp_workspace_bytes.restype = C.c_size_t
         L.crp_propagate.argtypes = [C.POINTER(crp_field), C.c_int32, C.POINTER(crp_params), C.c_int32,
@@ -315,10 +324,43 @@ def crp_bench_stream(src, dst, nbytes: int, sink, blocks: int, stream=None):
 # ------------------------------------------------------------- conveniences
 
 @dataclass
+class Modulation:
+    """A device modulation grid: descriptor plus the tensor that owns its storage."""
+    desc: crp_modulation
+    storage: object
+
+
+def make_modulation(values, spacing: float, origin=(0.0, 0.0, 0.0), dtype="f32", device="cuda",
+                    stream=None) -> Modulation:
+    """Upload an (n0, n1, n2) scalar modulation grid (numpy or torch; float64/float32)."""
+    torch = _torch()
+    src = values if isinstance(values, torch.Tensor) else torch.from_numpy(values)
+    src = src.to(device=device).contiguous()
+    if src.dtype not in (torch.float64, torch.float32) or src.dim() != 3:
+        raise TypeError("modulation must be a float64/float32 array of shape (n0, n1, n2)")
+    d = crp_modulation()
+    d.n[0], d.n[1], d.n[2] = (int(v) for v in src.shape)
+    d.dtype = DTYPES[dtype]
+    d.origin[0], d.origin[1], d.origin[2] = (float(o) for o in origin)
+    d.spacing = float(spacing)
+    nb = int(lib().crp_modulation_bytes(C.byref(d)))
+    if nb == 0:
+        raise CRPError(CRP_ERR_INVALID, crp_last_error())
+    storage = torch.empty(nb, dtype=torch.uint8, device=device)
+    d.data = storage.data_ptr()
+    sd = CRP_F64 if src.dtype == torch.float64 else CRP_F32
+    _check(lib().crp_modulation_upload(C.byref(d), _ptr(src), sd, _stream_handle(stream)))
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return Modulation(d, storage)
+
+
+@dataclass
 class Field:
-    """A device field grid: descriptor plus the torch tensor that owns its storage."""
+    """A device field grid: descriptor plus the torch tensor that owns its storage
+    (and the modulation it refers to, if any)."""
     desc: crp_field
     storage: object
+    modulation: object = None
 
     @property
     def nbytes(self) -> int:
@@ -326,8 +368,9 @@ class Field:
 
 
 def make_field(values, spacing: float, origin=(0.0, 0.0, 0.0), dtype="f32", layout="linear",
-               value_scale: float = 1.0, device="cuda", stream=None) -> Field:
-    """Upload an (n0, n1, n2, 3) grid in nG (numpy or torch; float64/float32)."""
+               value_scale: float = 1.0, device="cuda", stream=None, modulation: Modulation | None = None) -> Field:
+    """Upload an (n0, n1, n2, 3) grid in nG (numpy or torch; float64/float32),
+    optionally multiplied by a Modulation (section 3.2, modulated grids)."""
     torch = _torch()
     src = values if isinstance(values, torch.Tensor) else torch.from_numpy(values)
     src = src.to(device=device).contiguous()
@@ -345,7 +388,9 @@ def make_field(values, spacing: float, origin=(0.0, 0.0, 0.0), dtype="f32", layo
     d.data = storage.data_ptr()
     crp_field_upload(d, src, stream=stream)
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
-    return Field(d, storage)
+    if modulation is not None:
+        d.modulation = C.pointer(modulation.desc)
+    return Field(d, storage, modulation)
 
 
 def make_params(tol, h_min, h_max, obs_radius=0.0, l_max=math.inf, obs_center=(0.0, 0.0, 0.0),

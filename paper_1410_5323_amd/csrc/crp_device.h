@@ -200,11 +200,44 @@ __device__ __forceinline__ void cache_reset(CellCache<T> &c, T (*lds)[CACHE_BLOC
     c.misses = 0;
 }
 
-template <class T, int LAYOUT, bool CACHE>
+// Modulation value at X (section 3.2, modulated grids): trilinear on the
+// padded scalar grid, x then y then z, as the vector components.
+template <class M>
+__device__ __forceinline__ double mod_interp(const FieldDev &F, const double X[3]) {
+    double t[3];
+    int c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c[a] = cell_axis(X[a], F.mod_origin[a], F.mod_inv_spacing, F.mod_n[a], F.mod_pow2, t[a]);
+    const global_ptr<M> p = as_global<M>(F.mod_data) + ((uint32_t)c[0] * F.mod_sx + (uint32_t)c[1] * F.mod_sy + (uint32_t)c[2]);
+    const uint32_t sx = F.mod_sx, sy = F.mod_sy;
+    const double v000 = (double)p[0], v001 = (double)p[1];
+    const double v100 = (double)p[sx], v101 = (double)p[sx + 1];
+    const double v010 = (double)p[sy], v011 = (double)p[sy + 1];
+    const double v110 = (double)p[sx + sy], v111 = (double)p[sx + sy + 1];
+    const double c00 = lerp(v000, v100, t[0]);
+    const double c10 = lerp(v010, v110, t[0]);
+    const double c01 = lerp(v001, v101, t[0]);
+    const double c11 = lerp(v011, v111, t[0]);
+    return lerp(lerp(c00, c10, t[1]), lerp(c01, c11, t[1]), t[2]);
+}
+
+// B <- B * m(X) when the field carries a modulation grid.
+__device__ __forceinline__ void modulate(const FieldDev &F, const double X[3], double B[3]) {
+    if (!F.mod_data) return;
+    const double m = F.mod_dtype == CRP_F64 ? mod_interp<double>(F, X) : mod_interp<float>(F, X);
+    B[0] = B[0] * m;
+    B[1] = B[1] * m;
+    B[2] = B[2] * m;
+}
+
+// MOD: the launch has modulated fields (then each field's modulation, if any,
+// multiplies its value); without it no modulation code is compiled in.
+template <class T, int LAYOUT, bool CACHE, bool MOD = false>
 __device__ __forceinline__ void lookup_cached(const FieldDev &F, int fid, const double X[3], double B[3],
                                               CellCache<T> &cache) {
     if (!CACHE) {
         lookup<T, LAYOUT>(F, X, B);
+        if (MOD) modulate(F, X, B);
         cache.misses++;
         return;
     }
@@ -226,13 +259,14 @@ __device__ __forceinline__ void lookup_cached(const FieldDev &F, int fid, const 
         for (int w = 0; w < 24; ++w) v[w] = cache.v[w][cache.t];
     }
     interp_corners<T>(F, v, tx, ty, tz, B);
+    if (MOD) modulate(F, X, B);
 }
 
 // Right-hand side in path length: k = (U, kappa * U x B(X)) for Y = (X, U).
-template <class T, int LAYOUT, bool CACHE>
+template <class T, int LAYOUT, bool CACHE, bool MOD = false>
 __device__ __forceinline__ void rhs(const FieldDev &F, int fid, CellCache<T> &cache, double kap, const double Y[6],
                                     double k[6], double B[3]) {
-    lookup_cached<T, LAYOUT, CACHE>(F, fid, Y, B, cache);
+    lookup_cached<T, LAYOUT, CACHE, MOD>(F, fid, Y, B, cache);
     k[0] = Y[3];
     k[1] = Y[4];
     k[2] = Y[5];
@@ -259,41 +293,41 @@ struct NoStageRecord {
 // position (ex) and direction (eu) parts.  Stage sums accumulate over j in
 // increasing order with fma starting from zero; terms with a zero weight are
 // omitted (they only add a signed zero).
-template <class T, int LAYOUT, bool CACHE, class Rec = NoStageRecord>
+template <class T, int LAYOUT, bool CACHE, class Rec = NoStageRecord, bool MOD = false>
 __device__ __forceinline__ void ck_eval(const FieldDev &F, int fid, CellCache<T> &cache, double kap,
                                         const double y[6], double h, double y5[6], double &ex, double &eu,
                                         const Rec &rec = Rec()) {
     double k1[6], k2[6], k3[6], k4[6], k5[6], k6[6], Y[6], B[3];
-    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, y, k1, B);
+    rhs<T, LAYOUT, CACHE, MOD>(F, fid, cache, kap, y, k1, B);
     rec.field(0, B);
 #pragma unroll
     for (int c = 0; c < 6; ++c) Y[c] = fma(h, fma(A21, k1[c], 0.0), y[c]);
     rec.stage(1, Y);
-    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k2, B);
+    rhs<T, LAYOUT, CACHE, MOD>(F, fid, cache, kap, Y, k2, B);
     rec.field(1, B);
 #pragma unroll
     for (int c = 0; c < 6; ++c) Y[c] = fma(h, fma(A32, k2[c], fma(A31, k1[c], 0.0)), y[c]);
     rec.stage(2, Y);
-    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k3, B);
+    rhs<T, LAYOUT, CACHE, MOD>(F, fid, cache, kap, Y, k3, B);
     rec.field(2, B);
 #pragma unroll
     for (int c = 0; c < 6; ++c)
         Y[c] = fma(h, fma(A43, k3[c], fma(A42, k2[c], fma(A41, k1[c], 0.0))), y[c]);
     rec.stage(3, Y);
-    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k4, B);
+    rhs<T, LAYOUT, CACHE, MOD>(F, fid, cache, kap, Y, k4, B);
     rec.field(3, B);
 #pragma unroll
     for (int c = 0; c < 6; ++c)
         Y[c] = fma(h, fma(A54, k4[c], fma(A53, k3[c], fma(A52, k2[c], fma(A51, k1[c], 0.0)))), y[c]);
     rec.stage(4, Y);
-    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k5, B);
+    rhs<T, LAYOUT, CACHE, MOD>(F, fid, cache, kap, Y, k5, B);
     rec.field(4, B);
 #pragma unroll
     for (int c = 0; c < 6; ++c)
         Y[c] = fma(h, fma(A65, k5[c], fma(A64, k4[c], fma(A63, k3[c], fma(A62, k2[c], fma(A61, k1[c], 0.0))))),
                    y[c]);
     rec.stage(5, Y);
-    rhs<T, LAYOUT, CACHE>(F, fid, cache, kap, Y, k6, B);
+    rhs<T, LAYOUT, CACHE, MOD>(F, fid, cache, kap, Y, k6, B);
     rec.field(5, B);
     double d[6];
 #pragma unroll

@@ -51,6 +51,36 @@ size_t dtype_size(int32_t d) {
 }
 
 // Checks one field descriptor; data may be NULL only when !need_data.
+crp_status check_modulation(const crp_modulation *m, bool need_data, const char *what) {
+    if (!m) return fail(CRP_ERR_INVALID, "%s: null modulation descriptor", what);
+    for (int a = 0; a < 3; ++a) {
+        if (m->n[a] < 2 || m->n[a] > (1 << 20))
+            return fail(CRP_ERR_INVALID, "%s: modulation n[%d] = %d out of range [2, 2^20]", what, a, m->n[a]);
+        if (!std::isfinite(m->origin[a])) return fail(CRP_ERR_INVALID, "%s: modulation origin not finite", what);
+    }
+    if (!(m->spacing > 0.0) || !std::isfinite(m->spacing))
+        return fail(CRP_ERR_INVALID, "%s: modulation spacing must be finite and > 0", what);
+    if (m->dtype != CRP_F64 && m->dtype != CRP_F32)
+        return fail(CRP_ERR_INVALID, "%s: modulation dtype must be F64 or F32", what);
+    if (((uint64_t)m->n[0] + 1) * ((uint64_t)m->n[1] + 1) * ((uint64_t)m->n[2] + 1) >= (1ull << 32))
+        return fail(CRP_ERR_UNSUPPORTED, "%s: modulation grid limited to 2^32 stored values", what);
+    if (need_data && !m->data) return fail(CRP_ERR_INVALID, "%s: null modulation data pointer", what);
+    return CRP_OK;
+}
+
+void fill_modulation_dev(crp::FieldDev &d, const crp_modulation &m) {
+    d.mod_data = m.data;
+    for (int a = 0; a < 3; ++a) {
+        d.mod_n[a] = m.n[a];
+        d.mod_origin[a] = m.origin[a];
+    }
+    d.mod_pow2 = is_pow2(m.n[0]) && is_pow2(m.n[1]) && is_pow2(m.n[2]);
+    d.mod_inv_spacing = 1.0 / m.spacing;
+    d.mod_sy = (uint32_t)(m.n[2] + 1);
+    d.mod_sx = (uint32_t)((m.n[1] + 1) * (m.n[2] + 1));
+    d.mod_dtype = m.dtype;
+}
+
 crp_status check_field(const crp_field *f, bool need_data, const char *what) {
     if (!f) return fail(CRP_ERR_INVALID, "%s: null field descriptor", what);
     for (int a = 0; a < 3; ++a) {
@@ -71,6 +101,7 @@ crp_status check_field(const crp_field *f, bool need_data, const char *what) {
     if (f->layout == CRP_LAYOUT_CELL8 && n0 * n1 * n2 >= (1ull << 32))
         return fail(CRP_ERR_UNSUPPORTED, "%s: CELL8 layout limited to 2^32 cells", what);
     if (need_data && !f->data) return fail(CRP_ERR_INVALID, "%s: null data pointer", what);
+    if (need_data && f->modulation) return check_modulation(f->modulation, true, what);
     return CRP_OK;
 }
 
@@ -91,6 +122,7 @@ crp::FieldDev make_field_dev(const crp_field &f) {
     d.cx = (uint32_t)((uint64_t)f.n[1] * f.n[2]);
     d.dtype = f.dtype;
     d.layout = f.layout;
+    if (f.modulation) fill_modulation_dev(d, *f.modulation);
     return d;
 }
 
@@ -175,6 +207,31 @@ crp_status crp_field_upload(const crp_field *f, const void *src, int32_t src_dty
     return ok();
 }
 
+size_t crp_modulation_bytes(const crp_modulation *m) {
+    if (check_modulation(m, false, "crp_modulation_bytes") != CRP_OK) return 0;
+    uint64_t vals = ((uint64_t)m->n[0] + 1) * ((uint64_t)m->n[1] + 1) * ((uint64_t)m->n[2] + 1);
+    return (size_t)(vals * dtype_size(m->dtype));
+}
+
+crp_status crp_modulation_upload(const crp_modulation *m, const void *src, int32_t src_dtype, void *stream) {
+    crp_status st = check_modulation(m, true, "crp_modulation_upload");
+    if (st != CRP_OK) return st;
+    if (!src) return fail(CRP_ERR_INVALID, "crp_modulation_upload: null source");
+    if (src_dtype != CRP_F64 && src_dtype != CRP_F32)
+        return fail(CRP_ERR_INVALID, "crp_modulation_upload: source dtype must be F64 or F32");
+    size_t sb = (size_t)m->n[0] * m->n[1] * m->n[2] * dtype_size(src_dtype);
+    size_t db = crp_modulation_bytes(m);
+    const char *a = static_cast<const char *>(src), *b = static_cast<const char *>(m->data);
+    if (a < b + db && b < a + sb) return fail(CRP_ERR_INVALID, "crp_modulation_upload: source and destination overlap");
+    if (cu_count() <= 0) return fail(CRP_ERR_DEVICE, "crp_modulation_upload: no HIP device available");
+    crp::FieldDev d;
+    std::memset(&d, 0, sizeof d);
+    fill_modulation_dev(d, *m);
+    hipError_t e = crp::launch_upload_modulation(d, src, src_dtype, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_error(e, "crp_modulation_upload");
+    return ok();
+}
+
 size_t crp_workspace_bytes(int64_t n, int32_t n_fields, int32_t n_params) {
     if (n < 0 || n_fields < 1 || n_params < 1) return 0;
     return crp::ws_layout(n, n_fields, n_params).total;
@@ -206,8 +263,15 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
         return fail(CRP_ERR_INVALID, "%s: param_index is required with several parameter groups", fn);
     if (precision != CRP_PREC_FP64 && precision != CRP_PREC_MIXED_F64ACC && precision != CRP_PREC_MIXED_DFACC)
         return fail(CRP_ERR_INVALID, "%s: unknown precision %d", fn, precision);
+    bool modulated = false;
+    for (int i = 0; i < n_fields; ++i) modulated = modulated || fields[i].modulation != nullptr;
+    if (modulated && precision != CRP_PREC_FP64)
+        return fail(CRP_ERR_UNSUPPORTED, "%s: modulated fields need FP64 precision", fn);
+    if (modulated && fields[0].dtype != CRP_F64 && fields[0].dtype != CRP_F32)
+        return fail(CRP_ERR_UNSUPPORTED, "%s: modulated fields need F64 or F32 storage", fn);
     if (tape) {
         if (precision != CRP_PREC_FP64) return fail(CRP_ERR_UNSUPPORTED, "%s: a tape needs FP64 precision", fn);
+        if (modulated) return fail(CRP_ERR_UNSUPPORTED, "%s: no tape (adjoint) for modulated fields", fn);
         if (n_params > 1 || (n > 0 && p->param_index) || n_fields > 1)
             return fail(CRP_ERR_UNSUPPORTED, "%s: a tape is recorded for one field and one parameter group", fn);
         if (fields[0].dtype != CRP_F64 && fields[0].dtype != CRP_F32)
@@ -260,6 +324,7 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
     if (e != hipSuccess) return device_error(e, fn);
 
     crp::PropArgs a;
+    std::memset(&a, 0, sizeof a);
     a.x = p->x;
     a.y = p->y;
     a.z = p->z;
@@ -283,6 +348,7 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
     a.counters = reinterpret_cast<unsigned long long *>(counters);
     a.refill_threshold = t.refill_threshold;
     a.n_params = n_params;
+    a.modulated = modulated ? 1 : 0;
     a.tape_ckpt = tape ? tape->checkpoints : nullptr;
     a.tape_link = tape ? tape->links : nullptr;
     a.tape_head = tape ? tape->head : nullptr;
@@ -322,6 +388,7 @@ crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *param
     if (st != CRP_OK) return st;
     if (field->dtype != CRP_F64 && field->dtype != CRP_F32)
         return fail(CRP_ERR_UNSUPPORTED, "%s: the adjoint reads F64 or F32 grids", fn);
+    if (field->modulation) return fail(CRP_ERR_UNSUPPORTED, "%s: no adjoint for modulated fields", fn);
     if (!params) return fail(CRP_ERR_INVALID, "%s: null params", fn);
     st = check_params(params, 1, 0);
     if (st != CRP_OK) return st;

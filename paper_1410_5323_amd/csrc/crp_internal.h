@@ -12,7 +12,7 @@
 
 namespace crp {
 
-// Device descriptor of one field grid (128 bytes).
+// Device descriptor of one field grid (192 bytes).
 struct FieldDev {
     const void *data;
     int32_t n[3];          // nodes per axis
@@ -23,9 +23,17 @@ struct FieldDev {
     uint32_t sx, sy;       // LINEAR: node strides of the padded grid, (n1+1)(n2+1) and (n2+1)
     uint32_t cy, cx;       // CELL8: cell strides n2 and n1*n2
     int32_t dtype, layout;
-    int32_t pad_[10];
+    // modulation (mod_data NULL: none): padded [m0+1][m1+1][m2+1] scalars
+    const void *mod_data;
+    int32_t mod_n[3];
+    int32_t mod_pow2;
+    double mod_origin[3];
+    double mod_inv_spacing;
+    uint32_t mod_sx, mod_sy;
+    int32_t mod_dtype;
+    int32_t pad_[9];
 };
-static_assert(sizeof(FieldDev) == 128, "FieldDev layout");
+static_assert(sizeof(FieldDev) == 192, "FieldDev layout");
 
 // Device descriptor of one parameter group (128 bytes).
 struct ParamsDev {
@@ -43,7 +51,7 @@ static_assert(sizeof(ParamsDev) == 128, "ParamsDev layout");
 
 // Workspace layout (offsets in bytes from the 256-byte aligned base).
 //   [0, 256)                 control: queue head (uint64 at 0)
-//   [256, 256 + 128*nf)      FieldDev table
+//   [256, 256 + 192*nf)      FieldDev table
 //   then 128*np              ParamsDev table
 //   then 4*n                 order (int32 particle indices, rigidity buckets ascending)
 //   then 4*(NBUCKET+1)*2     bucket counts and cursors
@@ -57,8 +65,8 @@ inline WsLayout ws_layout(int64_t n, int32_t nf, int32_t np) {
     auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
     WsLayout w;
     w.fields = 256;
-    w.params = up(w.fields + 128 * size_t(nf));
-    w.order = up(w.params + 128 * size_t(np));
+    w.params = up(w.fields + sizeof(FieldDev) * size_t(nf));
+    w.order = up(w.params + sizeof(ParamsDev) * size_t(np));
     w.buckets = up(w.order + 4 * size_t(n > 0 ? n : 0));
     w.total = up(w.buckets + 8 * size_t(NBUCKET + 1));
     return w;
@@ -87,6 +95,7 @@ struct PropArgs {
     int32_t tape_k;                  // checkpoint interval
     int32_t refill_threshold;
     int32_t n_params;
+    int32_t modulated;               // some field carries a modulation grid
 };
 
 // Kernel arguments of the adjoint kernel.
@@ -137,6 +146,7 @@ hipError_t launch_propagate_mixed(const PropArgs &a, int dtype, int layout, bool
                                   int blocks, int block_size, hipStream_t s);
 hipError_t launch_adjoint_fp64(const AdjArgs &a, int blocks, hipStream_t s);
 hipError_t launch_order_by_steps(const double *fin, int64_t n, int32_t *order, unsigned int *buckets, hipStream_t s);
+hipError_t launch_upload_modulation(const FieldDev &f, const void *src, int src_dtype, hipStream_t s);
 hipError_t launch_upload(const FieldDev &f, const void *src, int src_dtype, void *dst, hipStream_t s);
 hipError_t launch_selftest(const double *in, double *out, int64_t n, int op, hipStream_t s);
 hipError_t launch_gather_bench(const FieldDev &F, int64_t lanes, int64_t lookups, double spread, uint32_t seed,

@@ -203,7 +203,7 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
 
 // One loop iteration of a working lane.  Returns a status != ACTIVE when the
 // particle ended (its result already stored).
-template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE>
+template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE, bool MOD>
 __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, CellCache<T> &cache, EventLDS &e,
                                        int &flags) {
     const int t = threadIdx.x;
@@ -211,7 +211,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
     const int fid = MULTI ? P.field_index : 0;
     const FieldDev &F = a.fields[fid];
     double y5[6], ex, eu;
-    ck_eval<T, LAYOUT, CACHE>(F, fid, cache, s.kap, s.y, s.h, y5, ex, eu);
+    ck_eval<T, LAYOUT, CACHE, NoStageRecord, MOD>(F, fid, cache, s.kap, s.y, s.h, y5, ex, eu);
     flags = F_EVAL;
 
     if (s.mode == MODE_NORMAL) {
@@ -332,7 +332,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
 #define CRP_FP64_MIN_WAVES 2
 #endif
 
-template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE>
+template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE, bool MOD>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CRP_FP64_MIN_WAVES, 8)))
 k_propagate_fp64(PropArgs a) {
     const int lane = threadIdx.x & 63;
@@ -378,7 +378,7 @@ k_propagate_fp64(PropArgs a) {
         n_iter++;
         int flags = 0;
         if (pid >= 0) {
-            int st = advance<T, LAYOUT, MULTI, CACHE, TAPE>(a, pid, s, cache, ev, flags);
+            int st = advance<T, LAYOUT, MULTI, CACHE, TAPE, MOD>(a, pid, s, cache, ev, flags);
             if (st != CRP_ST_ACTIVE) pid = -1;
         }
         n_eval += __popcll(__ballot(flags & F_EVAL));
@@ -402,25 +402,31 @@ k_propagate_fp64(PropArgs a) {
     }
 }
 
+template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE, bool MOD>
+hipError_t launch_one(const PropArgs &a, int blocks, int bs, hipStream_t s) {
+    hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, MULTI, CACHE, TAPE, MOD>), dim3(blocks), dim3(bs), 0, s, a);
+    return hipGetLastError();
+}
+
 template <class T, int LAYOUT, bool MULTI>
 hipError_t launch_c(const PropArgs &a, bool cache, int blocks, int bs, hipStream_t s) {
+    constexpr bool wide = std::is_same<T, double>::value || std::is_same<T, float>::value;
     if (a.tape_ckpt) {
-        // taped runs (for the adjoint): one field, FP64 or FP32 storage
-        if constexpr (!MULTI && (std::is_same<T, double>::value || std::is_same<T, float>::value)) {
-            if (cache)
-                hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, false, true, true>), dim3(blocks), dim3(bs), 0, s, a);
-            else
-                hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, false, false, true>), dim3(blocks), dim3(bs), 0, s,
-                                   a);
-            return hipGetLastError();
-        }
+        // taped runs (for the adjoint): one unmodulated field, FP64 or FP32 storage
+        if constexpr (!MULTI && wide)
+            return cache ? launch_one<T, LAYOUT, false, true, true, false>(a, blocks, bs, s)
+                         : launch_one<T, LAYOUT, false, false, true, false>(a, blocks, bs, s);
         return hipErrorInvalidValue;
     }
-    if (cache)
-        hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, MULTI, true, false>), dim3(blocks), dim3(bs), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, MULTI, false, false>), dim3(blocks), dim3(bs), 0, s, a);
-    return hipGetLastError();
+    if (a.modulated) {
+        // modulated fields: FP64 or FP32 storage
+        if constexpr (wide)
+            return cache ? launch_one<T, LAYOUT, MULTI, true, false, true>(a, blocks, bs, s)
+                         : launch_one<T, LAYOUT, MULTI, false, false, true>(a, blocks, bs, s);
+        return hipErrorInvalidValue;
+    }
+    return cache ? launch_one<T, LAYOUT, MULTI, true, false, false>(a, blocks, bs, s)
+                 : launch_one<T, LAYOUT, MULTI, false, false, false>(a, blocks, bs, s);
 }
 
 template <class T>

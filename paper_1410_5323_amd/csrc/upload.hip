@@ -8,6 +8,7 @@
 //         padded with zeros to 32 values (one 128-byte line for FP32).
 // Values are divided by value_scale in FP64, then rounded to nearest even:
 // FP64 -> FP32 directly; FP16/BF16 from the FP32 value.
+// Modulation grids (scalars) are stored like LINEAR with one component.
 #include "crp_device.h"
 
 namespace crp {
@@ -87,6 +88,32 @@ hipError_t launch_ts(const FieldDev &f, const S *src, void *dst, hipStream_t s) 
     return hipGetLastError();
 }
 
+// Modulation grid: source C-order [m0][m1][m2] scalars, stored padded
+// (m0+1)(m1+1)(m2+1) with the wrap, rounded to nearest even into T.
+template <class T, class S>
+__global__ void k_upload_mod(FieldDev f, const S *src, T *dst, uint64_t total) {
+    const uint64_t n1p = (uint64_t)f.mod_n[1] + 1, n2p = (uint64_t)f.mod_n[2] + 1;
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t k = e % n2p;
+        uint64_t t = e / n2p;
+        uint64_t j = t % n1p;
+        uint64_t i = t / n1p;
+        uint64_t si = i % (uint64_t)f.mod_n[0], sj = j % (uint64_t)f.mod_n[1], sk = k % (uint64_t)f.mod_n[2];
+        dst[e] = from_scaled<T>((double)src[(si * f.mod_n[1] + sj) * f.mod_n[2] + sk]);
+    }
+}
+
+template <class T, class S>
+hipError_t launch_mod(const FieldDev &f, const S *src, hipStream_t s) {
+    uint64_t total = ((uint64_t)f.mod_n[0] + 1) * ((uint64_t)f.mod_n[1] + 1) * ((uint64_t)f.mod_n[2] + 1);
+    uint64_t nb = (total + 255) / 256;
+    unsigned blocks = (unsigned)(nb < 65536 ? nb : 65536);
+    hipLaunchKernelGGL((k_upload_mod<T, S>), dim3(blocks), dim3(256), 0, s, f, src,
+                       static_cast<T *>(const_cast<void *>(f.mod_data)), total);
+    return hipGetLastError();
+}
+
 template <class S>
 hipError_t launch_s(const FieldDev &f, const S *src, void *dst, hipStream_t s) {
     switch (f.dtype) {
@@ -99,6 +126,17 @@ hipError_t launch_s(const FieldDev &f, const S *src, void *dst, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t launch_upload_modulation(const FieldDev &f, const void *src, int src_dtype, hipStream_t s) {
+    const bool d64 = f.mod_dtype == CRP_F64;
+    if (src_dtype == CRP_F64)
+        return d64 ? launch_mod<double, double>(f, static_cast<const double *>(src), s)
+                   : launch_mod<float, double>(f, static_cast<const double *>(src), s);
+    if (src_dtype == CRP_F32)
+        return d64 ? launch_mod<double, float>(f, static_cast<const float *>(src), s)
+                   : launch_mod<float, float>(f, static_cast<const float *>(src), s);
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_upload(const FieldDev &f, const void *src, int src_dtype, void *dst, hipStream_t s) {
     if (src_dtype == CRP_F64) return launch_s<double>(f, static_cast<const double *>(src), dst, s);

@@ -38,7 +38,8 @@ def test_every_declared_symbol_is_exported(crp):
 
 
 def test_struct_sizes_match_header(crp):
-    assert C.sizeof(crp.crp_field) == 4 * 6 + 8 * 3 + 8 + 8 + 8
+    assert C.sizeof(crp.crp_field) == 4 * 6 + 8 * 3 + 8 + 8 + 8 + 8
+    assert C.sizeof(crp.crp_modulation) == 4 * 4 + 8 * 3 + 8 + 8
     assert C.sizeof(crp.crp_params) == 8 * 3 + 8 * 3 + 8 + 8 + 8 + 8
     assert C.sizeof(crp.crp_particles) == 16 * 8
     assert C.sizeof(crp.crp_tuning) == 32
@@ -183,3 +184,40 @@ def test_tape_and_adjoint_reject_bad_arguments_without_device(crp):
     assert adj(params=crp.make_params(0.0, 0.01, 1.0, l_max=10.0)) == crp.CRP_ERR_INVALID
     assert adj() == crp.CRP_ERR_WORKSPACE
     assert adj(n=0) == crp.CRP_OK
+
+
+def test_modulation_descriptor_checks(crp):
+    L = crp.lib()
+    m = crp.crp_modulation()
+    m.n[0], m.n[1], m.n[2] = 10, 12, 14
+    m.dtype = crp.CRP_F32
+    m.spacing = 0.3
+    assert L.crp_modulation_bytes(C.byref(m)) == 11 * 13 * 15 * 4
+    m.dtype = crp.CRP_F16
+    assert L.crp_modulation_bytes(C.byref(m)) == 0
+    m.dtype = crp.CRP_F64
+    assert L.crp_modulation_bytes(C.byref(m)) == 11 * 13 * 15 * 8
+    assert L.crp_modulation_upload(C.byref(m), 0x1000, crp.CRP_F64, None) == crp.CRP_ERR_INVALID  # no data
+    m.data = 0x100000
+    assert L.crp_modulation_upload(C.byref(m), 0x100008, crp.CRP_F64, None) == crp.CRP_ERR_INVALID  # overlap
+    m.spacing = -1.0
+    assert L.crp_modulation_bytes(C.byref(m)) == 0
+    # a modulated field: mixed precision, tape and adjoint are refused before any device work
+    m.spacing = 0.3
+    f = _field(crp)
+    f.data = 0x1000
+    f.modulation = C.pointer(m)
+    farr = (crp.crp_field * 1)(f)
+    parr = (crp.crp_params * 1)(crp.make_params(1e-4, 0.01, 1.0, l_max=10.0))
+    parts = crp.crp_particles(**{k: 0x2000 for k in crp._PARTICLE_FIELDS})
+    parts.param_index = None
+    assert L.crp_propagate(farr, 1, parr, 1, C.byref(parts), 10, None, crp.CRP_PREC_MIXED_F64ACC, None, None, None,
+                           0, None) == crp.CRP_ERR_UNSUPPORTED
+    tape = crp.crp_tape(0x3000, 0x4000, 0x5000, 0x5800, 100, 64, 0)
+    assert L.crp_propagate(farr, 1, parr, 1, C.byref(parts), 10, C.byref(tape), 0, None, None, None, 0,
+                           None) == crp.CRP_ERR_UNSUPPORTED
+    assert L.crp_propagate(farr, 1, parr, 1, C.byref(parts), 10, None, 0, None, None, None, 0,
+                           None) == crp.CRP_ERR_WORKSPACE
+    m.data = None
+    assert L.crp_propagate(farr, 1, parr, 1, C.byref(parts), 10, None, 0, None, None, None, 0,
+                           None) == crp.CRP_ERR_INVALID
