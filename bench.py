@@ -7,7 +7,8 @@ FP32 Kolmogorov grid (spacing 50 kpc, l_min 100 kpc, l_max 5 Mpc, B_rms 1 nG),
 tolerance 1e-4, steps 1 kpc .. 1 Mpc, stop at the r = 20 Mpc sphere or at
 1 Gpc of path.  A step of the benchmark propagates every particle until it
 stops.  Other workloads: --workload small_fp64_32cube | batched_64x64cube |
-precision_1024cube | adjoint_128cube.
+precision_1024cube | adjoint_128cube | modulated_256cube (the production
+vector grid times a 440^3 modulation grid at 300 kpc, section 3.2).
 
 Prints one JSON line: particle-steps/s (accepted Cash-Karp steps per second of
 the whole job), the lookup roofline of the propagation kernel (algorithmic
@@ -62,6 +63,17 @@ def angle(a, b):
     return np.arctan2(np.linalg.norm(np.cross(a, b), axis=1), np.sum(a * b, axis=1))
 
 
+def build_modulation(w):
+    """The modulation grid of a modulated workload (numpy FP32), else None."""
+    import numpy as np
+
+    import crp_inputs as ci
+    if not w.mod_n:
+        return None
+    _, _, rs = ci.config_seeds(w.index)
+    return ci.lognormal_modulation(w.mod_n, w.mod_spacing, w.mod_l_corr, w.mod_sigma, rs, dtype=np.float32)
+
+
 def build_inputs(w, n_override):
     """Field grids (numpy, FP32 or FP64), per-group stop radii and the particle list."""
     import numpy as np
@@ -84,7 +96,7 @@ def build_inputs(w, n_override):
     return grids, radii, P
 
 
-def cpu_baseline(grids, radii, w, P, sample: int):
+def cpu_baseline(grids, radii, w, P, sample: int, modulation=None):
     """The oracle, as it stands, on the first `sample` particles, all host cores."""
     import numpy as np
 
@@ -104,7 +116,8 @@ def cpu_baseline(grids, radii, w, P, sample: int):
     for gi in np.unique(groups):
         sel = np.nonzero(groups == gi)[0]
         prm = O.params_array(w.tol, w.h_min, w.h_max, radius=radii[gi], l_max=w.max_length)
-        r = O.propagate(O.Grid(grids[gi], w.spacing), prm, P["pos"][sel], P["dir"][sel], P["energy"][sel],
+        mod = None if modulation is None else O.Modulation(modulation, w.mod_spacing, (w.mod_origin,) * 3)
+        r = O.propagate(O.Grid(grids[gi], w.spacing, modulation=mod), prm, P["pos"][sel], P["dir"][sel], P["energy"][sel],
                         P["charge"][sel], nthreads=threads)
         for k in out:
             out[k][sel] = r[k]
@@ -268,7 +281,9 @@ def main():
     ap.add_argument("--mixed-grid-dtype", default="f16", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--block-size", type=int, default=256)
-    ap.add_argument("--blocks-per-cu", type=int, default=4)
+    ap.add_argument("--blocks-per-cu", type=int, default=None,
+                    help="persistent blocks per CU (default 2 for the FP64 kernel, whose occupancy is 2 waves/SIMD; "
+                         "4 for the mixed kernel)")
     ap.add_argument("--refill-threshold", type=int, default=32)
     ap.add_argument("--cache-cells", type=int, default=0, help="1 on, -1 off, 0 automatic")
     ap.add_argument("--no-order", action="store_true")
@@ -329,8 +344,11 @@ def main():
     state = crp.clone_particles(pristine)
     ws = torch.empty(crp.crp_workspace_bytes(n, len(grids), len(params)), dtype=torch.uint8, device=dev)
     counters = torch.zeros(crp.NCOUNTERS, dtype=torch.int64, device=dev)
-    tuning = crp.make_tuning(args.block_size, args.blocks_per_cu, args.refill_threshold,
-                             0 if args.no_order else 1, args.cache_cells)
+    bpc = args.blocks_per_cu if args.blocks_per_cu is not None else (2 if prec == 0 else 4)
+    tuning = crp.make_tuning(args.block_size, bpc, args.refill_threshold, 0 if args.no_order else 1,
+                             args.cache_cells)
+    mixed_tuning = crp.make_tuning(args.block_size, args.blocks_per_cu if args.blocks_per_cu is not None else 4,
+                                   args.refill_threshold, 0 if args.no_order else 1, args.cache_cells)
 
     def timed(fields, precision, tun, steps, warmup, label):
         """Warm-up passes, then `steps` timed passes of the whole hot path."""
@@ -372,7 +390,9 @@ def main():
         return {"elapsed": elapsed, "launch_ms": launch_ms, "counters": counters.cpu().numpy().astype(np.int64),
                 "host": crp.particles_to_host(state)}
 
-    fields = [crp.make_field(g, w.spacing, dtype=gdt_name, layout=layout) for g in grids]
+    mod_np = build_modulation(w)
+    mod = None if mod_np is None else crp.make_modulation(mod_np, w.mod_spacing, origin=(w.mod_origin,) * 3)
+    fields = [crp.make_field(g, w.spacing, dtype=gdt_name, layout=layout, modulation=mod) for g in grids]
     tuned = None
     if use_tuner:
         from paper_1410_5323_amd.autotune import autotune
@@ -417,8 +437,10 @@ def main():
                    "grid_spacing_mpc": w.spacing, "layout": layout, "tol": w.tol,
                    "h_min_mpc": w.h_min, "h_max_mpc": w.h_max,
                    "obs_radius_mpc": [min(radii), max(radii)] if batched else w.obs_radius,
+                   "modulation": None if mod is None else f"{w.mod_n}^3 f32, {w.mod_spacing} Mpc, log-normal "
+                                                          f"sigma {w.mod_sigma}, correlation {w.mod_l_corr} Mpc",
                    "l_max_mpc": w.max_length, "precision": args.precision, "hipgraph": use_graph,
-                   "tuning": tuned or {"block_size": args.block_size, "blocks_per_cu": args.blocks_per_cu,
+                   "tuning": tuned or {"block_size": args.block_size, "blocks_per_cu": bpc,
                                        "refill_threshold": args.refill_threshold,
                                        "order_by_rigidity": not args.no_order, "cache_cells": args.cache_cells}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -441,10 +463,10 @@ def main():
     }
 
     mixed_host = None
-    if prec == 0 and not args.no_mixed and not batched:
+    if prec == 0 and not args.no_mixed and not batched and mod is None:
         mdt = args.mixed_grid_dtype
         mfields = [crp.make_field(g, w.spacing, dtype=mdt, layout=layout) for g in grids]
-        mix = timed(mfields, PRECISIONS["mixed_f64acc"], tuning, args.steps, 1, f"mixed_f64acc/{mdt}/{layout}")
+        mix = timed(mfields, PRECISIONS["mixed_f64acc"], mixed_tuning, args.steps, 1, f"mixed_f64acc/{mdt}/{layout}")
         del mfields
         torch.cuda.empty_cache()
         mixed_host = mix["host"]
@@ -455,7 +477,7 @@ def main():
         # noise floor of the FP64 path on the error sample: the same run with each
         # initial direction rotated by 1e-7 rad
         m = min(args.cpu_sample, n)
-        pf = [crp.make_field(g, w.spacing, dtype=gdt_name, layout=layout) for g in grids]
+        pf = [crp.make_field(g, w.spacing, dtype=gdt_name, layout=layout, modulation=mod) for g in grids]
         probe = crp.particles_to_device(P["pos"][:m], rotate_directions(P["dir"][:m], 1e-7), P["energy"][:m],
                                         P["charge"][:m])
         crp.crp_propagate(pf, params[:1], probe, tuning=tuning)
@@ -481,7 +503,7 @@ def main():
     if not args.no_cpu_baseline:
         m = min(args.cpu_sample, n)
         log(f"bench: timing the CPU oracle on the first {m} particles")
-        cb, ref = cpu_baseline(grids, radii, w, P, m)
+        cb, ref = cpu_baseline(grids, radii, w, P, m, modulation=mod_np)
         result["cpu_baseline"] = cb
         if prec == 0:
             g = {k: v[:m] for k, v in host.items()}
