@@ -407,6 +407,8 @@ def main():
     evals = int(c[0])
     avg_launch_s = float(np.mean(head["launch_ms"])) / 1e3
     bytes_per_eval = 6 * 8 * 3 * BYTES_PER_VALUE[gdt_name]
+    if mod is not None:
+        bytes_per_eval += 6 * 8 * 4  # the modulation grid's 8 FP32 corners per lookup
     evals_per_launch = evals / args.steps
     achieved = bytes_per_eval * evals_per_launch / avg_launch_s / 1e9
     traffic = measured_traffic(w.name, layout) if prec == 0 else None
