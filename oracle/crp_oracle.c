@@ -32,7 +32,13 @@
  *     Norsett & Wanner II.4);
  *   - event location of the sphere crossing by the Illinois variant of
  *     regula falsi (Dowell & Jarratt 1971) on the Cash-Karp step map, keeping
- *     the bracket end outside the sphere as the crossing point.
+ *     the bracket end outside the sphere as the crossing point;
+ *   - an optional reflective box (section 4 uses reflective boundaries): the
+ *     distance to its nearest face bids like the sphere distance, and a step
+ *     that ends outside is mirrored on the face (x -> 2 face - x, the
+ *     direction component negated) after the sphere test;
+ *   - an optional modulation grid (section 3.2, modulated grids) multiplying
+ *     the vector grid's value, interpolated the same way.
  *
  * Arithmetic is IEEE FP64, round to nearest even, compiled with
  * -ffp-contract=off; fused multiply-adds appear only where fma() is written.
@@ -276,7 +282,25 @@ typedef struct {
     double radius;        /* <= 0: no observer sphere */
     double l_max;         /* +inf: no length limit */
     int64_t max_steps;    /* accepted steps allowed in this call; 0 = no limit */
+    int reflect;          /* reflective box on */
+    double box_lo[3], box_hi[3];
 } params_t;
+
+/* Reflective box (the example of section 4 uses reflective boundaries): a
+ * particle whose accepted step ends outside the box on an axis is mirrored on
+ * that face, position x -> 2 face - x and that direction component negated. */
+static void reflect_state(const params_t *p, double y[6])
+{
+    for (int a = 0; a < 3; ++a) {
+        if (y[a] > p->box_hi[a]) {
+            y[a] = 2.0 * p->box_hi[a] - y[a];
+            y[3 + a] = -y[3 + a];
+        } else if (y[a] < p->box_lo[a]) {
+            y[a] = 2.0 * p->box_lo[a] - y[a];
+            y[3 + a] = -y[3 + a];
+        }
+    }
+}
 
 static double sphere_g(const params_t *p, const double x[3])
 {
@@ -351,6 +375,13 @@ static int propagate_one(const grid_t *g, const params_t *p, double y[6], double
             double d0 = y[0] - p->center[0], d1 = y[1] - p->center[1], d2 = y[2] - p->center[2];
             double dist = p->radius - sqrt(d0 * d0 + d1 * d1 + d2 * d2);
             if (dist < h) h = dist;
+        }
+        if (p->reflect) {         /* the distance to the nearest face of the box bids too */
+            for (int a = 0; a < 3; ++a) {
+                double dlo = y[a] - p->box_lo[a], dhi = p->box_hi[a] - y[a];
+                if (dlo < h) h = dlo;
+                if (dhi < h) h = dhi;
+            }
         }
         if (h < p->h_min) h = p->h_min;
         int binding = 0;
@@ -471,6 +502,8 @@ static int propagate_one(const grid_t *g, const params_t *p, double y[6], double
             }
             return ST_ARRIVED;
         }
+        if (p->reflect)
+            reflect_state(p, ynew);
         memcpy(y, ynew, sizeof ynew);
         *L = Lnew;
         if (lmax_on && *L >= p->l_max) {
@@ -603,6 +636,13 @@ int oracle_propagate(const void *grid, int dtype, int64_t n0, int64_t n1, int64_
     p.center[2] = prm[5];
     p.radius = prm[6];
     p.l_max = prm[7];
+    p.reflect = prm[14] != 0.0;
+    for (int a = 0; a < 3; ++a) {
+        p.box_lo[a] = prm[8 + a];
+        p.box_hi[a] = prm[11 + a];
+    }
+    if (p.reflect && !(p.box_lo[0] < p.box_hi[0] && p.box_lo[1] < p.box_hi[1] && p.box_lo[2] < p.box_hi[2]))
+        return -1;
     p.max_steps = max_steps;
     if (!(p.tol > 0.0) || !(p.h_min > 0.0) || !(p.h_max >= p.h_min) || isnan(p.l_max) ||
         !(p.l_max > 0.0) || (!isfinite(p.l_max) && max_steps <= 0))
@@ -669,6 +709,15 @@ int64_t oracle_propagate_taped(const void *grid, int dtype, int64_t n0, int64_t 
     p.center[2] = prm[5];
     p.radius = prm[6];
     p.l_max = prm[7];
+    p.reflect = prm[14] != 0.0;
+    for (int a = 0; a < 3; ++a) {
+        p.box_lo[a] = prm[8 + a];
+        p.box_hi[a] = prm[11 + a];
+    }
+    if (p.reflect && !(p.box_lo[0] < p.box_hi[0] && p.box_lo[1] < p.box_hi[1] && p.box_lo[2] < p.box_hi[2]))
+        return -1;
+    if (p.reflect) /* the replayed map has no mirror: no tape for reflective boxes */
+        return -1;
     p.max_steps = 0;
     if (!isfinite(p.l_max))
         return -1;

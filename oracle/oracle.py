@@ -135,9 +135,12 @@ def fixed_steps(grid: Grid, kap: float, y, h: float, nsteps: int) -> np.ndarray:
     return y
 
 
-def params_array(tol, h_min, h_max, center=(0.0, 0.0, 0.0), radius=0.0, l_max=math.inf):
-    return np.array([tol, h_min, h_max, center[0], center[1], center[2], radius, l_max],
-                    dtype=np.float64)
+def params_array(tol, h_min, h_max, center=(0.0, 0.0, 0.0), radius=0.0, l_max=math.inf, box=None):
+    """Parameter block of the oracle: tolerance, step limits, observer sphere,
+    length limit and an optional reflective box ((lo x, y, z), (hi x, y, z))."""
+    lo, hi, on = ((0.0,) * 3, (0.0,) * 3, 0.0) if box is None else (box[0], box[1], 1.0)
+    return np.array([tol, h_min, h_max, center[0], center[1], center[2], radius, l_max,
+                     lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], on], dtype=np.float64)
 
 
 def propagate(grid: Grid, prm: np.ndarray, pos, dir, energy, charge, length=None, h_next=None,
