@@ -8,7 +8,9 @@ tolerance 1e-4, steps 1 kpc .. 1 Mpc, stop at the r = 20 Mpc sphere or at
 1 Gpc of path.  A step of the benchmark propagates every particle until it
 stops.  Other workloads: --workload small_fp64_32cube | batched_64x64cube |
 precision_1024cube | adjoint_128cube | modulated_256cube (the production
-vector grid times a 440^3 modulation grid at 300 kpc, section 3.2).
+vector grid times a 440^3 modulation grid at 300 kpc, section 3.2) |
+reflective_132box (that modulated field inside a reflective 132 Mpc box, the
+particles starting uniformly in it, 100 Mpc of path; section 4).
 
 Prints one JSON line: particle-steps/s (accepted Cash-Karp steps per second of
 the whole job), the lookup roofline of the propagation kernel (algorithmic
@@ -91,6 +93,8 @@ def build_inputs(w, n_override):
     else:
         n = w.n_particles if n_override is None else n_override
         P = ci.isotropic_particles(n, w.e_min, w.e_max, w.charges, ps, charge_rule=w.charge_rule)
+        if w.reflect_box is not None:
+            P["pos"] = ci.box_positions(n, w.reflect_box[0], w.reflect_box[1], ci.position_seed(w.index))
         grids = [ci.kolmogorov_field(w.grid_n, w.spacing, w.l_min, w.l_max, w.b_rms, fs, dtype=gdt)]
         radii = [w.obs_radius]
     return grids, radii, P
@@ -115,7 +119,7 @@ def cpu_baseline(grids, radii, w, P, sample: int, modulation=None):
     t0 = time.perf_counter()
     for gi in np.unique(groups):
         sel = np.nonzero(groups == gi)[0]
-        prm = O.params_array(w.tol, w.h_min, w.h_max, radius=radii[gi], l_max=w.max_length)
+        prm = O.params_array(w.tol, w.h_min, w.h_max, radius=radii[gi], l_max=w.max_length, box=w.reflect_box)
         mod = None if modulation is None else O.Modulation(modulation, w.mod_spacing, (w.mod_origin,) * 3)
         r = O.propagate(O.Grid(grids[gi], w.spacing, modulation=mod), prm, P["pos"][sel], P["dir"][sel], P["energy"][sel],
                         P["charge"][sel], nthreads=threads)
@@ -337,8 +341,8 @@ def main():
     prec = PRECISIONS[args.precision]
     gdt_name = args.grid_dtype or ("f16" if prec != 0 else ("f64" if w.grid_dtype == "f64" else "f32"))
     layout = args.layout or ("cell8" if w.grid_n <= 512 else "linear")
-    params = [crp.make_params(w.tol, w.h_min, w.h_max, obs_radius=radii[r], l_max=w.max_length, field_index=r)
-              for r in range(len(grids))]
+    params = [crp.make_params(w.tol, w.h_min, w.h_max, obs_radius=radii[r], l_max=w.max_length, field_index=r,
+                              box=w.reflect_box) for r in range(len(grids))]
     pristine = crp.particles_to_device(P["pos"], P["dir"], P["energy"], P["charge"], mass=P["mass"],
                                        param_index=P.get("param_index"))
     state = crp.clone_particles(pristine)
@@ -441,7 +445,8 @@ def main():
                    "obs_radius_mpc": [min(radii), max(radii)] if batched else w.obs_radius,
                    "modulation": None if mod is None else f"{w.mod_n}^3 f32, {w.mod_spacing} Mpc, log-normal "
                                                           f"sigma {w.mod_sigma}, correlation {w.mod_l_corr} Mpc",
-                   "l_max_mpc": w.max_length, "precision": args.precision, "hipgraph": use_graph,
+                   "reflective_box_mpc": w.reflect_box, "l_max_mpc": w.max_length, "precision": args.precision,
+                   "hipgraph": use_graph,
                    "tuning": tuned or {"block_size": args.block_size, "blocks_per_cu": bpc,
                                        "refill_threshold": args.refill_threshold,
                                        "order_by_rigidity": not args.no_order, "cache_cells": args.cache_cells}},
@@ -465,7 +470,7 @@ def main():
     }
 
     mixed_host = None
-    if prec == 0 and not args.no_mixed and not batched and mod is None:
+    if prec == 0 and not args.no_mixed and not batched and mod is None and w.reflect_box is None:
         mdt = args.mixed_grid_dtype
         mfields = [crp.make_field(g, w.spacing, dtype=mdt, layout=layout) for g in grids]
         mix = timed(mfields, PRECISIONS["mixed_f64acc"], mixed_tuning, args.steps, 1, f"mixed_f64acc/{mdt}/{layout}")

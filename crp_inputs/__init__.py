@@ -12,13 +12,13 @@ mixed composition of H, He, N and Fe nuclei (section 4, text after Eq. (1)).
 from .configs import CONFIGS, Workload, get_config, mass_number
 from .kolmogorov import kolmogorov_field, coherence_length, spectral_mask
 from .modulation import lognormal_modulation
-from .particles import isotropic_particles, realisation_table, realisation_particles
+from .particles import box_positions, isotropic_particles, realisation_table, realisation_particles
 from .quantize import round_to_bf16, round_to_f16
-from .seeds import config_seeds
+from .seeds import config_seeds, position_seed
 
 __all__ = [
     "CONFIGS", "Workload", "get_config", "mass_number",
     "kolmogorov_field", "coherence_length", "spectral_mask", "lognormal_modulation",
-    "isotropic_particles", "realisation_table", "realisation_particles",
-    "config_seeds", "round_to_f16", "round_to_bf16",
+    "box_positions", "isotropic_particles", "realisation_table", "realisation_particles",
+    "config_seeds", "position_seed", "round_to_f16", "round_to_bf16",
 ]

@@ -1,4 +1,4 @@
-"""The five workloads: sizes, field parameters, step limits and stops.
+"""The workloads: sizes, field parameters, step limits and stops.
 
 Values follow the workload descriptions of this project; entries marked
 "chosen" fill parameters those descriptions leave open.  Lengths are in Mpc,
@@ -51,11 +51,20 @@ class Workload:
     mod_spacing: float = 0.0     # Mpc
     mod_l_corr: float = 0.0      # correlation length of the log-normal modulation, Mpc
     mod_sigma: float = 0.0       # standard deviation of log m
+    reflect_half: float = 0.0    # > 0: reflective box [-h, h]^3 (Mpc); the particles start uniformly in it
 
     @property
     def mod_origin(self) -> float:
         """The modulation grid is centred on the origin (where the particles start)."""
         return -0.5 * self.mod_n * self.mod_spacing
+
+    @property
+    def reflect_box(self):
+        """((lo x, y, z), (hi x, y, z)) of the reflective box, or None."""
+        if self.reflect_half <= 0.0:
+            return None
+        h = self.reflect_half
+        return ((-h, -h, -h), (h, h, h))
 
     @property
     def box(self) -> float:
@@ -87,6 +96,12 @@ CONFIGS = (
     # log-normal modulation (correlation length 2 Mpc, sigma 1) is chosen.
     Workload("modulated_256cube", 5, 1_000_000, MIXED, 1e18, 1e20, 256, 0.05, 0.1, 5.0, 1.0, "f32",
              1e-4, 0.001, 1.0, 20.0, 1000.0, mod_n=440, mod_spacing=0.3, mod_l_corr=2.0, mod_sigma=1.0),
+    # The paper's example with its reflective boundaries: the modulated field above inside a
+    # reflective box over the modulation grid's 132 Mpc; 1e6 nuclei start uniformly in the box
+    # (uniform sources and the 100 Mpc length limit per call are chosen; no observer sphere).
+    Workload("reflective_132box", 6, 1_000_000, MIXED, 1e18, 1e20, 256, 0.05, 0.1, 5.0, 1.0, "f32",
+             1e-4, 0.001, 1.0, 0.0, 100.0, mod_n=440, mod_spacing=0.3, mod_l_corr=2.0, mod_sigma=1.0,
+             reflect_half=66.0),
 )
 
 

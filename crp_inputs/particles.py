@@ -53,6 +53,14 @@ def isotropic_particles(n: int, e_min: float, e_max: float, charges, seed,
     }
 
 
+def box_positions(n: int, lo, hi, seed) -> np.ndarray:
+    """n start positions (Mpc) drawn uniformly in the box [lo, hi] (per axis)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    return lo + (hi - lo) * rng.random((n, 3))
+
+
 def _mass_vec(charge: np.ndarray) -> np.ndarray:
     """Vectorised ``mass_number``: A = 1 for |Z| = 1, else A = 2|Z|."""
     z = np.abs(charge)

@@ -100,7 +100,12 @@ typedef struct {
     const crp_modulation *modulation;  /* host pointer, NULL for none; FP64 precision only, no tape */
 } crp_field;
 
-/* Bidding and stopping parameters of one particle group (section 3.1). */
+/* Bidding and stopping parameters of one particle group (section 3.1).
+ * Reflective box (the example of section 4 has reflective boundaries): with
+ * reflect = 1 the distance to the nearest face also bids (after the sphere
+ * distance, before the h_min floor), and a particle whose accepted step ends
+ * outside the box on an axis, without arriving at the sphere, is mirrored on
+ * that face: position 2 face - x, that direction component negated. */
 typedef struct {
     double tol;            /* accuracy: error norm per step <= tol, > 0 */
     double h_min, h_max;   /* step limits in Mpc, 0 < h_min <= h_max */
@@ -109,7 +114,8 @@ typedef struct {
     double l_max;          /* length limit, Mpc, > 0; +inf disables it (then max_steps > 0) */
     int64_t max_steps;     /* accepted steps allowed per particle in one call; 0 = no limit */
     int32_t field_index;   /* which entry of the fields array this group uses */
-    int32_t reserved;
+    int32_t reflect;       /* 1: reflective box below (FP64 precision, no tape); 0: none */
+    double box_lo[3], box_hi[3];  /* Mpc, lo < hi on every axis when reflect = 1 */
 } crp_params;
 
 /* Structure-of-arrays particle state; every pointer is [dev] with n entries

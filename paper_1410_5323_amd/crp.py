@@ -47,7 +47,8 @@ class crp_field(C.Structure):
 class crp_params(C.Structure):
     _fields_ = [("tol", C.c_double), ("h_min", C.c_double), ("h_max", C.c_double),
                 ("obs_center", C.c_double * 3), ("obs_radius", C.c_double), ("l_max", C.c_double),
-                ("max_steps", C.c_int64), ("field_index", C.c_int32), ("reserved", C.c_int32)]
+                ("max_steps", C.c_int64), ("field_index", C.c_int32), ("reflect", C.c_int32),
+                ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3)]
 
 
 _PARTICLE_FIELDS = ["x", "y", "z", "ux", "uy", "uz", "energy", "charge", "mass", "length",
@@ -394,8 +395,14 @@ def make_field(values, spacing: float, origin=(0.0, 0.0, 0.0), dtype="f32", layo
 
 
 def make_params(tol, h_min, h_max, obs_radius=0.0, l_max=math.inf, obs_center=(0.0, 0.0, 0.0),
-                max_steps=0, field_index=0) -> crp_params:
+                max_steps=0, field_index=0, box=None) -> crp_params:
+    """One parameter group; ``box`` = ((lo x, y, z), (hi x, y, z)) in Mpc turns on
+    the reflective box (FP64 precision only, no tape)."""
     p = crp_params()
+    if box is not None:
+        p.reflect = 1
+        for i in range(3):
+            p.box_lo[i], p.box_hi[i] = float(box[0][i]), float(box[1][i])
     p.tol, p.h_min, p.h_max = float(tol), float(h_min), float(h_max)
     for i in range(3):
         p.obs_center[i] = float(obs_center[i])

@@ -142,6 +142,11 @@ crp_status check_params(const crp_params *p, int32_t n_fields, int i) {
         return fail(CRP_ERR_INVALID, "params[%d]: h_min below the FP64 resolution of l_max", i);
     if (p->field_index < 0 || p->field_index >= n_fields)
         return fail(CRP_ERR_INVALID, "params[%d]: field_index %d out of range", i, p->field_index);
+    if (p->reflect != 0 && p->reflect != 1) return fail(CRP_ERR_INVALID, "params[%d]: reflect must be 0 or 1", i);
+    if (p->reflect)
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(p->box_lo[a]) || !std::isfinite(p->box_hi[a]) || !(p->box_lo[a] < p->box_hi[a]))
+                return fail(CRP_ERR_INVALID, "params[%d]: reflective box needs finite lo < hi on every axis", i);
     return CRP_OK;
 }
 
@@ -159,6 +164,11 @@ crp::ParamsDev make_params_dev(const crp_params &p) {
     d.field_index = p.field_index;
     d.sphere_on = p.obs_radius > 0.0;
     d.lmax_on = std::isfinite(p.l_max);
+    d.reflect_on = p.reflect != 0;
+    for (int a = 0; a < 3; ++a) {
+        d.box_lo[a] = p.box_lo[a];
+        d.box_hi[a] = p.box_hi[a];
+    }
     return d;
 }
 
@@ -269,9 +279,14 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
         return fail(CRP_ERR_UNSUPPORTED, "%s: modulated fields need FP64 precision", fn);
     if (modulated && fields[0].dtype != CRP_F64 && fields[0].dtype != CRP_F32)
         return fail(CRP_ERR_UNSUPPORTED, "%s: modulated fields need F64 or F32 storage", fn);
+    bool reflective = false;
+    for (int i = 0; i < n_params; ++i) reflective = reflective || params[i].reflect != 0;
+    if (reflective && precision != CRP_PREC_FP64)
+        return fail(CRP_ERR_UNSUPPORTED, "%s: a reflective box needs FP64 precision", fn);
     if (tape) {
         if (precision != CRP_PREC_FP64) return fail(CRP_ERR_UNSUPPORTED, "%s: a tape needs FP64 precision", fn);
         if (modulated) return fail(CRP_ERR_UNSUPPORTED, "%s: no tape (adjoint) for modulated fields", fn);
+        if (reflective) return fail(CRP_ERR_UNSUPPORTED, "%s: no tape (adjoint) with a reflective box", fn);
         if (n_params > 1 || (n > 0 && p->param_index) || n_fields > 1)
             return fail(CRP_ERR_UNSUPPORTED, "%s: a tape is recorded for one field and one parameter group", fn);
         if (fields[0].dtype != CRP_F64 && fields[0].dtype != CRP_F32)
@@ -349,6 +364,7 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
     a.refill_threshold = t.refill_threshold;
     a.n_params = n_params;
     a.modulated = modulated ? 1 : 0;
+    a.reflective = reflective ? 1 : 0;
     a.tape_ckpt = tape ? tape->checkpoints : nullptr;
     a.tape_link = tape ? tape->links : nullptr;
     a.tape_head = tape ? tape->head : nullptr;
@@ -392,6 +408,7 @@ crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *param
     if (!params) return fail(CRP_ERR_INVALID, "%s: null params", fn);
     st = check_params(params, 1, 0);
     if (st != CRP_OK) return st;
+    if (params->reflect) return fail(CRP_ERR_UNSUPPORTED, "%s: no adjoint with a reflective box", fn);
     if (!initial || !tape) return fail(CRP_ERR_INVALID, "%s: null particles or tape", fn);
     if (n < 0 || n > (int64_t)0x7fffffff) return fail(CRP_ERR_INVALID, "%s: n out of range", fn);
     if (tape->every_k < 1 || tape->every_k > 4096) return fail(CRP_ERR_INVALID, "%s: bad tape interval", fn);

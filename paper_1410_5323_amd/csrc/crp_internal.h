@@ -42,17 +42,19 @@ struct ParamsDev {
     double radius, r2;     // r2 = radius * radius
     double l_max;
     int64_t max_steps;
+    double box_lo[3], box_hi[3];  // reflective box faces
     int32_t field_index;
     int32_t sphere_on;     // radius > 0
     int32_t lmax_on;       // l_max finite
-    int32_t pad_[9];
+    int32_t reflect_on;    // reflective box on
+    int32_t pad_[4];
 };
-static_assert(sizeof(ParamsDev) == 128, "ParamsDev layout");
+static_assert(sizeof(ParamsDev) == 160, "ParamsDev layout");
 
 // Workspace layout (offsets in bytes from the 256-byte aligned base).
 //   [0, 256)                 control: queue head (uint64 at 0)
 //   [256, 256 + 192*nf)      FieldDev table
-//   then 128*np              ParamsDev table
+//   then 160*np              ParamsDev table
 //   then 4*n                 order (int32 particle indices, rigidity buckets ascending)
 //   then 4*(NBUCKET+1)*2     bucket counts and cursors
 constexpr int NBUCKET = 256;
@@ -96,6 +98,7 @@ struct PropArgs {
     int32_t refill_threshold;
     int32_t n_params;
     int32_t modulated;               // some field carries a modulation grid
+    int32_t reflective;              // some parameter group has a reflective box
 };
 
 // Kernel arguments of the adjoint kernel.

@@ -80,6 +80,7 @@ __device__ __forceinline__ double sphere_g(const ParamsDev &P, const double x[3]
 
 // Bid of the next step: controller, h_max and sphere distance, floored by
 // h_min; then the remaining length (not floored), which lands exactly on l_max.
+template <bool RFL>
 __device__ __forceinline__ void bid(const ParamsDev &P, Lane &s) {
     double h = s.hctrl;
     if (h > P.h_max) h = P.h_max;
@@ -87,6 +88,15 @@ __device__ __forceinline__ void bid(const ParamsDev &P, Lane &s) {
         double d0 = s.y[0] - P.center[0], d1 = s.y[1] - P.center[1], d2 = s.y[2] - P.center[2];
         double dist = P.radius - sqrt(d0 * d0 + d1 * d1 + d2 * d2);
         if (dist < h) h = dist;
+    }
+    if (RFL && P.reflect_on) {
+        // the distance to the nearest face of the reflective box bids too
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double dlo = s.y[c] - P.box_lo[c], dhi = P.box_hi[c] - s.y[c];
+            if (dlo < h) h = dlo;
+            if (dhi < h) h = dhi;
+        }
     }
     if (h < P.h_min) h = P.h_min;
     s.binding = 0;
@@ -98,6 +108,21 @@ __device__ __forceinline__ void bid(const ParamsDev &P, Lane &s) {
         }
     }
     s.h = h;
+}
+
+// Reflective box: an accepted step that ends outside the box on an axis is
+// mirrored on that face (position 2 face - x, that direction component negated).
+__device__ __forceinline__ void reflect(const ParamsDev &P, double y[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (y[c] > P.box_hi[c]) {
+            y[c] = 2.0 * P.box_hi[c] - y[c];
+            y[3 + c] = -y[3 + c];
+        } else if (y[c] < P.box_lo[c]) {
+            y[c] = 2.0 * P.box_lo[c] - y[c];
+            y[3 + c] = -y[3 + c];
+        }
+    }
 }
 
 // Write the particle's state back (its own slots only).
@@ -136,7 +161,7 @@ enum { F_EVAL = 1, F_ACC = 2, F_REJ = 4, F_EVENT = 8, F_FLOOR = 16 };
 
 // Start particle p in lane state s.  Returns true if it needs steps; false if
 // it was skipped (not ACTIVE) or finished at once (its result is stored).
-template <bool MULTI, bool TAPE>
+template <bool MULTI, bool TAPE, bool RFL>
 __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
     int st = a.status[p];
     if (TAPE) {
@@ -197,13 +222,13 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
     s.kap = ((double)Z * K_LORENTZ) / E;
     s.mode = MODE_NORMAL;
     if (TAPE) tape_checkpoint(a, s);
-    bid(P, s);
+    bid<RFL>(P, s);
     return true;
 }
 
 // One loop iteration of a working lane.  Returns a status != ACTIVE when the
 // particle ended (its result already stored).
-template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE, bool MOD>
+template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE, bool MOD, bool RFL>
 __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, CellCache<T> &cache, EventLDS &e,
                                        int &flags) {
     const int t = threadIdx.x;
@@ -272,6 +297,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
         s.y[3] = y5[3] / un;
         s.y[4] = y5[4] / un;
         s.y[5] = y5[5] / un;
+        if (RFL && P.reflect_on) reflect(P, s.y);
         s.L = Lnew;
         if (P.lmax_on && s.L >= P.l_max) {
             store(a, p, s, s.hctrl, CRP_ST_MAX_LENGTH);
@@ -284,7 +310,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
             return CRP_ST_MAX_STEPS;
         }
         if (TAPE && s.dacc % a.tape_k == 0) tape_checkpoint(a, s);
-        bid(P, s);
+        bid<RFL>(P, s);
         return CRP_ST_ACTIVE;
     }
 
@@ -332,7 +358,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
 #define CRP_FP64_MIN_WAVES 2
 #endif
 
-template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE, bool MOD>
+template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE, bool MOD, bool RFL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CRP_FP64_MIN_WAVES, 8)))
 k_propagate_fp64(PropArgs a) {
     const int lane = threadIdx.x & 63;
@@ -364,7 +390,7 @@ k_propagate_fp64(PropArgs a) {
                 if (q < (unsigned long long)a.n) {
                     int64_t p = a.order ? (int64_t)a.order[q] : (int64_t)q;
                     got = 1;
-                    pid = start<MULTI, TAPE>(a, p, s) ? p : -1;
+                    pid = start<MULTI, TAPE, RFL>(a, p, s) ? p : -1;
                 } else {
                     pid = -2;
                 }
@@ -378,7 +404,7 @@ k_propagate_fp64(PropArgs a) {
         n_iter++;
         int flags = 0;
         if (pid >= 0) {
-            int st = advance<T, LAYOUT, MULTI, CACHE, TAPE, MOD>(a, pid, s, cache, ev, flags);
+            int st = advance<T, LAYOUT, MULTI, CACHE, TAPE, MOD, RFL>(a, pid, s, cache, ev, flags);
             if (st != CRP_ST_ACTIVE) pid = -1;
         }
         n_eval += __popcll(__ballot(flags & F_EVAL));
@@ -402,9 +428,9 @@ k_propagate_fp64(PropArgs a) {
     }
 }
 
-template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE, bool MOD>
+template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE, bool MOD, bool RFL = false>
 hipError_t launch_one(const PropArgs &a, int blocks, int bs, hipStream_t s) {
-    hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, MULTI, CACHE, TAPE, MOD>), dim3(blocks), dim3(bs), 0, s, a);
+    hipLaunchKernelGGL((k_propagate_fp64<T, LAYOUT, MULTI, CACHE, TAPE, MOD, RFL>), dim3(blocks), dim3(bs), 0, s, a);
     return hipGetLastError();
 }
 
@@ -417,6 +443,15 @@ hipError_t launch_c(const PropArgs &a, bool cache, int blocks, int bs, hipStream
             return cache ? launch_one<T, LAYOUT, false, true, true, false>(a, blocks, bs, s)
                          : launch_one<T, LAYOUT, false, false, true, false>(a, blocks, bs, s);
         return hipErrorInvalidValue;
+    }
+    if (a.reflective) {
+        // a reflective box (the cell cache, a tuning option only, is not
+        // instantiated for it); with or without modulation
+        if (a.modulated) {
+            if constexpr (wide) return launch_one<T, LAYOUT, MULTI, false, false, true, true>(a, blocks, bs, s);
+            return hipErrorInvalidValue;
+        }
+        return launch_one<T, LAYOUT, MULTI, false, false, false, true>(a, blocks, bs, s);
     }
     if (a.modulated) {
         // modulated fields: FP64 or FP32 storage
@@ -882,10 +917,10 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
         }
         // one attempt per loop iteration, so a lane's rejections cost the others nothing
         int j = 0;
-        if (m > 0) bid(a.P, s);
+        if (m > 0) bid<false>(a.P, s);
         while (__ballot(j < m) != 0ull) {
             if (j < m && replay_attempt<T, LAYOUT>(a.F, a.P, s, col + (int64_t)j * rstride, a.lanes))
-                if (++j < m) bid(a.P, s);
+                if (++j < m) bid<false>(a.P, s);
         }
         const int mmax = wave_max(m);
         if (event) {

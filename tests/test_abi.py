@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(crp):
 def test_struct_sizes_match_header(crp):
     assert C.sizeof(crp.crp_field) == 4 * 6 + 8 * 3 + 8 + 8 + 8 + 8
     assert C.sizeof(crp.crp_modulation) == 4 * 4 + 8 * 3 + 8 + 8
-    assert C.sizeof(crp.crp_params) == 8 * 3 + 8 * 3 + 8 + 8 + 8 + 8
+    assert C.sizeof(crp.crp_params) == 8 * 3 + 8 * 3 + 8 + 8 + 8 + 8 + 8 * 6
     assert C.sizeof(crp.crp_particles) == 16 * 8
     assert C.sizeof(crp.crp_tuning) == 32
 
@@ -221,3 +221,40 @@ def test_modulation_descriptor_checks(crp):
     m.data = None
     assert L.crp_propagate(farr, 1, parr, 1, C.byref(parts), 10, None, 0, None, None, None, 0,
                            None) == crp.CRP_ERR_INVALID
+
+
+def test_reflective_box_checks(crp):
+    """A reflective box needs lo < hi on every axis and FP64 precision; tapes
+    and the adjoint refuse it, all before any device work."""
+    L = crp.lib()
+    f = _field(crp)
+    f.data = 0x1000
+    farr = (crp.crp_field * 1)(f)
+    parts = crp.crp_particles(**{k: 0x2000 for k in crp._PARTICLE_FIELDS})
+    parts.param_index = None
+    box = ((0.0, 0.0, 0.0), (10.0, 10.0, 10.0))
+
+    def call(p, prec=0, tape=None):
+        q = (crp.crp_params * 1)(p)
+        return L.crp_propagate(farr, 1, q, 1, C.byref(parts), 10, C.byref(tape) if tape else None, prec, None, None,
+                               None, 0, None)
+
+    good = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0, box=box)
+    assert good.reflect == 1 and tuple(good.box_hi) == (10.0, 10.0, 10.0)
+    assert call(good) == crp.CRP_ERR_WORKSPACE  # arguments fine, no workspace
+    for bad_box in [((0.0, 0.0, 0.0), (10.0, 0.0, 10.0)), ((0.0, 0.0, 5.0), (10.0, 10.0, 4.0)),
+                    ((0.0, 0.0, 0.0), (math.inf, 10.0, 10.0)), ((math.nan, 0.0, 0.0), (10.0, 10.0, 10.0))]:
+        assert call(crp.make_params(1e-4, 0.01, 1.0, l_max=10.0, box=bad_box)) == crp.CRP_ERR_INVALID, bad_box
+    odd = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0, box=box)
+    odd.reflect = 2
+    assert call(odd) == crp.CRP_ERR_INVALID
+    assert call(good, prec=crp.CRP_PREC_MIXED_F64ACC) == crp.CRP_ERR_UNSUPPORTED
+    assert call(good, prec=crp.CRP_PREC_MIXED_DFACC) == crp.CRP_ERR_UNSUPPORTED
+    tape = crp.crp_tape(0x3000, 0x4000, 0x5000, 0x5800, 100, 64, 0)
+    assert call(good, tape=tape) == crp.CRP_ERR_UNSUPPORTED
+    assert L.crp_propagate_adjoint(C.byref(f), C.byref(good), C.byref(parts), 10, C.byref(tape), 0x6000, None, None,
+                                   0x7000, None, 0x8000, None, 0, None) == crp.CRP_ERR_UNSUPPORTED
+    # a box that is off (reflect = 0) is not checked
+    off = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0)
+    off.box_lo[0] = 5.0
+    assert call(off) == crp.CRP_ERR_WORKSPACE
