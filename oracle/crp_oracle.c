@@ -38,7 +38,11 @@
  *     that ends outside is mirrored on the face (x -> 2 face - x, the
  *     direction component negated) after the sphere test;
  *   - an optional modulation grid (section 3.2, modulated grids) multiplying
- *     the vector grid's value, interpolated the same way.
+ *     the vector grid's value, interpolated the same way;
+ *   - backtracking (section 3.3): the input is a particle's state where it
+ *     was observed; it is propagated as its antiparticle (charge -Z) with the
+ *     direction reversed, and the direction reached is reversed again, so
+ *     that input and output directions are the physical particle's.
  *
  * Arithmetic is IEEE FP64, round to nearest even, compiled with
  * -ffp-contract=off; fused multiply-adds appear only where fma() is written.
@@ -284,7 +288,32 @@ typedef struct {
     int64_t max_steps;    /* accepted steps allowed in this call; 0 = no limit */
     int reflect;          /* reflective box on */
     double box_lo[3], box_hi[3];
+    int backtrack;        /* propagate the antiparticle backwards */
 } params_t;
+
+/* Parameter block: [tol, h_min, h_max, cx, cy, cz, R, l_max, box lo x, y, z,
+ * box hi x, y, z, reflect, backtrack].  Returns 0, or -1 for a box that is on
+ * with lo >= hi on some axis. */
+static int read_params(const double *prm, params_t *p)
+{
+    p->tol = prm[0];
+    p->h_min = prm[1];
+    p->h_max = prm[2];
+    p->center[0] = prm[3];
+    p->center[1] = prm[4];
+    p->center[2] = prm[5];
+    p->radius = prm[6];
+    p->l_max = prm[7];
+    for (int a = 0; a < 3; ++a) {
+        p->box_lo[a] = prm[8 + a];
+        p->box_hi[a] = prm[11 + a];
+    }
+    p->reflect = prm[14] != 0.0;
+    p->backtrack = prm[15] != 0.0;
+    if (p->reflect && !(p->box_lo[0] < p->box_hi[0] && p->box_lo[1] < p->box_hi[1] && p->box_lo[2] < p->box_hi[2]))
+        return -1;
+    return 0;
+}
 
 /* Reflective box (the example of section 4 uses reflective boundaries): a
  * particle whose accepted step ends outside the box on an axis is mirrored on
@@ -615,7 +644,7 @@ int oracle_fixed_steps(const void *grid, int dtype, int64_t n0, int64_t n1, int6
     return 0;
 }
 
-/* Propagate n particles in place.  prm: [tol, h_min, h_max, cx, cy, cz, R, l_max].
+/* Propagate n particles in place.  prm: the parameter block of read_params.
  * Arrays of length n (pos/dir are n x 3).  counters (may be NULL): 5 int64 summed
  * [evals, accepted, rejected, event_evals, floor_hits].  Returns 0 or -1. */
 int oracle_propagate(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2,
@@ -628,20 +657,7 @@ int oracle_propagate(const void *grid, int dtype, int64_t n0, int64_t n1, int64_
     if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing, mod, mod_desc) || n < 0 || !prm)
         return -1;
     params_t p;
-    p.tol = prm[0];
-    p.h_min = prm[1];
-    p.h_max = prm[2];
-    p.center[0] = prm[3];
-    p.center[1] = prm[4];
-    p.center[2] = prm[5];
-    p.radius = prm[6];
-    p.l_max = prm[7];
-    p.reflect = prm[14] != 0.0;
-    for (int a = 0; a < 3; ++a) {
-        p.box_lo[a] = prm[8 + a];
-        p.box_hi[a] = prm[11 + a];
-    }
-    if (p.reflect && !(p.box_lo[0] < p.box_hi[0] && p.box_lo[1] < p.box_hi[1] && p.box_lo[2] < p.box_hi[2]))
+    if (read_params(prm, &p))
         return -1;
     p.max_steps = max_steps;
     if (!(p.tol > 0.0) || !(p.h_min > 0.0) || !(p.h_max >= p.h_min) || isnan(p.l_max) ||
@@ -659,15 +675,20 @@ int oracle_propagate(const void *grid, int dtype, int64_t n0, int64_t n1, int64_
             continue;
         double y[6] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2],
                        dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
+        int32_t z = charge[i];
+        if (p.backtrack) { /* the antiparticle, moving the other way */
+            for (int c = 3; c < 6; ++c)
+                y[c] = -y[c];
+            z = -z;
+        }
         counts_t cnt = {0, 0, 0, 0, 0};
         double L = length[i], hn = h_next[i];
-        int st = propagate_one(&g, &p, y, energy[i], charge[i], &L, &hn, &n_acc[i], &n_rej[i],
-                               &cnt, NULL);
+        int st = propagate_one(&g, &p, y, energy[i], z, &L, &hn, &n_acc[i], &n_rej[i], &cnt, NULL);
         status[i] = st;
         if (st != ST_BAD_INPUT) {
             for (int c = 0; c < 3; ++c) {
                 pos[3 * i + c] = y[c];
-                dir[3 * i + c] = y[3 + c];
+                dir[3 * i + c] = p.backtrack ? -y[3 + c] : y[3 + c];
             }
             length[i] = L;
             h_next[i] = hn;
@@ -701,22 +722,9 @@ int64_t oracle_propagate_taped(const void *grid, int dtype, int64_t n0, int64_t 
     if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing, mod, mod_desc))
         return -1;
     params_t p;
-    p.tol = prm[0];
-    p.h_min = prm[1];
-    p.h_max = prm[2];
-    p.center[0] = prm[3];
-    p.center[1] = prm[4];
-    p.center[2] = prm[5];
-    p.radius = prm[6];
-    p.l_max = prm[7];
-    p.reflect = prm[14] != 0.0;
-    for (int a = 0; a < 3; ++a) {
-        p.box_lo[a] = prm[8 + a];
-        p.box_hi[a] = prm[11 + a];
-    }
-    if (p.reflect && !(p.box_lo[0] < p.box_hi[0] && p.box_lo[1] < p.box_hi[1] && p.box_lo[2] < p.box_hi[2]))
+    if (read_params(prm, &p))
         return -1;
-    if (p.reflect) /* the replayed map has no mirror: no tape for reflective boxes */
+    if (p.reflect || p.backtrack) /* the replayed map has no mirror and no reversal */
         return -1;
     p.max_steps = 0;
     if (!isfinite(p.l_max))

@@ -28,7 +28,8 @@ _GRID_ARGS = [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_int64, _pd, C.c_dou
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        src = os.path.join(HERE, "crp_oracle.c")
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
             from . import build_oracle  # noqa: F401  (package-relative when imported as oracle.oracle)
             build_oracle.build()
         L = C.CDLL(_LIB_PATH)
@@ -135,12 +136,21 @@ def fixed_steps(grid: Grid, kap: float, y, h: float, nsteps: int) -> np.ndarray:
     return y
 
 
-def params_array(tol, h_min, h_max, center=(0.0, 0.0, 0.0), radius=0.0, l_max=math.inf, box=None):
+def params_array(tol, h_min, h_max, center=(0.0, 0.0, 0.0), radius=0.0, l_max=math.inf, box=None,
+                 backtrack=False):
     """Parameter block of the oracle: tolerance, step limits, observer sphere,
-    length limit and an optional reflective box ((lo x, y, z), (hi x, y, z))."""
+    length limit, an optional reflective box ((lo x, y, z), (hi x, y, z)) and
+    the backtracking flag."""
     lo, hi, on = ((0.0,) * 3, (0.0,) * 3, 0.0) if box is None else (box[0], box[1], 1.0)
     return np.array([tol, h_min, h_max, center[0], center[1], center[2], radius, l_max,
-                     lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], on], dtype=np.float64)
+                     lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], on, 1.0 if backtrack else 0.0], dtype=np.float64)
+
+
+def _prm(prm) -> np.ndarray:
+    a = np.ascontiguousarray(prm, dtype=np.float64)
+    if a.shape != (16,):
+        raise ValueError("the parameter block has 16 entries (params_array)")
+    return a
 
 
 def propagate(grid: Grid, prm: np.ndarray, pos, dir, energy, charge, length=None, h_next=None,
@@ -159,7 +169,7 @@ def propagate(grid: Grid, prm: np.ndarray, pos, dir, energy, charge, length=None
         "n_rej": np.zeros(n, np.int64) if n_rej is None else np.array(n_rej, dtype=np.int64),
     }
     counters = np.zeros(5, dtype=np.int64)
-    rc = lib().oracle_propagate(*grid.args(), np.ascontiguousarray(prm, dtype=np.float64),
+    rc = lib().oracle_propagate(*grid.args(), _prm(prm),
                                 int(max_steps), n, st["pos"], st["dir"], st["energy"],
                                 st["charge"], st["length"], st["h_next"], st["status"],
                                 st["n_acc"], st["n_rej"], counters.ctypes.data, int(nthreads))
@@ -178,7 +188,7 @@ def propagate_taped(grid: Grid, prm: np.ndarray, pos, dir, energy, charge, cap: 
     hn = np.zeros(1)
     tape = np.zeros(cap)
     info = np.zeros(4)
-    m = lib().oracle_propagate_taped(*grid.args(), np.ascontiguousarray(prm, np.float64), y,
+    m = lib().oracle_propagate_taped(*grid.args(), _prm(prm), y,
                                      float(energy), int(charge), L, hn, tape, cap, info)
     if m < 0:
         raise ValueError("oracle_propagate_taped: bad arguments")
