@@ -101,6 +101,12 @@ typedef struct {
 } crp_field;
 
 /* Bidding and stopping parameters of one particle group (section 3.1).
+ * Backtracking (section 3.3): with backtrack = 1 the particles' states are
+ * where they were observed, and each is propagated as its antiparticle
+ * (charge -Z) with the direction reversed; the direction written back is
+ * reversed again, so input and output directions are the physical particle's
+ * direction of motion (the output is the physical state a path length L
+ * earlier).
  * Reflective box (the example of section 4 has reflective boundaries): with
  * reflect = 1 the distance to the nearest face also bids (after the sphere
  * distance, before the h_min floor), and a particle whose accepted step ends
@@ -116,6 +122,8 @@ typedef struct {
     int32_t field_index;   /* which entry of the fields array this group uses */
     int32_t reflect;       /* 1: reflective box below (FP64 precision, no tape); 0: none */
     double box_lo[3], box_hi[3];  /* Mpc, lo < hi on every axis when reflect = 1 */
+    int32_t backtrack;     /* 1: backtracking (section 3.3), no tape; 0: forward */
+    int32_t reserved;      /* 0 */
 } crp_params;
 
 /* Structure-of-arrays particle state; every pointer is [dev] with n entries

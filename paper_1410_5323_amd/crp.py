@@ -48,7 +48,8 @@ class crp_params(C.Structure):
     _fields_ = [("tol", C.c_double), ("h_min", C.c_double), ("h_max", C.c_double),
                 ("obs_center", C.c_double * 3), ("obs_radius", C.c_double), ("l_max", C.c_double),
                 ("max_steps", C.c_int64), ("field_index", C.c_int32), ("reflect", C.c_int32),
-                ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3)]
+                ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3), ("backtrack", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 _PARTICLE_FIELDS = ["x", "y", "z", "ux", "uy", "uz", "energy", "charge", "mass", "length",
@@ -395,10 +396,12 @@ def make_field(values, spacing: float, origin=(0.0, 0.0, 0.0), dtype="f32", layo
 
 
 def make_params(tol, h_min, h_max, obs_radius=0.0, l_max=math.inf, obs_center=(0.0, 0.0, 0.0),
-                max_steps=0, field_index=0, box=None) -> crp_params:
+                max_steps=0, field_index=0, box=None, backtrack=False) -> crp_params:
     """One parameter group; ``box`` = ((lo x, y, z), (hi x, y, z)) in Mpc turns on
-    the reflective box (FP64 precision only, no tape)."""
+    the reflective box (FP64 precision only, no tape); ``backtrack`` traces the
+    particles back from where they were observed (no tape)."""
     p = crp_params()
+    p.backtrack = 1 if backtrack else 0
     if box is not None:
         p.reflect = 1
         for i in range(3):

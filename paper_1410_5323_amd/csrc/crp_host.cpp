@@ -143,6 +143,8 @@ crp_status check_params(const crp_params *p, int32_t n_fields, int i) {
     if (p->field_index < 0 || p->field_index >= n_fields)
         return fail(CRP_ERR_INVALID, "params[%d]: field_index %d out of range", i, p->field_index);
     if (p->reflect != 0 && p->reflect != 1) return fail(CRP_ERR_INVALID, "params[%d]: reflect must be 0 or 1", i);
+    if (p->backtrack != 0 && p->backtrack != 1)
+        return fail(CRP_ERR_INVALID, "params[%d]: backtrack must be 0 or 1", i);
     if (p->reflect)
         for (int a = 0; a < 3; ++a)
             if (!std::isfinite(p->box_lo[a]) || !std::isfinite(p->box_hi[a]) || !(p->box_lo[a] < p->box_hi[a]))
@@ -165,6 +167,7 @@ crp::ParamsDev make_params_dev(const crp_params &p) {
     d.sphere_on = p.obs_radius > 0.0;
     d.lmax_on = std::isfinite(p.l_max);
     d.reflect_on = p.reflect != 0;
+    d.backtrack_on = p.backtrack != 0;
     for (int a = 0; a < 3; ++a) {
         d.box_lo[a] = p.box_lo[a];
         d.box_hi[a] = p.box_hi[a];
@@ -287,6 +290,7 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
         if (precision != CRP_PREC_FP64) return fail(CRP_ERR_UNSUPPORTED, "%s: a tape needs FP64 precision", fn);
         if (modulated) return fail(CRP_ERR_UNSUPPORTED, "%s: no tape (adjoint) for modulated fields", fn);
         if (reflective) return fail(CRP_ERR_UNSUPPORTED, "%s: no tape (adjoint) with a reflective box", fn);
+        if (params[0].backtrack) return fail(CRP_ERR_UNSUPPORTED, "%s: no tape (adjoint) for backtracking", fn);
         if (n_params > 1 || (n > 0 && p->param_index) || n_fields > 1)
             return fail(CRP_ERR_UNSUPPORTED, "%s: a tape is recorded for one field and one parameter group", fn);
         if (fields[0].dtype != CRP_F64 && fields[0].dtype != CRP_F32)
@@ -409,6 +413,7 @@ crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *param
     st = check_params(params, 1, 0);
     if (st != CRP_OK) return st;
     if (params->reflect) return fail(CRP_ERR_UNSUPPORTED, "%s: no adjoint with a reflective box", fn);
+    if (params->backtrack) return fail(CRP_ERR_UNSUPPORTED, "%s: no adjoint for backtracking", fn);
     if (!initial || !tape) return fail(CRP_ERR_INVALID, "%s: null particles or tape", fn);
     if (n < 0 || n > (int64_t)0x7fffffff) return fail(CRP_ERR_INVALID, "%s: n out of range", fn);
     if (tape->every_k < 1 || tape->every_k > 4096) return fail(CRP_ERR_INVALID, "%s: bad tape interval", fn);

@@ -47,7 +47,8 @@ struct ParamsDev {
     int32_t sphere_on;     // radius > 0
     int32_t lmax_on;       // l_max finite
     int32_t reflect_on;    // reflective box on
-    int32_t pad_[4];
+    int32_t backtrack_on;  // propagate the antiparticle backwards
+    int32_t pad_[3];
 };
 static_assert(sizeof(ParamsDev) == 160, "ParamsDev layout");
 

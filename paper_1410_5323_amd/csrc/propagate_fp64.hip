@@ -126,13 +126,15 @@ __device__ __forceinline__ void reflect(const ParamsDev &P, double y[6]) {
 }
 
 // Write the particle's state back (its own slots only).
-__device__ __forceinline__ void store(const PropArgs &a, int64_t p, const Lane &s, double hnext, int st) {
+__device__ __forceinline__ void store(const PropArgs &a, const ParamsDev &P, int64_t p, const Lane &s, double hnext,
+                                     int st) {
     a.x[p] = s.y[0];
     a.y[p] = s.y[1];
     a.z[p] = s.y[2];
-    a.ux[p] = s.y[3];
-    a.uy[p] = s.y[4];
-    a.uz[p] = s.y[5];
+    // backtracking carries the antiparticle's direction: reverse it back
+    a.ux[p] = P.backtrack_on ? -s.y[3] : s.y[3];
+    a.uy[p] = P.backtrack_on ? -s.y[4] : s.y[4];
+    a.uz[p] = P.backtrack_on ? -s.y[5] : s.y[5];
     a.length[p] = s.L;
     a.h_next[p] = hnext;
     if (s.dacc) a.n_acc[p] += s.dacc;
@@ -185,6 +187,11 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
     s.y[3] = a.ux[p];
     s.y[4] = a.uy[p];
     s.y[5] = a.uz[p];
+    if (P.backtrack_on) {  // the antiparticle, moving the other way
+        s.y[3] = -s.y[3];
+        s.y[4] = -s.y[4];
+        s.y[5] = -s.y[5];
+    }
     s.L = a.length[p];
     s.dacc = 0;
     s.drej = 0;
@@ -209,17 +216,17 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
     }
     s.tflags = hn == 0.0 ? CRP_TAPE_FRESH : 0;
     if (P.sphere_on && sphere_g(P, s.y) >= 0.0) {
-        store(a, p, s, hn, CRP_ST_ARRIVED);
+        store(a, P, p, s, hn, CRP_ST_ARRIVED);
         if (TAPE) tape_final(a, p, s, 0.0, CRP_TAPE_COMPLETE);
         return false;
     }
     if (P.lmax_on && s.L >= P.l_max) {
-        store(a, p, s, hn, CRP_ST_MAX_LENGTH);
+        store(a, P, p, s, hn, CRP_ST_MAX_LENGTH);
         if (TAPE) tape_final(a, p, s, 0.0, CRP_TAPE_COMPLETE);
         return false;
     }
     s.hctrl = hn == 0.0 ? P.h_max : hn;
-    s.kap = ((double)Z * K_LORENTZ) / E;
+    s.kap = ((double)(P.backtrack_on ? -Z : Z) * K_LORENTZ) / E;
     s.mode = MODE_NORMAL;
     if (TAPE) tape_checkpoint(a, s);
     bid<RFL>(P, s);
@@ -242,7 +249,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
     if (s.mode == MODE_NORMAL) {
         double exh = ex / s.h;
         if (!isfinite(eu) || !isfinite(exh)) {
-            store(a, p, s, s.hctrl, CRP_ST_NONFINITE);
+            store(a, P, p, s, s.hctrl, CRP_ST_NONFINITE);
             if (TAPE) tape_final(a, p, s, 0.0, 0);
             return CRP_ST_NONFINITE;
         }
@@ -300,12 +307,12 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
         if (RFL && P.reflect_on) reflect(P, s.y);
         s.L = Lnew;
         if (P.lmax_on && s.L >= P.l_max) {
-            store(a, p, s, s.hctrl, CRP_ST_MAX_LENGTH);
+            store(a, P, p, s, s.hctrl, CRP_ST_MAX_LENGTH);
             if (TAPE) tape_final(a, p, s, 0.0, CRP_TAPE_COMPLETE);
             return CRP_ST_MAX_LENGTH;
         }
         if (P.max_steps > 0 && s.dacc >= P.max_steps) {
-            store(a, p, s, s.hctrl, CRP_ST_MAX_STEPS);
+            store(a, P, p, s, s.hctrl, CRP_ST_MAX_STEPS);
             if (TAPE) tape_final(a, p, s, 0.0, 0);
             return CRP_ST_MAX_STEPS;
         }
@@ -318,7 +325,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
     if (s.mode == MODE_EVENT) {
         double gs = sphere_g(P, y5);
         if (!isfinite(gs)) {
-            store(a, p, s, s.hctrl, CRP_ST_NONFINITE);
+            store(a, P, p, s, s.hctrl, CRP_ST_NONFINITE);
             if (TAPE) tape_final(a, p, s, 0.0, 0);
             return CRP_ST_NONFINITE;
         }
@@ -347,7 +354,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
     s.y[4] = y5[4] / sn;
     s.y[5] = y5[5] / sn;
     s.L = e.hi[t] == e.hacc[t] ? e.lacc[t] : s.L + e.hi[t];
-    store(a, p, s, s.hctrl, CRP_ST_ARRIVED);
+    store(a, P, p, s, s.hctrl, CRP_ST_ARRIVED);
     if (TAPE) tape_final(a, p, s, e.hi[t], CRP_TAPE_COMPLETE | CRP_TAPE_EVENT);
     return CRP_ST_ARRIVED;
 }

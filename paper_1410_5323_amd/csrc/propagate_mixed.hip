@@ -300,13 +300,16 @@ __device__ __forceinline__ void bid(const ParamsDev &P, Lane<ACC> &s) {
 }
 
 template <int ACC>
-__device__ __forceinline__ void store(const PropArgs &a, int64_t p, const Lane<ACC> &s, double hnext, int st) {
+__device__ __forceinline__ void store(const PropArgs &a, const ParamsDev &P, int64_t p, const Lane<ACC> &s,
+                                     double hnext, int st) {
     a.x[p] = s.acc.X(0);
     a.y[p] = s.acc.X(1);
     a.z[p] = s.acc.X(2);
-    a.ux[p] = (double)s.u[0];
-    a.uy[p] = (double)s.u[1];
-    a.uz[p] = (double)s.u[2];
+    // backtracking carries the antiparticle's direction: reverse it back
+    const double sg = P.backtrack_on ? -1.0 : 1.0;
+    a.ux[p] = sg * (double)s.u[0];
+    a.uy[p] = sg * (double)s.u[1];
+    a.uz[p] = sg * (double)s.u[2];
     double L = s.acc.len();
     a.length[p] = L;
     a.h_next[p] = hnext;
@@ -342,6 +345,11 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane<ACC> &s
     int Z = a.charge[p];
     double x[3] = {a.x[p], a.y[p], a.z[p]};
     double u[3] = {a.ux[p], a.uy[p], a.uz[p]};
+    if (P.backtrack_on) {  // the antiparticle, moving the other way
+        u[0] = -u[0];
+        u[1] = -u[1];
+        u[2] = -u[2];
+    }
     double L = a.length[p];
     double hn = a.h_next[p];
     s.dacc = 0;
@@ -370,15 +378,15 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane<ACC> &s
     s.u[2] = (float)u[2];
     const float z[3] = {0.f, 0.f, 0.f};
     if (P.sphere_on && s.acc.sphere(P, z) >= 0.0) {
-        store(a, p, s, hn, CRP_ST_ARRIVED);
+        store(a, P, p, s, hn, CRP_ST_ARRIVED);
         return false;
     }
     if (P.lmax_on && L >= P.l_max) {
-        store(a, p, s, hn, CRP_ST_MAX_LENGTH);
+        store(a, P, p, s, hn, CRP_ST_MAX_LENGTH);
         return false;
     }
     s.hctrl = hn == 0.0 ? (float)P.h_max : (float)hn;
-    s.kap = (float)(((double)Z * K_LORENTZ) / E);
+    s.kap = (float)(((double)(P.backtrack_on ? -Z : Z) * K_LORENTZ) / E);
     s.mode = MODE_NORMAL;
     bid(P, s);
     return true;
@@ -403,7 +411,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &
     if (s.mode == MODE_NORMAL) {
         float exh = ex / s.h;
         if (!isfinite(eu) || !isfinite(exh)) {
-            store(a, p, s, (double)s.hctrl, CRP_ST_NONFINITE);
+            store(a, P, p, s, (double)s.hctrl, CRP_ST_NONFINITE);
             return CRP_ST_NONFINITE;
         }
         float err = (eu > exh ? eu : exh) / (float)P.tol;
@@ -460,11 +468,11 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &
         s.u[1] = u5[1] / un;
         s.u[2] = u5[2] / un;
         if (P.lmax_on && s.acc.len() >= P.l_max) {
-            store(a, p, s, (double)s.hctrl, CRP_ST_MAX_LENGTH);
+            store(a, P, p, s, (double)s.hctrl, CRP_ST_MAX_LENGTH);
             return CRP_ST_MAX_LENGTH;
         }
         if (P.max_steps > 0 && s.dacc >= P.max_steps) {
-            store(a, p, s, (double)s.hctrl, CRP_ST_MAX_STEPS);
+            store(a, P, p, s, (double)s.hctrl, CRP_ST_MAX_STEPS);
             return CRP_ST_MAX_STEPS;
         }
         bid(P, s);
@@ -475,7 +483,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &
     if (s.mode == MODE_EVENT) {
         double gs = s.acc.sphere(P, dx5);
         if (!isfinite(gs)) {
-            store(a, p, s, (double)s.hctrl, CRP_ST_NONFINITE);
+            store(a, P, p, s, (double)s.hctrl, CRP_ST_NONFINITE);
             return CRP_ST_NONFINITE;
         }
         if (gs >= 0.0) {
@@ -502,7 +510,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &
     s.u[0] = u5[0] / sn;
     s.u[1] = u5[1] / sn;
     s.u[2] = u5[2] / sn;
-    store(a, p, s, (double)s.hctrl, CRP_ST_ARRIVED);
+    store(a, P, p, s, (double)s.hctrl, CRP_ST_ARRIVED);
     return CRP_ST_ARRIVED;
 }
 

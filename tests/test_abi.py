@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(crp):
 def test_struct_sizes_match_header(crp):
     assert C.sizeof(crp.crp_field) == 4 * 6 + 8 * 3 + 8 + 8 + 8 + 8
     assert C.sizeof(crp.crp_modulation) == 4 * 4 + 8 * 3 + 8 + 8
-    assert C.sizeof(crp.crp_params) == 8 * 3 + 8 * 3 + 8 + 8 + 8 + 8 + 8 * 6
+    assert C.sizeof(crp.crp_params) == 8 * 3 + 8 * 3 + 8 + 8 + 8 + 8 + 8 * 6 + 8
     assert C.sizeof(crp.crp_particles) == 16 * 8
     assert C.sizeof(crp.crp_tuning) == 32
 
@@ -258,3 +258,30 @@ def test_reflective_box_checks(crp):
     off = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0)
     off.box_lo[0] = 5.0
     assert call(off) == crp.CRP_ERR_WORKSPACE
+
+
+def test_backtrack_checks(crp):
+    """backtrack is 0 or 1; tapes and the adjoint refuse it."""
+    L = crp.lib()
+    f = _field(crp)
+    f.data = 0x1000
+    farr = (crp.crp_field * 1)(f)
+    parts = crp.crp_particles(**{k: 0x2000 for k in crp._PARTICLE_FIELDS})
+    parts.param_index = None
+    tape = crp.crp_tape(0x3000, 0x4000, 0x5000, 0x5800, 100, 64, 0)
+
+    def call(p, prec=0, t=None):
+        q = (crp.crp_params * 1)(p)
+        return L.crp_propagate(farr, 1, q, 1, C.byref(parts), 10, C.byref(t) if t else None, prec, None, None,
+                               None, 0, None)
+
+    bt = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0, backtrack=True)
+    assert bt.backtrack == 1
+    assert call(bt) == crp.CRP_ERR_WORKSPACE
+    assert call(bt, prec=crp.CRP_PREC_MIXED_F64ACC) == crp.CRP_ERR_WORKSPACE  # the mixed kernel backtracks too
+    assert call(bt, t=tape) == crp.CRP_ERR_UNSUPPORTED
+    assert L.crp_propagate_adjoint(C.byref(f), C.byref(bt), C.byref(parts), 10, C.byref(tape), 0x6000, None, None,
+                                   0x7000, None, 0x8000, None, 0, None) == crp.CRP_ERR_UNSUPPORTED
+    bad = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0)
+    bad.backtrack = -1
+    assert call(bad) == crp.CRP_ERR_INVALID
