@@ -10,7 +10,9 @@ stops.  Other workloads: --workload small_fp64_32cube | batched_64x64cube |
 precision_1024cube | adjoint_128cube | modulated_256cube (the production
 vector grid times a 440^3 modulation grid at 300 kpc, section 3.2) |
 reflective_132box (that modulated field inside a reflective 132 Mpc box, the
-particles starting uniformly in it, 100 Mpc of path; section 4).
+particles starting uniformly in it, 100 Mpc of path; section 4) | lens_nside64
+(3,145,728 protons at 10 EeV traced back through the production field to a
+20 Mpc sphere, then a HEALPix nside-64 lens built and applied; section 3.3).
 
 Prints one JSON line: particle-steps/s (accepted Cash-Karp steps per second of
 the whole job), the lookup roofline of the propagation kernel (algorithmic
@@ -95,6 +97,11 @@ def build_inputs(w, n_override):
         P = ci.isotropic_particles(n, w.e_min, w.e_max, w.charges, ps, charge_rule=w.charge_rule)
         if w.reflect_box is not None:
             P["pos"] = ci.box_positions(n, w.reflect_box[0], w.reflect_box[1], ci.position_seed(w.index))
+        if w.lens_nside:
+            # the drawn directions are where the particles are observed to come
+            # from; backtracking starts from the reversed velocity
+            P["sky"] = P["dir"].copy()
+            P["dir"] = -P["dir"]
         grids = [ci.kolmogorov_field(w.grid_n, w.spacing, w.l_min, w.l_max, w.b_rms, fs, dtype=gdt)]
         radii = [w.obs_radius]
     return grids, radii, P
@@ -119,7 +126,8 @@ def cpu_baseline(grids, radii, w, P, sample: int, modulation=None):
     t0 = time.perf_counter()
     for gi in np.unique(groups):
         sel = np.nonzero(groups == gi)[0]
-        prm = O.params_array(w.tol, w.h_min, w.h_max, radius=radii[gi], l_max=w.max_length, box=w.reflect_box)
+        prm = O.params_array(w.tol, w.h_min, w.h_max, radius=radii[gi], l_max=w.max_length, box=w.reflect_box,
+                             backtrack=w.lens_nside > 0)
         mod = None if modulation is None else O.Modulation(modulation, w.mod_spacing, (w.mod_origin,) * 3)
         r = O.propagate(O.Grid(grids[gi], w.spacing, modulation=mod), prm, P["pos"][sel], P["dir"][sel], P["energy"][sel],
                         P["charge"][sel], nthreads=threads)
@@ -131,6 +139,70 @@ def cpu_baseline(grids, radii, w, P, sample: int, modulation=None):
     return {"value": acc / dt, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"first {sample} particles of the same seeded list ({acc} accepted steps, "
                       f"{evals} evaluations, {dt:.1f} s)"}, out
+
+
+def lens_leg(crp, torch, w, P, state, reps: int = 20) -> dict:
+    """Lens of the workload's rigidity from the backtracking pass just timed:
+    observed pixels of the launches, lens construction and lens application
+    (one map and 64 maps), each timed with events on the current stream."""
+    import numpy as np
+    nside = w.lens_nside
+    npix = crp.healpix_npix(nside)
+    stream = torch.cuda.current_stream()
+    sky = [torch.from_numpy(np.ascontiguousarray(P["sky"][:, k])).cuda() for k in range(3)]
+    n = int(sky[0].numel())
+    ws = torch.empty(crp.crp_lens_workspace_bytes(nside, n), dtype=torch.uint8, device="cuda")
+
+    def ev_ms(fn, count):
+        out = []
+        for _ in range(count):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            b.synchronize()
+            out.append(a.elapsed_time(b))
+        return out
+
+    rows = crp.crp_healpix_pixels(nside, *sky)
+    pix_ms = ev_ms(lambda: crp.crp_healpix_pixels(nside, *sky, pix=rows), 5)
+    lens = crp.crp_lens_build(nside, rows, state, workspace=ws)
+    outs = (torch.empty_like(lens.row_ptr), torch.empty(n, dtype=torch.int32, device="cuda"),
+            torch.empty(n, dtype=torch.float32, device="cuda"))
+    build_ms = ev_ms(lambda: crp.crp_lens_build(nside, rows, state, workspace=ws, out=outs), 5)
+    out = {"nside": nside, "pixels": npix, "launches": n, "nnz": lens.nnz, "entries_per_row": lens.nnz / npix,
+           "escaped_fraction": float((state["status"] == 1).float().mean().item()),
+           "matrix_MB": lens.nbytes() / 1e6, "pixels_ms": float(np.median(pix_ms)),
+           "build_ms": float(np.median(build_ms))}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    for nvec in (1, 64):
+        x = torch.rand((npix, nvec) if nvec > 1 else (npix,), generator=g, device="cuda", dtype=torch.float32)
+        y = torch.empty_like(x)
+        crp.crp_lens_apply(lens, x, y)
+        ms = float(np.median(ev_ms(lambda: crp.crp_lens_apply(lens, x, y), reps)))
+        alg = 8 * lens.nnz + 8 * (npix + 1) + 2 * 4 * npix * nvec
+        out[f"apply_{nvec}"] = {"ms": ms, "algorithmic_bytes": alg, "GB_per_s": alg / (ms * 1e-3) / 1e9,
+                                "frac_of_hbm_peak": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+    return out
+
+
+def lens_cpu_baseline(w, P, ref, m: int) -> dict:
+    """The lens oracle on the oracle's own backtracking of the first m launches."""
+    import numpy as np
+
+    from oracle import lens as LN
+    nside = w.lens_nside
+    t0 = time.perf_counter()
+    rows = LN.pix_ring(nside, P["sky"][:m, 0], P["sky"][:m, 1], P["sky"][:m, 2])
+    row_ptr, col, val = LN.lens_matrix(nside, rows, ref["dir"][:, 0], ref["dir"][:, 1], ref["dir"][:, 2],
+                                       ref["status"] == 1)
+    t1 = time.perf_counter()
+    x = np.random.default_rng(5).random((LN.npix(nside), 64)).astype(np.float32)
+    LN.lens_apply(row_ptr, col, val, x)
+    t2 = time.perf_counter()
+    return {"kind": "oracle", "sample": f"first {m} launches", "build_launches_per_s": m / (t1 - t0),
+            "apply_64_ms": (t2 - t1) * 1e3, "nnz": int(len(col))}
 
 
 def gather_ceiling(field, lanes: int = 262144, per_lane: int = 200, reps: int = 3) -> dict:
@@ -342,7 +414,7 @@ def main():
     gdt_name = args.grid_dtype or ("f16" if prec != 0 else ("f64" if w.grid_dtype == "f64" else "f32"))
     layout = args.layout or ("cell8" if w.grid_n <= 512 else "linear")
     params = [crp.make_params(w.tol, w.h_min, w.h_max, obs_radius=radii[r], l_max=w.max_length, field_index=r,
-                              box=w.reflect_box) for r in range(len(grids))]
+                              box=w.reflect_box, backtrack=w.lens_nside > 0) for r in range(len(grids))]
     pristine = crp.particles_to_device(P["pos"], P["dir"], P["energy"], P["charge"], mass=P["mass"],
                                        param_index=P.get("param_index"))
     state = crp.clone_particles(pristine)
@@ -470,7 +542,7 @@ def main():
     }
 
     mixed_host = None
-    if prec == 0 and not args.no_mixed and not batched and mod is None and w.reflect_box is None:
+    if prec == 0 and not args.no_mixed and not batched and mod is None and w.reflect_box is None and not w.lens_nside:
         mdt = args.mixed_grid_dtype
         mfields = [crp.make_field(g, w.spacing, dtype=mdt, layout=layout) for g in grids]
         mix = timed(mfields, PRECISIONS["mixed_f64acc"], mixed_tuning, args.steps, 1, f"mixed_f64acc/{mdt}/{layout}")
@@ -499,6 +571,10 @@ def main():
         result["mixed"]["error_vs_fp64"]["reference"] = ("FP64 path on the FP32 grid (bitwise equal to the oracle "
                                                          "on this sample)")
 
+    if w.lens_nside:
+        result["lens"] = lens_leg(crp, torch, w, P, state)
+        log(f"bench: lens leg {result['lens']}")
+
     if not args.no_adjoint:
         del state, pristine, ws
         torch.cuda.empty_cache()
@@ -518,6 +594,8 @@ def main():
                    & (g["length"] == ref["length"]) & (g["status"] == ref["status"]))
             result["detail"]["parity_sample"] = {"particles": m, "bitwise_fraction": float(np.mean(bit)),
                                                  "max_angle_rad": float(np.max(angle(g["dir"], ref["dir"])))}
+        if w.lens_nside:
+            result["lens"]["cpu_baseline"] = lens_cpu_baseline(w, P, ref, m)
         if mixed_host is not None:
             a = angle(mixed_host["dir"][:m], ref["dir"])
             result["mixed"]["angle_vs_oracle_rad"] = {"p50": float(np.percentile(a, 50)),

@@ -52,6 +52,7 @@ class Workload:
     mod_l_corr: float = 0.0      # correlation length of the log-normal modulation, Mpc
     mod_sigma: float = 0.0       # standard deviation of log m
     reflect_half: float = 0.0    # > 0: reflective box [-h, h]^3 (Mpc); the particles start uniformly in it
+    lens_nside: int = 0          # > 0: a lens workload (backtracking from the origin, HEALPix nside)
 
     @property
     def mod_origin(self) -> float:
@@ -102,6 +103,13 @@ CONFIGS = (
     Workload("reflective_132box", 6, 1_000_000, MIXED, 1e18, 1e20, 256, 0.05, 0.1, 5.0, 1.0, "f32",
              1e-4, 0.001, 1.0, 0.0, 100.0, mod_n=440, mod_spacing=0.3, mod_l_corr=2.0, mod_sigma=1.0,
              reflect_half=66.0),
+    # A lens of one rigidity (section 3.3, lensing): protons at 10 EeV observed at the origin in
+    # directions spread uniformly over the sky are traced back through the production field to a
+    # sphere of 20 Mpc standing for the galactic border (r_g = 10.8 Mpc in 1 nG, as 10 EeV
+    # protons in a 1 uG galaxy of 20 kpc); HEALPix nside 64 (49,152 pixels, < 1 degree) with 64
+    # launches per pixel on average (all chosen).
+    Workload("lens_nside64", 7, 12 * 64 * 64 * 64, (1,), 1e19, 1e19, 256, 0.05, 0.1, 5.0, 1.0, "f32",
+             1e-4, 0.001, 1.0, 20.0, 1000.0, lens_nside=64),
 )
 
 

@@ -10,7 +10,7 @@ root on every call to keep results reproducible.
 import numpy as np
 
 ROOT_SEED = 14105323
-N_WORKLOADS = 7
+N_WORKLOADS = 8
 
 
 def config_seeds(index: int):

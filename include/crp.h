@@ -300,6 +300,52 @@ crp_status crp_bench_gather(const crp_field *f, int64_t lanes, int64_t lookups_p
  * bandwidth ceiling and to calibrate hardware byte counters. */
 crp_status crp_bench_stream(const void *src, void *dst, size_t bytes, double *sink, int32_t blocks, void *stream);
 
+/* ---- Lenses (section 3.3, the lensing technique of PARSEC) ----------------
+ * For one rigidity, particles traced back from Earth (crp_propagate with
+ * backtrack = 1, the observer sphere standing for the galactic border) give a
+ * sparse matrix over sky pixels that maps cosmic-ray directions at the border
+ * to the directions observed at Earth; arrival distributions are transformed
+ * by matrix-vector products.  Pixels are HEALPix (Gorski et al. 2005, ApJ
+ * 622:759) in the RING numbering, npix = 12 nside^2. */
+
+/* Pixel of each direction (ux, uy, uz)[i]: any non-zero finite length, -1
+ * for a zero or non-finite one.  1 <= nside <= 8192.  ux, uy, uz, pix: [dev]
+ * n entries.  FP64 decision: z = uz/|u| and phi = atan2(uy, ux) in [0, 2 pi)
+ * select the ring and the pixel in it.  Asynchronous on stream. */
+crp_status crp_healpix_pixels(int32_t nside, const double *ux, const double *uy, const double *uz, int64_t n,
+                              int32_t *pix, void *stream);
+
+/* Workspace of crp_lens_build for nside and n launches (0 if out of range). */
+size_t crp_lens_workspace_bytes(int32_t nside, int64_t n);
+
+/* Lens of one rigidity from n backtracked launches.
+ *   row: [dev] observed pixel of each launch, in [0, npix) (the pixel of the
+ *        direction the particle was observed to come from, i.e. of the
+ *        reversed velocity given to the backtracking run);
+ *   ux, uy, uz, status: [dev] that run's output; a launch with status
+ *        CRP_ST_ARRIVED adds to the entry at the pixel of its reversed
+ *        velocity (the direction it came from at the border); every launch
+ *        counts in its row's denominator;
+ *   row_ptr: [dev] npix + 1 entries; col, val: [dev] capacity >= n entries;
+ *        out: CSR with val[e] = (launches of row i reaching the border from
+ *        pixel col[e]) / (launches of row i), FP64 ratio rounded to FP32,
+ *        columns ascending within a row;
+ *   nnz: [host] out, the number of entries (the call waits for the stream).
+ * 1 <= nside <= 1024; a row with more than 4096 launches gives
+ * CRP_ERR_UNSUPPORTED, a row index out of range CRP_ERR_INVALID (both found
+ * on the device, reported after the wait). */
+crp_status crp_lens_build(int32_t nside, const int32_t *row, const double *ux, const double *uy, const double *uz,
+                          const int32_t *status, int64_t n, int64_t *row_ptr, int32_t *col, float *val,
+                          int64_t capacity, int64_t *nnz, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Lens application y = L x for nvec maps at once: y[i][v] = sum over the
+ * entries e of row i of val[e] * x[col[e]][v], summed in FP64, stored FP32.
+ * x, y: [dev] npix x nvec, pixel-major.  row_ptr, col, val: [dev] a lens as
+ * crp_lens_build writes it (every col in [0, npix): the caller's to ensure);
+ * nnz its entry count; 1 <= nvec <= 4096.  Allocates nothing; asynchronous. */
+crp_status crp_lens_apply(int32_t nside, const int64_t *row_ptr, const int32_t *col, const float *val, int64_t nnz,
+                          const float *x, float *y, int32_t nvec, void *stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *crp_last_error(void);
 

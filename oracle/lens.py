@@ -23,18 +23,23 @@ Readings (the paper gives the technique, not its formulas):
   * the application y = L x maps a flux map at the border to the observed
     one (flux is constant along a trajectory), summed in FP64.
 
+The clamps below change nothing in exact arithmetic (the ring index and q
+stay in range there); they only keep a direction that rounding puts exactly
+on the belt's edge inside the valid pixel range.
+
 Pixel decision (FP64 throughout, in this order):
     r = sqrt(ux*ux + uy*uy + uz*uz), z = uz / r, za = |z|
     phi = atan2(uy, ux), plus 2 pi if negative; tt = phi / (pi/2), 0 if tt >= 4
     za <= 2/3 (equatorial belt):
         t1 = nside * (0.5 + tt), t2 = nside * (z * 0.75)
         jp = floor(t1 - t2), jm = floor(t1 + t2)       (edge-line indices)
-        ir = nside + 1 + jp - jm                        (ring, 1 .. 2 nside + 1)
-        ip = (jp + jm - nside + (1 - ir mod 2) + 1) / 2 mod 4 nside
+        ir = nside + 1 + jp - jm, clamped to 1 .. 2 nside + 1 (belt rings)
+        q = jp + jm - nside + (1 - ir mod 2) + 1, clamped to >= 0
+        ip = (q / 2, rounded down) mod 4 nside
         pix = 2 nside (nside - 1) + 4 nside (ir - 1) + ip
     za > 2/3 (polar caps):
         tp = tt - floor(tt), s = nside * sqrt(3 * (1 - za))
-        jp = floor(tp * s), jm = floor((1 - tp) * s), ir = jp + jm + 1
+        jp = floor(tp * s), jm = floor((1 - tp) * s), ir = jp + jm + 1 clamped to 1 .. nside
         ip = floor(tt * ir) mod 4 ir
         pix = 2 ir (ir - 1) + ip (north), 12 nside^2 - 2 ir (ir + 1) + ip (south)
 """
@@ -53,13 +58,18 @@ def npix(nside: int) -> int:
 
 
 def pix_ring(nside: int, ux, uy, uz) -> np.ndarray:
-    """RING-scheme pixel of each direction (any non-zero length), int64."""
+    """RING-scheme pixel of each direction (any non-zero finite length), int64;
+    -1 for a zero or non-finite direction."""
     ux = np.asarray(ux, dtype=np.float64)
     uy = np.asarray(uy, dtype=np.float64)
     uz = np.asarray(uz, dtype=np.float64)
     ns = float(nside)
     r = np.sqrt(ux * ux + uy * uy + uz * uz)
-    z = uz / r
+    bad = ~((r > 0.0) & np.isfinite(r))
+    r = np.where(bad, 1.0, r)
+    z = np.where(bad, 0.0, uz / r)
+    ux = np.where(bad, 1.0, ux)
+    uy = np.where(bad, 0.0, uy)
     za = np.abs(z)
     phi = np.arctan2(uy, ux)
     phi = np.where(phi < 0.0, phi + TWO_PI, phi)
@@ -72,10 +82,10 @@ def pix_ring(nside: int, ux, uy, uz) -> np.ndarray:
     t2 = ns * (z[eq] * 0.75)
     jp = np.floor(t1 - t2).astype(np.int64)
     jm = np.floor(t1 + t2).astype(np.int64)
-    ir = nside + 1 + jp - jm
+    ir = np.clip(nside + 1 + jp - jm, 1, 2 * nside + 1)
     kshift = 1 - (ir & 1)
-    ip = (jp + jm - nside + kshift + 1) // 2  # the numerator is >= 0
-    ip = np.mod(ip, 4 * nside)
+    q = np.maximum(jp + jm - nside + kshift + 1, 0)
+    ip = np.mod(q // 2, 4 * nside)
     out[eq] = 2 * nside * (nside - 1) + 4 * nside * (ir - 1) + ip
 
     po = ~eq
@@ -84,9 +94,10 @@ def pix_ring(nside: int, ux, uy, uz) -> np.ndarray:
     s = ns * np.sqrt(3.0 * (1.0 - za[po]))
     jp = np.floor(tp * s).astype(np.int64)
     jm = np.floor((1.0 - tp) * s).astype(np.int64)
-    ir = jp + jm + 1
+    ir = np.clip(jp + jm + 1, 1, nside)
     ip = np.mod(np.floor(ttp * ir).astype(np.int64), 4 * ir)
     out[po] = np.where(z[po] > 0.0, 2 * ir * (ir - 1) + ip, npix(nside) - 2 * ir * (ir + 1) + ip)
+    out[bad] = -1
     return out
 
 
@@ -127,6 +138,10 @@ def lens_matrix(nside: int, rows, ux, uy, uz, arrived):
     n_pix = npix(nside)
     launches = np.bincount(rows, minlength=n_pix)
     cols = pix_ring(nside, -np.asarray(ux)[arrived], -np.asarray(uy)[arrived], -np.asarray(uz)[arrived])
+    keep = cols >= 0  # a direction that cannot be binned counts as not arrived
+    arrived = arrived.copy()
+    arrived[np.nonzero(arrived)[0][~keep]] = False
+    cols = cols[keep]
     keys, counts = np.unique(rows[arrived] * n_pix + cols, return_counts=True)
     r = keys // n_pix
     c = keys % n_pix

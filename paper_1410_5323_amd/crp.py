@@ -116,6 +116,17 @@ def lib():
         L.crp_graph_destroy.argtypes = [C.c_void_p]
         for f in (L.crp_graph_create, L.crp_graph_launch, L.crp_graph_destroy):
             f.restype = C.c_int
+        L.crp_healpix_pixels.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                         C.c_void_p]
+        L.crp_lens_workspace_bytes.argtypes = [C.c_int32, C.c_int64]
+        L.crp_lens_workspace_bytes.restype = C.c_size_t
+        L.crp_lens_build.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                     C.POINTER(C.c_int64), C.c_void_p, C.c_size_t, C.c_void_p]
+        L.crp_lens_apply.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                     C.c_void_p, C.c_int32, C.c_void_p]
+        for f in (L.crp_healpix_pixels, L.crp_lens_build, L.crp_lens_apply):
+            f.restype = C.c_int
         L.crp_last_error.restype = C.c_char_p
         L.crp_version.restype = C.c_char_p
         for f in (L.crp_field_upload, L.crp_propagate, L.crp_selftest_arith):
@@ -251,6 +262,76 @@ def crp_propagate_adjoint(field, params, initial: dict, tape: Tape, gbar_dir, gb
                                        _ptr(gbar_dir), _ptr(gbar_time), _ptr(gbar_energy), _ptr(grad_u0),
                                        _ptr(grad_x0), _ptr(grad_field), _ptr(workspace), workspace.numel(),
                                        _stream_handle(stream)))
+
+
+def healpix_npix(nside: int) -> int:
+    return 12 * int(nside) * int(nside)
+
+
+def crp_healpix_pixels(nside: int, ux, uy, uz, pix=None, stream=None):
+    """RING-scheme HEALPix pixel (int32, -1 for a zero direction) of each direction."""
+    torch = _torch()
+    n = int(ux.numel())
+    if pix is None:
+        pix = torch.empty(n, dtype=torch.int32, device=ux.device)
+    _check(lib().crp_healpix_pixels(int(nside), _ptr(ux), _ptr(uy), _ptr(uz), n, _ptr(pix),
+                                    _stream_handle(stream)))
+    return pix
+
+
+def crp_lens_workspace_bytes(nside: int, n: int) -> int:
+    return int(lib().crp_lens_workspace_bytes(int(nside), int(n)))
+
+
+class Lens:
+    """A CSR lens over HEALPix pixels (device tensors) for one rigidity."""
+
+    def __init__(self, nside, row_ptr, col, val, nnz):
+        self.nside, self.row_ptr, self.nnz = int(nside), row_ptr, int(nnz)
+        self.col, self.val = col[:self.nnz], val[:self.nnz]
+
+    @property
+    def npix(self) -> int:
+        return healpix_npix(self.nside)
+
+    def nbytes(self) -> int:
+        return 8 * (self.npix + 1) + 8 * self.nnz
+
+
+def crp_lens_build(nside: int, rows, particles: dict, workspace=None, stream=None, out=None) -> Lens:
+    """Lens from the launches' observed pixels (rows) and the output of their
+    backtracking run (particles: ux, uy, uz, status).  Waits for the stream.
+    out: optional (row_ptr, col, val) device tensors to write into."""
+    torch = _torch()
+    n = int(rows.numel())
+    dev = rows.device
+    npx = healpix_npix(nside)
+    if out is not None:
+        row_ptr, col, val = out
+    else:
+        row_ptr = torch.empty(npx + 1, dtype=torch.int64, device=dev)
+        col = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        val = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+    if workspace is None:
+        workspace = torch.empty(crp_lens_workspace_bytes(nside, n), dtype=torch.uint8, device=dev)
+    nnz = C.c_int64(0)
+    _check(lib().crp_lens_build(int(nside), _ptr(rows), _ptr(particles["ux"]), _ptr(particles["uy"]),
+                                _ptr(particles["uz"]), _ptr(particles["status"]), n, _ptr(row_ptr), _ptr(col),
+                                _ptr(val), col.numel(), C.byref(nnz), _ptr(workspace), workspace.numel(),
+                                _stream_handle(stream)))
+    return Lens(nside, row_ptr, col, val, nnz.value)
+
+
+def crp_lens_apply(lens: Lens, x, y=None, stream=None):
+    """y = L x for x of shape (npix,) or (npix, nvec), float32 on the device."""
+    torch = _torch()
+    x = x.contiguous()
+    nvec = 1 if x.dim() == 1 else int(x.shape[1])
+    if y is None:
+        y = torch.empty_like(x)
+    _check(lib().crp_lens_apply(lens.nside, _ptr(lens.row_ptr), _ptr(lens.col), _ptr(lens.val), lens.nnz, _ptr(x),
+                                _ptr(y), nvec, _stream_handle(stream)))
+    return y
 
 
 def _marshal(fields, params, particles, tuning):

@@ -553,4 +553,63 @@ crp_status crp_bench_stream(const void *src, void *dst, size_t bytes, double *si
     return ok();
 }
 
+crp_status crp_healpix_pixels(int32_t nside, const double *ux, const double *uy, const double *uz, int64_t n,
+                              int32_t *pix, void *stream) {
+    const char *fn = "crp_healpix_pixels";
+    if (nside < 1 || nside > 8192) return fail(CRP_ERR_INVALID, "%s: nside must be in [1, 8192]", fn);
+    if (n < 0 || n > (int64_t)1 << 40) return fail(CRP_ERR_INVALID, "%s: n out of range", fn);
+    if (n > 0 && (!ux || !uy || !uz || !pix)) return fail(CRP_ERR_INVALID, "%s: null pointer", fn);
+    hipError_t e = crp::launch_healpix(nside, ux, uy, uz, n, 1.0, pix, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_error(e, fn);
+    return ok();
+}
+
+size_t crp_lens_workspace_bytes(int32_t nside, int64_t n) {
+    if (nside < 1 || nside > 1024 || n < 0 || n > (int64_t)0x7fffffff) return 0;
+    return crp::lens_ws_layout(nside, n).total;
+}
+
+crp_status crp_lens_build(int32_t nside, const int32_t *row, const double *ux, const double *uy, const double *uz,
+                          const int32_t *status, int64_t n, int64_t *row_ptr, int32_t *col, float *val,
+                          int64_t capacity, int64_t *nnz, void *workspace, size_t workspace_bytes, void *stream) {
+    const char *fn = "crp_lens_build";
+    if (nside < 1 || nside > 1024) return fail(CRP_ERR_INVALID, "%s: nside must be in [1, 1024]", fn);
+    if (n < 0 || n > (int64_t)0x7fffffff) return fail(CRP_ERR_INVALID, "%s: n out of range", fn);
+    if (!row_ptr || !nnz) return fail(CRP_ERR_INVALID, "%s: null row_ptr or nnz", fn);
+    if (n > 0 && (!row || !ux || !uy || !uz || !status || !col || !val))
+        return fail(CRP_ERR_INVALID, "%s: null pointer", fn);
+    if (capacity < n) return fail(CRP_ERR_INVALID, "%s: capacity must be at least n", fn);
+    const crp::LensWs wl = crp::lens_ws_layout(nside, n);
+    if (!workspace || workspace_bytes < wl.total)
+        return fail(CRP_ERR_WORKSPACE, "%s: need %zu workspace bytes", fn, wl.total);
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(CRP_ERR_WORKSPACE, "%s: workspace alignment", fn);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    hipError_t e = crp::launch_lens_build(nside, row, ux, uy, uz, status, n, row_ptr, col, val, ws, s);
+    uint32_t flag = 0;
+    int64_t total = 0;
+    const int64_t npix = 12 * (int64_t)nside * nside;
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, ws + wl.flag, sizeof flag, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&total, row_ptr + npix, sizeof total, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_error(e, fn);
+    *nnz = total;
+    if (flag & 1u) return fail(CRP_ERR_INVALID, "%s: a row index is outside [0, npix)", fn);
+    if (flag & 2u) return fail(CRP_ERR_UNSUPPORTED, "%s: a row holds more than 4096 launches", fn);
+    return ok();
+}
+
+crp_status crp_lens_apply(int32_t nside, const int64_t *row_ptr, const int32_t *col, const float *val, int64_t nnz,
+                          const float *x, float *y, int32_t nvec, void *stream) {
+    const char *fn = "crp_lens_apply";
+    if (nside < 1 || nside > 8192) return fail(CRP_ERR_INVALID, "%s: nside must be in [1, 8192]", fn);
+    if (nvec < 1 || nvec > 4096) return fail(CRP_ERR_INVALID, "%s: nvec must be in [1, 4096]", fn);
+    if (nnz < 0) return fail(CRP_ERR_INVALID, "%s: nnz < 0", fn);
+    if (!row_ptr || !x || !y || (nnz > 0 && (!col || !val))) return fail(CRP_ERR_INVALID, "%s: null pointer", fn);
+    const int64_t npix = 12 * (int64_t)nside * nside;
+    hipError_t e = crp::launch_lens_apply(row_ptr, col, val, x, y, npix, nvec, nnz, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_error(e, fn);
+    return ok();
+}
+
 }  // extern "C"

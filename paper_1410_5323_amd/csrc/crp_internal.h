@@ -155,6 +155,20 @@ hipError_t launch_upload(const FieldDev &f, const void *src, int src_dtype, void
 hipError_t launch_selftest(const double *in, double *out, int64_t n, int op, hipStream_t s);
 hipError_t launch_gather_bench(const FieldDev &F, int64_t lanes, int64_t lookups, double spread, uint32_t seed,
                                double *sink, hipStream_t s);
+// Lens construction workspace (byte offsets): device flag, launches per row,
+// cursors, row segment starts, the grouped border pixels and the run-length
+// encoded entries per row segment.
+struct LensWs {
+    size_t flag, counts, cursor, starts, colbuf, scol, sval, total;
+};
+LensWs lens_ws_layout(int32_t nside, int64_t n);
+hipError_t launch_healpix(int32_t nside, const double *ux, const double *uy, const double *uz, int64_t n,
+                          double sign, int32_t *pix, hipStream_t s);
+hipError_t launch_lens_build(int32_t nside, const int32_t *row, const double *ux, const double *uy,
+                             const double *uz, const int32_t *status, int64_t n, int64_t *row_ptr, int32_t *col,
+                             float *val, uint8_t *ws, hipStream_t s);
+hipError_t launch_lens_apply(const int64_t *row_ptr, const int32_t *col, const float *val, const float *x, float *y,
+                             int64_t npix, int32_t nvec, int64_t nnz, hipStream_t s);
 hipError_t launch_stream(const void *src, void *dst, size_t bytes, double *sink, int blocks, hipStream_t s);
 
 }  // namespace crp

@@ -285,3 +285,29 @@ def test_backtrack_checks(crp):
     bad = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0)
     bad.backtrack = -1
     assert call(bad) == crp.CRP_ERR_INVALID
+
+
+def test_lens_entry_points_reject_bad_arguments(crp):
+    L = crp.lib()
+    assert L.crp_healpix_pixels(0, 0x1000, 0x2000, 0x3000, 10, 0x4000, None) == crp.CRP_ERR_INVALID
+    assert L.crp_healpix_pixels(8193, 0x1000, 0x2000, 0x3000, 10, 0x4000, None) == crp.CRP_ERR_INVALID
+    assert L.crp_healpix_pixels(64, None, 0x2000, 0x3000, 10, 0x4000, None) == crp.CRP_ERR_INVALID
+    assert L.crp_healpix_pixels(64, None, None, None, 0, None, None) == crp.CRP_OK  # nothing to do
+    assert crp.crp_lens_workspace_bytes(0, 10) == 0 and crp.crp_lens_workspace_bytes(2048, 10) == 0
+    a, b = crp.crp_lens_workspace_bytes(64, 1000), crp.crp_lens_workspace_bytes(64, 100000)
+    assert b > a >= 12 * 64 * 64 * 16 + 1000 * 12
+    nnz = C.c_int64(-1)
+
+    def build(nside=64, n=1000, cap=1000, ws=None, wsb=0, row=0x1000):
+        return L.crp_lens_build(nside, row, 0x2000, 0x3000, 0x4000, 0x5000, n, 0x6000, 0x7000, 0x8000, cap,
+                                C.byref(nnz), ws, wsb, None)
+
+    assert build(nside=2048) == crp.CRP_ERR_INVALID
+    assert build(n=-1) == crp.CRP_ERR_INVALID
+    assert build(cap=999) == crp.CRP_ERR_INVALID
+    assert build(row=None) == crp.CRP_ERR_INVALID
+    assert build() == crp.CRP_ERR_WORKSPACE
+    assert build(ws=0x100008, wsb=1 << 30) == crp.CRP_ERR_WORKSPACE  # misaligned
+    assert L.crp_lens_apply(64, 0x1000, 0x2000, 0x3000, 10, 0x4000, 0x5000, 0, None) == crp.CRP_ERR_INVALID
+    assert L.crp_lens_apply(64, 0x1000, 0x2000, 0x3000, 10, 0x4000, 0x5000, 5000, None) == crp.CRP_ERR_INVALID
+    assert L.crp_lens_apply(64, 0x1000, None, 0x3000, 10, 0x4000, 0x5000, 1, None) == crp.CRP_ERR_INVALID
