@@ -1026,7 +1026,7 @@ int oracle_replay_tangent(const void *grid, int dtype, int64_t n0, int64_t n1, i
  * unnormalised output (the event term).  ybar gets the cotangent of y; the grid
  * cotangent is accumulated into gbar (may be NULL). */
 static void step_vjp(const grid_t *g, double kappa, const double y[6], double s, const double lam[6],
-                     const double *comb, double ybar[6], double *gbar)
+                     const double *comb, double ybar[6], double *gbar, double *kbar)
 {
     double k[6][6], Y[6][6];
     for (int i = 0; i < 6; ++i) {
@@ -1077,6 +1077,9 @@ static void step_vjp(const grid_t *g, double kappa, const double y[6], double s,
         /* B-bar = kappa ku x U, U-bar = kx + kappa B x ku */
         double Bb[3] = {kappa * (kb[4] * U[2] - kb[5] * U[1]), kappa * (kb[5] * U[0] - kb[3] * U[2]),
                         kappa * (kb[3] * U[1] - kb[4] * U[0])};
+        /* kappa enters the stage as kappa U x B: kappa-bar += ku . (U x B) */
+        *kbar += kb[3] * (U[1] * B[2] - U[2] * B[1]) + kb[4] * (U[2] * B[0] - U[0] * B[2]) +
+                 kb[5] * (U[0] * B[1] - U[1] * B[0]);
         Ybar[i][3] = kb[0] + kappa * (B[1] * kb[5] - B[2] * kb[4]);
         Ybar[i][4] = kb[1] + kappa * (B[2] * kb[3] - B[0] * kb[5]);
         Ybar[i][5] = kb[2] + kappa * (B[0] * kb[4] - B[1] * kb[3]);
@@ -1100,11 +1103,14 @@ static void step_vjp(const grid_t *g, double kappa, const double y[6], double s,
 /* Reverse-mode replay (full tape).  ubar: cotangent of u_N (3); Lbar:
  * cotangent of the path length (t-bar * Mpc / c).  Outputs: u0bar (cotangent
  * of the raw initial direction), x0bar; gbar (3 n0 n1 n2, FP64) accumulated if
- * not NULL.  Returns 0 or -1. */
+ * not NULL; kappabar (may be NULL): the cotangent of kappa = Z K / E, summed
+ * over the stages from the last step to the first (the crossing s* depends on
+ * kappa too and is carried by the combined cotangent of the last step); the
+ * energy gradient is kappabar * (-kappa / E).  Returns 0 or -1. */
 int oracle_replay_adjoint(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2, const double *origin,
                           double spacing, const void *mod, const double *mod_desc, double kappa, const double *x0, const double *u0, const double *h,
                           int64_t n, int event, const double *c, double R, const double *ubar, double Lbar,
-                          double *u0bar, double *x0bar, double *gbar)
+                          double *u0bar, double *x0bar, double *gbar, double *kappabar)
 {
     grid_t g;
     if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing, mod, mod_desc) || n < 1)
@@ -1133,6 +1139,7 @@ int oracle_replay_adjoint(const void *grid, int dtype, int64_t n0, int64_t n1, i
     const double *yl = ys + 6 * (n - 1);
     double lam[6] = {0.0, 0.0, 0.0, ubar[0], ubar[1], ubar[2]};
     double ybar[6];
+    double kb = 0.0;
     double sstar = h[n - 1];
     if (event) {
         double y5[6], d5[6];
@@ -1162,13 +1169,13 @@ int oracle_replay_adjoint(const void *grid, int dtype, int64_t n0, int64_t n1, i
         double comb[6];
         for (int a = 0; a < 6; ++a)
             comb[a] = -(psi / gs) * dg[a];
-        step_vjp(&g, kappa, yl, sstar, lam, comb, ybar, gbar);
+        step_vjp(&g, kappa, yl, sstar, lam, comb, ybar, gbar, &kb);
     } else {
-        step_vjp(&g, kappa, yl, sstar, lam, NULL, ybar, gbar);
+        step_vjp(&g, kappa, yl, sstar, lam, NULL, ybar, gbar, &kb);
     }
     for (int64_t s = n - 2; s >= 0; --s) {
         double nb[6];
-        step_vjp(&g, kappa, ys + 6 * s, h[s], ybar, NULL, nb, gbar);
+        step_vjp(&g, kappa, ys + 6 * s, h[s], ybar, NULL, nb, gbar, &kb);
         memcpy(ybar, nb, sizeof nb);
     }
     /* initial normalisation */
@@ -1178,6 +1185,8 @@ int oracle_replay_adjoint(const void *grid, int dtype, int64_t n0, int64_t n1, i
         u0bar[a] = (ybar[3 + a] - lu * u[a]) / un;
         x0bar[a] = ybar[a];
     }
+    if (kappabar)
+        *kappabar = kb;
     free(ys);
     return 0;
 }

@@ -50,7 +50,7 @@ def lib():
                                                          C.c_int, _pd, C.c_double, _pd]
         L.oracle_replay_tangent.restype = C.c_int
         L.oracle_replay_adjoint.argtypes = _GRID_ARGS + [C.c_double, _pd, _pd, _pd, C.c_int64, C.c_int, _pd,
-                                                         C.c_double, _pd, C.c_double, _pd, _pd, _pdn]
+                                                         C.c_double, _pd, C.c_double, _pd, _pd, _pdn, _pd]
         L.oracle_replay_adjoint.restype = C.c_int
         for f in (L.oracle_field_at, L.oracle_ck_eval, L.oracle_fixed_steps, L.oracle_propagate):
             f.restype = C.c_int
@@ -221,16 +221,18 @@ def replay_tangent(grid: Grid, kap: float, x0, u0, h, event: bool, center=(0.0, 
 def replay_adjoint(grid: Grid, kap: float, x0, u0, h, event: bool, ubar, lbar: float, center=(0.0, 0.0, 0.0),
                    radius=0.0, gbar=None) -> dict:
     """Full-tape reverse sweep of the frozen-step replay.  gbar (FP64 array of
-    the grid's shape) is accumulated in place when given."""
+    the grid's shape) is accumulated in place when given.  kappabar: the
+    cotangent of kappa (the energy gradient is kappabar * (-kappa / E))."""
     u0b = np.zeros(3)
     x0b = np.zeros(3)
+    kb = np.zeros(1)
     if gbar is not None:
         assert gbar.dtype == np.float64 and gbar.flags.c_contiguous
     rc = lib().oracle_replay_adjoint(*grid.args(), float(kap), np.ascontiguousarray(x0, np.float64),
                                      np.ascontiguousarray(u0, np.float64), np.ascontiguousarray(h, np.float64),
                                      len(h), int(bool(event)), np.asarray(center, np.float64), float(radius),
                                      np.ascontiguousarray(ubar, np.float64), float(lbar), u0b, x0b,
-                                     None if gbar is None else gbar.ctypes.data)
+                                     None if gbar is None else gbar.ctypes.data, kb)
     if rc:
         raise ValueError("oracle_replay_adjoint: no crossing bracketed or bad arguments")
-    return {"u0bar": u0b, "x0bar": x0b}
+    return {"u0bar": u0b, "x0bar": x0b, "kappabar": float(kb[0])}
