@@ -248,17 +248,22 @@ size_t crp_adjoint_workspace_bytes(int64_t n, int32_t every_k);
  * parameter group of the forward run; `initial` = the particles' state before
  * the forward run (raw direction, energy, charge); the cotangents gbar_dir
  * ([dev] n x 3) of the final direction and gbar_time ([dev] n, per second) of
- * the arrival time; gbar_energy may be NULL (the energy is unchanged, so it
- * contributes nothing).  Outputs: grad_u0 ([dev] n x 3, written) with
+ * the arrival time; gbar_energy ([dev] n, may be NULL) of the final energy,
+ * which equals the initial one.  Outputs: grad_u0 ([dev] n x 3, written) with
  * respect to the initial direction (as given, before normalisation),
- * grad_x0 ([dev] n x 3, written, may be NULL), and grad_field ([dev] FP64
+ * grad_x0 ([dev] n x 3, written, may be NULL), grad_energy ([dev] n, written,
+ * may be NULL) with respect to the initial energy in eV: the rigidity
+ * derivative (section 3.3: rigidity sets the deflection), kappa-bar * (-kappa /
+ * E) with kappa = Z K / E and kappa-bar the cotangent of kappa summed over
+ * every stage of the replay, plus gbar_energy; and grad_field ([dev] FP64
  * [n0][n1][n2][3], accumulated: the caller zeroes it) with respect to the
  * grid values in nG.  Particles without a complete tape get zero gradients.
  * workspace: [dev] crp_adjoint_workspace_bytes(n, K) bytes, 256-aligned. */
 crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *params, const crp_particles *initial,
                                  int64_t n, const crp_tape *tape, const double *gbar_dir, const double *gbar_time,
                                  const double *gbar_energy, double *grad_u0, double *grad_x0,
-                                 double *grad_field, void *workspace, size_t workspace_bytes, void *stream);
+                                 double *grad_energy, double *grad_field, void *workspace, size_t workspace_bytes,
+                                 void *stream);
 
 /* A captured propagation (hipGraph): the whole sequence of crp_propagate for
  * these exact arguments (descriptor tables, queue reset, longest-first order,

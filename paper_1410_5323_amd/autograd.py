@@ -5,16 +5,15 @@ particles from a fresh start in one field (section 3.2 grid, Lorentz-force
 equation of section 2.1 in path length, Cash-Karp steps of section 3.1) and
 returns the arrival direction, arrival time and energy.  Its backward pass
 gives the gradients with respect to the initial direction, the initial
-position and the grid values.
+position, the energy (through the rigidity E/Z, which sets the deflection;
+the output energy equals the input one) and the grid values.
 
 The derivative is that of the replayed map: the accepted step sizes of the
 forward run are held fixed and the sphere crossing of the last step is
 differentiated through its defining equation.  The forward records a
 checkpoint every ``every_k`` accepted steps into a pool of records (run a
 second time only if the pool was too small).  The backward pass replays each
-segment from its checkpoint on the GPU and sweeps it in reverse.  The energy is unchanged by the propagation, so its
-cotangent contributes nothing; no gradient with respect to the input energy
-is computed (asking for one raises).
+segment from its checkpoint on the GPU and sweeps it in reverse.
 """
 from __future__ import annotations
 
@@ -40,8 +39,6 @@ def _initial_state(u0, x0, energy, charge):
 class PropagateFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u0, grid, x0, energy, charge, spacing, origin, params, layout, every_k, tape_capacity):
-        if ctx.needs_input_grad[3]:
-            raise NotImplementedError("no gradient with respect to the particle energy")
         if u0.dtype != torch.float64 or x0.dtype != torch.float64 or energy.dtype != torch.float64:
             raise TypeError("u0, x0 and energy must be float64")
         if grid.dtype not in (torch.float64, torch.float32):
@@ -72,15 +69,18 @@ class PropagateFunction(torch.autograd.Function):
         gd = (g_dir if g_dir is not None else torch.zeros(n, 3, dtype=torch.float64, device=dev))
         gd = gd.to(torch.float64).contiguous()
         gt = g_time.to(torch.float64).contiguous() if g_time is not None else None
+        ge = g_energy.to(torch.float64).contiguous() if g_energy is not None else None
         grad_u0 = torch.empty(n, 3, dtype=torch.float64, device=dev)
         grad_x0 = torch.empty(n, 3, dtype=torch.float64, device=dev)
+        grad_e = torch.empty(n, dtype=torch.float64, device=dev)
         grad_field = torch.zeros(ctx.grid_shape, dtype=torch.float64, device=dev)
         crp.crp_propagate_adjoint(ctx.field, ctx.params, ctx.init, ctx.tape, gd, gt, grad_u0, grad_field,
-                                  grad_x0=grad_x0)
+                                  grad_x0=grad_x0, gbar_energy=ge, grad_energy=grad_e)
         gu = grad_u0 if ctx.needs_input_grad[0] else None
         gg = grad_field.to(ctx.grid_dtype) if ctx.needs_input_grad[1] else None
         gx = grad_x0 if ctx.needs_input_grad[2] else None
-        return gu, gg, gx, None, None, None, None, None, None, None, None
+        gE = grad_e if ctx.needs_input_grad[3] else None
+        return gu, gg, gx, gE, None, None, None, None, None, None, None
 
 
 def propagate(u0, grid, x0, energy, charge, spacing: float, params, layout: str = "linear", every_k: int = 64,

@@ -100,8 +100,8 @@ def lib():
         L.crp_adjoint_workspace_bytes.restype = C.c_size_t
         L.crp_propagate_adjoint.argtypes = [C.POINTER(crp_field), C.POINTER(crp_params), C.POINTER(crp_particles),
                                             C.c_int64, C.POINTER(crp_tape), C.c_void_p, C.c_void_p, C.c_void_p,
-                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
-                                            C.c_void_p]
+                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_size_t, C.c_void_p]
         L.crp_propagate_adjoint.restype = C.c_int
         L.crp_selftest_arith.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
         L.crp_bench_gather.argtypes = [C.POINTER(crp_field), C.c_int64, C.c_int64, C.c_double, C.c_uint64,
@@ -249,7 +249,7 @@ def crp_adjoint_workspace_bytes(n: int, every_k: int) -> int:
 
 
 def crp_propagate_adjoint(field, params, initial: dict, tape: Tape, gbar_dir, gbar_time, grad_u0, grad_field,
-                          grad_x0=None, gbar_energy=None, workspace=None, stream=None):
+                          grad_x0=None, gbar_energy=None, workspace=None, stream=None, grad_energy=None):
     """Reverse-mode derivatives of a taped forward run (see crp.h)."""
     torch = _torch()
     n = int(initial["energy"].numel())
@@ -260,7 +260,8 @@ def crp_propagate_adjoint(field, params, initial: dict, tape: Tape, gbar_dir, gb
                                 device=initial["energy"].device)
     _check(lib().crp_propagate_adjoint(C.byref(field.desc), C.byref(params), C.byref(ps), n, C.byref(tape.desc),
                                        _ptr(gbar_dir), _ptr(gbar_time), _ptr(gbar_energy), _ptr(grad_u0),
-                                       _ptr(grad_x0), _ptr(grad_field), _ptr(workspace), workspace.numel(),
+                                       _ptr(grad_x0), _ptr(grad_energy), _ptr(grad_field), _ptr(workspace),
+                                       workspace.numel(),
                                        _stream_handle(stream)))
 
 

@@ -400,10 +400,10 @@ size_t crp_adjoint_workspace_bytes(int64_t n, int32_t every_k) {
 
 crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *params, const crp_particles *initial,
                                  int64_t n, const crp_tape *tape, const double *gbar_dir, const double *gbar_time,
-                                 const double *gbar_energy, double *grad_u0, double *grad_x0, double *grad_field,
+                                 const double *gbar_energy, double *grad_u0, double *grad_x0, double *grad_energy,
+                                 double *grad_field,
                                  void *workspace, size_t workspace_bytes, void *stream) {
     const char *fn = "crp_propagate_adjoint";
-    (void)gbar_energy;  // the energy is unchanged by the propagation: no contribution
     crp_status st = check_field(field, true, fn);
     if (st != CRP_OK) return st;
     if (field->dtype != CRP_F64 && field->dtype != CRP_F32)
@@ -451,8 +451,10 @@ crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *param
     a.K = tape->every_k;
     a.gbar_dir = gbar_dir;
     a.gbar_time = gbar_time;
+    a.gbar_energy = gbar_energy;
     a.grad_u0 = grad_u0;
     a.grad_x0 = grad_x0;
+    a.grad_energy = grad_energy;
     a.grad_field = grad_field;
     a.segbuf = reinterpret_cast<double *>(ws + off_seg);
     a.lanes = lanes;

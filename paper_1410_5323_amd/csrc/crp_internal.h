@@ -114,8 +114,8 @@ struct AdjArgs {
     int64_t cap;
     int32_t K;
     int32_t pad_;
-    const double *gbar_dir, *gbar_time;
-    double *grad_u0, *grad_x0, *grad_field;
+    const double *gbar_dir, *gbar_time, *gbar_energy;
+    double *grad_u0, *grad_x0, *grad_energy, *grad_field;
     double *segbuf;                  // [step j][58][lane] replay records, then [36][lane] scratch
     int64_t lanes;                   // threads launched (segbuf stride)
     unsigned long long *queue;

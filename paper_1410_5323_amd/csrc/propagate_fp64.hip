@@ -748,7 +748,7 @@ __device__ __forceinline__ void grad_select(const FieldDev &F, GradAccum &g, con
 // crossing term).  Grid-gradient contributions go to gbar.
 template <class T, int LAYOUT>
 __device__ void reverse_step(const FieldDev &F, double kap, const double *r, int64_t stride, double lam[6],
-                             const double *comb, GradAccum &acc, double *gbar) {
+                             const double *comb, GradAccum &acc, double *gbar, double &kbar) {
     const double s = r[REC_H * stride];
     double z[6];
 #pragma unroll
@@ -780,6 +780,9 @@ __device__ void reverse_step(const FieldDev &F, double kap, const double *r, int
         const double *U = Y + 3;
         const double Bb[3] = {kap * (kb[4] * U[2] - kb[5] * U[1]), kap * (kb[5] * U[0] - kb[3] * U[2]),
                               kap * (kb[3] * U[1] - kb[4] * U[0])};
+        // kappa enters the stage as kappa U x B: kappa-bar += ku . (U x B)
+        kbar += kb[3] * (U[1] * B[2] - U[2] * B[1]) + kb[4] * (U[2] * B[0] - U[0] * B[2]) +
+                kb[5] * (U[0] * B[1] - U[1] * B[0]);
         Yb[i][3] = kb[0] + kap * (B[1] * kb[5] - B[2] * kb[4]);
         Yb[i][4] = kb[1] + kap * (B[2] * kb[3] - B[0] * kb[5]);
         Yb[i][5] = kb[2] + kap * (B[0] * kb[4] - B[1] * kb[3]);
@@ -829,6 +832,7 @@ struct AdjLane {
     int64_t slot;     // tape record of that segment's first state
     int flags;
     double kap, Lbar;
+    double kbar;      // cotangent of kappa, summed from the last step back
     double lam[6];    // cotangent of the state after the segment being processed
 };
 
@@ -847,6 +851,20 @@ __device__ __forceinline__ void adj_finish(const AdjArgs &a, const AdjLane &L) {
     }
     if (a.grad_x0)
         for (int c = 0; c < 3; ++c) a.grad_x0[3 * p + c] = L.lam[c];
+    if (a.grad_energy) {
+        // d kappa / d E = -kappa / E
+        const double ge = L.kbar * (-(L.kap / a.energy[p]));
+        a.grad_energy[p] = a.gbar_energy ? a.gbar_energy[p] + ge : ge;
+    }
+}
+
+// A particle with no adjoint (incomplete tape or broken record chain): zero gradients.
+__device__ __forceinline__ void adj_zero(const AdjArgs &a, int64_t p) {
+    for (int c = 0; c < 3; ++c) {
+        a.grad_u0[3 * p + c] = 0.0;
+        if (a.grad_x0) a.grad_x0[3 * p + c] = 0.0;
+    }
+    if (a.grad_energy) a.grad_energy[p] = 0.0;
 }
 
 // One lane per particle; the lanes of a wavefront move through their
@@ -882,13 +900,12 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
             for (int c = 0; c < 3; ++c) L.lam[c] = 0.0;
             for (int c = 0; c < 3; ++c) L.lam[3 + c] = a.gbar_dir[3 * p + c];
             if (!(L.flags & CRP_TAPE_COMPLETE) || (L.flags & CRP_TAPE_OVERFLOW)) {
-                for (int c = 0; c < 3; ++c) {
-                    a.grad_u0[3 * p + c] = 0.0;
-                    if (a.grad_x0) a.grad_x0[3 * p + c] = 0.0;
-                }
+                adj_zero(a, p);
                 L.p = -1;
                 continue;
             }
+            L.kap = ((double)a.charge[p] * K_LORENTZ) / a.energy[p];
+            L.kbar = 0.0;
             if (L.N == 0) {
                 adj_finish(a, L);
                 L.p = -1;
@@ -896,14 +913,10 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
             }
             L.slot = (int64_t)fin[2];
             if (L.slot < 0 || L.slot >= a.cap) {  // no record although steps were taken: no adjoint
-                for (int c = 0; c < 3; ++c) {
-                    a.grad_u0[3 * p + c] = 0.0;
-                    if (a.grad_x0) a.grad_x0[3 * p + c] = 0.0;
-                }
+                adj_zero(a, p);
                 L.p = -1;
                 continue;
             }
-            L.kap = ((double)a.charge[p] * K_LORENTZ) / a.energy[p];
             L.Lbar = a.gbar_time ? a.gbar_time[p] * SEC_PER_MPC : 0.0;
             L.seg = (L.N + a.K - 1) / a.K - 1;
         }
@@ -958,13 +971,14 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
                 gs += dg[c] * zs[c];
             }
             double comb[3] = {-(psi / gs) * dg[0], -(psi / gs) * dg[1], -(psi / gs) * dg[2]};
-            reverse_step<T, LAYOUT>(a.F, L.kap, r, a.lanes, L.lam, comb, acc, a.grad_field);
+            reverse_step<T, LAYOUT>(a.F, L.kap, r, a.lanes, L.lam, comb, acc, a.grad_field, L.kbar);
         }
         // reverse sweep (the crossing step, if any, is done above)
         const int mrev = event ? m - 1 : m;
         for (int j = mmax - 1; j >= 0; --j)
-            if (j < mrev) reverse_step<T, LAYOUT>(a.F, L.kap, col + (int64_t)j * rstride, a.lanes, L.lam, nullptr, acc,
-                                                  a.grad_field);
+            if (j < mrev)
+                reverse_step<T, LAYOUT>(a.F, L.kap, col + (int64_t)j * rstride, a.lanes, L.lam, nullptr, acc,
+                                        a.grad_field, L.kbar);
         if (busy) {
             if (--L.seg < 0) {
                 grad_flush(a.F, acc, a.grad_field);
@@ -974,10 +988,7 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
                 L.slot = a.link[L.slot];
                 if (L.slot < 0 || L.slot >= a.cap) {  // a broken chain: no adjoint for this particle
                     grad_flush(a.F, acc, a.grad_field);
-                    for (int c = 0; c < 3; ++c) {
-                        a.grad_u0[3 * L.p + c] = 0.0;
-                        if (a.grad_x0) a.grad_x0[3 * L.p + c] = 0.0;
-                    }
+                    adj_zero(a, L.p);
                     L.p = -1;
                 }
             }

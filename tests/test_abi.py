@@ -172,7 +172,7 @@ def test_tape_and_adjoint_reject_bad_arguments_without_device(crp):
 
     def adj(field=f, params=p, t=tape, n=10, g=0x6000, gu=0x7000, gf=0x8000, ws=None, wsb=0):
         return L.crp_propagate_adjoint(C.byref(field), C.byref(params), C.byref(parts), n, C.byref(t), g, None, None,
-                                       gu, None, gf, ws, wsb, None)
+                                       gu, None, None, gf, ws, wsb, None)
 
     assert adj(n=-1) == crp.CRP_ERR_INVALID
     assert adj(t=crp.crp_tape(0x3000, 0x4000, 0x5000, 0x5800, 100, 0, 0)) == crp.CRP_ERR_INVALID
@@ -253,7 +253,7 @@ def test_reflective_box_checks(crp):
     tape = crp.crp_tape(0x3000, 0x4000, 0x5000, 0x5800, 100, 64, 0)
     assert call(good, tape=tape) == crp.CRP_ERR_UNSUPPORTED
     assert L.crp_propagate_adjoint(C.byref(f), C.byref(good), C.byref(parts), 10, C.byref(tape), 0x6000, None, None,
-                                   0x7000, None, 0x8000, None, 0, None) == crp.CRP_ERR_UNSUPPORTED
+                                   0x7000, None, None, 0x8000, None, 0, None) == crp.CRP_ERR_UNSUPPORTED
     # a box that is off (reflect = 0) is not checked
     off = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0)
     off.box_lo[0] = 5.0
@@ -281,7 +281,7 @@ def test_backtrack_checks(crp):
     assert call(bt, prec=crp.CRP_PREC_MIXED_F64ACC) == crp.CRP_ERR_WORKSPACE  # the mixed kernel backtracks too
     assert call(bt, t=tape) == crp.CRP_ERR_UNSUPPORTED
     assert L.crp_propagate_adjoint(C.byref(f), C.byref(bt), C.byref(parts), 10, C.byref(tape), 0x6000, None, None,
-                                   0x7000, None, 0x8000, None, 0, None) == crp.CRP_ERR_UNSUPPORTED
+                                   0x7000, None, None, 0x8000, None, 0, None) == crp.CRP_ERR_UNSUPPORTED
     bad = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0)
     bad.backtrack = -1
     assert call(bad) == crp.CRP_ERR_INVALID

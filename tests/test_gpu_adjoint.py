@@ -36,7 +36,7 @@ def dev():
 
 
 def _gpu_adjoint(crp, torch, B, spacing, prm, pos, dirs, energy, charge, gdir, gtime, every_k=64,
-                 layout="linear", capacity=None):
+                 layout="linear", capacity=None, genergy=None):
     dt = "f64" if B.dtype == np.float64 else "f32"
     f = crp.make_field(B, spacing, dtype=dt, layout=layout)
     init = crp.particles_to_device(pos, dirs, energy, charge)
@@ -51,11 +51,14 @@ def _gpu_adjoint(crp, torch, B, spacing, prm, pos, dirs, energy, charge, gdir, g
     gu = torch.full((n, 3), np.nan, dtype=torch.float64, device="cuda")
     gx = torch.full((n, 3), np.nan, dtype=torch.float64, device="cuda")
     gg = torch.zeros(B.shape, dtype=torch.float64, device="cuda")
+    ge = torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
     gd = torch.from_numpy(np.ascontiguousarray(gdir, dtype=np.float64)).cuda()
     gt = torch.from_numpy(np.ascontiguousarray(gtime, dtype=np.float64)).cuda()
-    crp.crp_propagate_adjoint(f, prm, init, tape, gd, gt, gu, gg, grad_x0=gx)
+    gbe = None if genergy is None else torch.from_numpy(np.ascontiguousarray(genergy, dtype=np.float64)).cuda()
+    crp.crp_propagate_adjoint(f, prm, init, tape, gd, gt, gu, gg, grad_x0=gx, gbar_energy=gbe, grad_energy=ge)
     torch.cuda.synchronize()
     return {"state": crp.particles_to_host(st), "gu": gu.cpu().numpy(), "gx": gx.cpu().numpy(),
+            "ge": ge.cpu().numpy(),
             "gg": gg.cpu().numpy(), "flags": tape.flags().cpu().numpy(),
             "finals": tape.finals.view(-1, 4).cpu().numpy()}
 
@@ -63,7 +66,7 @@ def _gpu_adjoint(crp, torch, B, spacing, prm, pos, dirs, energy, charge, gdir, g
 def _oracle_adjoint(O, B, spacing, prm_arr, pos, dirs, energy, charge, gdir, gtime, center, radius):
     g = O.Grid(B, spacing)
     gbar = np.zeros(B.shape, dtype=np.float64)
-    gu, gx, steps = [], [], []
+    gu, gx, ge, steps = [], [], [], []
     for i in range(len(energy)):
         t = O.propagate_taped(g, prm_arr, pos[i], dirs[i], energy[i], charge[i])
         assert t["status"] in (1, 2)
@@ -71,8 +74,18 @@ def _oracle_adjoint(O, B, spacing, prm_arr, pos, dirs, energy, charge, gdir, gti
                              gtime[i] * SEC_PER_MPC, center=center, radius=radius, gbar=gbar)
         gu.append(a["u0bar"])
         gx.append(a["x0bar"])
+        kap = O.kappa(charge[i], energy[i])
+        ge.append(a["kappabar"] * (-(kap / energy[i])))  # d kappa / d E = -kappa / E
         steps.append(t["n_steps"])
+    _oracle_adjoint.last_ge = np.array(ge)
     return np.array(gu), np.array(gx), gbar, np.array(steps)
+
+
+def _rel_scalar(a, b):
+    """Relative difference of scalars, against |b| floored at 1e-6 of the
+    sample's median |b| (a near-cancelled sum has no relative accuracy)."""
+    floor = 1e-6 * max(np.median(np.abs(b)), 1e-300)
+    return np.abs(a - b) / np.maximum(np.abs(b), floor)
 
 
 def _rel(a, b):
@@ -92,9 +105,10 @@ def _check_against_oracle(O, r, B, spacing, prm_arr, P, sel, gdir, gtime, center
     assert np.array_equal(r["finals"][:, 0].astype(np.int64), steps), f"{label}: accepted-step counts differ"
     eu, ex = _rel(r["gu"], gu), _rel(r["gx"], gx)
     eg = _rel_all(r["gg"], gbar)
+    ee = _rel_scalar(r["ge"], _oracle_adjoint.last_ge)
     _say(f"{label}: steps {steps.min()}..{steps.max()}, max rel err grad_u0 {eu.max():.2e}, "
-         f"grad_x0 {ex.max():.2e}, grid {eg:.2e}")
-    assert eu.max() <= GRAD_TOL and ex.max() <= GRAD_TOL and eg <= GRAD_TOL
+         f"grad_x0 {ex.max():.2e}, grad_energy {ee.max():.2e}, grid {eg:.2e}")
+    assert eu.max() <= GRAD_TOL and ex.max() <= GRAD_TOL and eg <= GRAD_TOL and ee.max() <= GRAD_TOL
 
 
 def test_adjoint_matches_oracle_small_grid(dev, oracle_mod):
@@ -162,6 +176,11 @@ def test_uniform_field_rotation(dev):
     J = Rm @ (np.eye(3) - np.outer(u0, u0))
     assert np.max(np.abs(r["gu"][:3] - J)) < 1e-7  # row a of J is J^T e_a
     assert np.all(r["gu"][3] == 0.0) and np.all(r["gx"][3] == 0.0)
+    # rigidity: d u_N / d kappa = -|B| L (b x u_N), d kappa / d E = -kappa / E
+    uN = r["state"]["dir"][0]
+    du_dE = (-kap / E) * (-np.linalg.norm(Bv) * L * np.cross(bh, uN))
+    assert np.max(np.abs(r["ge"][:3] - du_dE)) < 1e-7 * np.linalg.norm(du_dE)
+    assert r["ge"][3] == 0.0  # the path length of a length stop does not depend on E
 
 
 def test_edge_cases(dev):
@@ -178,6 +197,7 @@ def test_edge_cases(dev):
     r = _gpu_adjoint(crp, torch, B, w.spacing, prm, np.array([[5.0, 0, 0], [0, 0, -9.0]]), u0, np.full(2, 1e18),
                      np.ones(2, np.int32), lam, np.ones(2))
     assert np.all(r["state"]["status"] == 1) and np.all(r["finals"][:, 0] == 0)
+    assert np.all(r["ge"] == 0.0)
     for i in range(2):
         nu = np.linalg.norm(u0[i])
         uh = u0[i] / nu
@@ -191,8 +211,13 @@ def test_edge_cases(dev):
     over = (r["flags"] & 2) != 0
     # the record after step 4 is needed only if the particle goes on after it
     assert np.array_equal(over, r["finals"][:, 0] > 4)
-    assert np.all(r["gu"][over] == 0.0) and np.all(r["gx"][over] == 0.0)
+    assert np.all(r["gu"][over] == 0.0) and np.all(r["gx"][over] == 0.0) and np.all(r["ge"][over] == 0.0)
     assert over.any()
+    _say("case: the energy cotangent passes through (the energy is unchanged)")
+    g6 = np.arange(6, dtype=np.float64) + 0.5
+    r2 = _gpu_adjoint(crp, torch, B, w.spacing, prm, P["pos"], P["dir"], P["energy"], P["charge"],
+                      np.zeros((6, 3)), np.zeros(6), genergy=g6)
+    assert np.array_equal(r2["ge"], g6)
 
 
 def _affine_grid():
@@ -226,7 +251,7 @@ def test_autograd_against_central_differences(dev):
     grid = torch.from_numpy(B).cuda().requires_grad_(True)
     u0 = torch.from_numpy(P["dir"]).cuda().requires_grad_(True)
     x0 = torch.from_numpy(P["pos"]).cuda()
-    E = torch.from_numpy(P["energy"]).cuda()
+    E = torch.from_numpy(P["energy"]).cuda().requires_grad_(True)
     Zt = torch.from_numpy(P["charge"].astype(np.int32)).cuda()
     _say("case: autograd forward/backward, affine field")
     d, t, e, st = propagate(u0, grid, x0, E, Zt, sp, prm, origin=org)
@@ -236,10 +261,11 @@ def test_autograd_against_central_differences(dev):
     assert torch.equal(e, E)
     gu = u0.grad.cpu().numpy()
     gg = grid.grad.cpu().numpy()
+    gE = E.grad.cpu().numpy()
 
-    def losses(u, Bg):
+    def losses(u, Bg, En=P["energy"]):
         f = crp.make_field(Bg, sp, origin=org, dtype="f64")
-        s = crp.particles_to_device(P["pos"], u, P["energy"], P["charge"])
+        s = crp.particles_to_device(P["pos"], u, En, P["charge"])
         crp.crp_propagate([f], [prm], s)
         dd = torch.stack([s["ux"], s["uy"], s["uz"]], 1)
         return ((dd * wd).sum(1) + s["time"] * wt).cpu().numpy()
@@ -257,6 +283,18 @@ def test_autograd_against_central_differences(dev):
     err = np.abs(d1 - jv) / np.abs(jv)
     _say(f"u0 directional derivatives: max rel err {err.max():.2e}")
     assert err.max() <= 1e-6
+
+    _say("case: central differences in the energy (rigidity)")
+
+    def fde(eps):
+        return (losses(P["dir"], B, P["energy"] * (1 + eps)) - losses(P["dir"], B, P["energy"] * (1 - eps))) / (
+            2 * eps * P["energy"])
+
+    e1, e2 = fde(1e-6), fde(2e-6)
+    assert np.max(np.abs(e1 - e2) / np.abs(e1)) <= 1e-5  # smooth at this scale
+    errE = np.abs(e1 - gE) / np.abs(e1)
+    _say(f"energy derivatives: max rel err {errE.max():.2e}")
+    assert errE.max() <= 1e-5
 
     _say("case: central differences in grid values")
     for fi in np.argsort(-np.abs(gg).ravel())[:4]:
@@ -308,8 +346,9 @@ def test_full_adjoint_workload_sampled(dev, oracle_mod):
                                         P["charge"][sel], gdir[sel], gtime[sel], (0.0, 0.0, 0.0), w.obs_radius)
     assert np.array_equal(steps[sel].astype(np.int64), ost)
     eu = _rel(r["gu"][sel], gu)
-    _say(f"sampled steps {ost.min()}..{ost.max()}, max rel err grad_u0 {eu.max():.2e}")
-    assert eu.max() <= GRAD_TOL
+    ee = _rel_scalar(r["ge"][sel], _oracle_adjoint.last_ge)
+    _say(f"sampled steps {ost.min()}..{ost.max()}, max rel err grad_u0 {eu.max():.2e}, grad_energy {ee.max():.2e}")
+    assert eu.max() <= GRAD_TOL and ee.max() <= GRAD_TOL
     # the gradients that overflow on the GPU overflow in the oracle's adjoint too
     bad = np.nonzero(~fin)[0]
     if len(bad):
