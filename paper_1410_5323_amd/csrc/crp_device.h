@@ -200,25 +200,47 @@ __device__ __forceinline__ void cache_reset(CellCache<T> &c, T (*lds)[CACHE_BLOC
     c.misses = 0;
 }
 
-// Modulation value at X (section 3.2, modulated grids): trilinear on the
-// padded scalar grid, x then y then z, as the vector components.
+// Modulation corners of the cell holding X (section 3.2, modulated grids):
+// the padded scalar grid's 8 stored values and the cell fractions.
 template <class M>
-__device__ __forceinline__ double mod_interp(const FieldDev &F, const double X[3]) {
+struct ModCorners {
+    M v000, v001, v100, v101, v010, v011, v110, v111;
     double t[3];
+};
+
+template <class M>
+__device__ __forceinline__ void mod_load(const FieldDev &F, const double X[3], ModCorners<M> &m) {
     int c[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) c[a] = cell_axis(X[a], F.mod_origin[a], F.mod_inv_spacing, F.mod_n[a], F.mod_pow2, t[a]);
+    for (int a = 0; a < 3; ++a) c[a] = cell_axis(X[a], F.mod_origin[a], F.mod_inv_spacing, F.mod_n[a], F.mod_pow2, m.t[a]);
     const global_ptr<M> p = as_global<M>(F.mod_data) + ((uint32_t)c[0] * F.mod_sx + (uint32_t)c[1] * F.mod_sy + (uint32_t)c[2]);
     const uint32_t sx = F.mod_sx, sy = F.mod_sy;
-    const double v000 = (double)p[0], v001 = (double)p[1];
-    const double v100 = (double)p[sx], v101 = (double)p[sx + 1];
-    const double v010 = (double)p[sy], v011 = (double)p[sy + 1];
-    const double v110 = (double)p[sx + sy], v111 = (double)p[sx + sy + 1];
-    const double c00 = lerp(v000, v100, t[0]);
-    const double c10 = lerp(v010, v110, t[0]);
-    const double c01 = lerp(v001, v101, t[0]);
-    const double c11 = lerp(v011, v111, t[0]);
-    return lerp(lerp(c00, c10, t[1]), lerp(c01, c11, t[1]), t[2]);
+    m.v000 = p[0];
+    m.v001 = p[1];
+    m.v100 = p[sx];
+    m.v101 = p[sx + 1];
+    m.v010 = p[sy];
+    m.v011 = p[sy + 1];
+    m.v110 = p[sx + sy];
+    m.v111 = p[sx + sy + 1];
+}
+
+// Modulation value from its corners: trilinear, x then y then z, as the
+// vector components.
+template <class M>
+__device__ __forceinline__ double mod_value(const ModCorners<M> &m) {
+    const double c00 = lerp((double)m.v000, (double)m.v100, m.t[0]);
+    const double c10 = lerp((double)m.v010, (double)m.v110, m.t[0]);
+    const double c01 = lerp((double)m.v001, (double)m.v101, m.t[0]);
+    const double c11 = lerp((double)m.v011, (double)m.v111, m.t[0]);
+    return lerp(lerp(c00, c10, m.t[1]), lerp(c01, c11, m.t[1]), m.t[2]);
+}
+
+template <class M>
+__device__ __forceinline__ double mod_interp(const FieldDev &F, const double X[3]) {
+    ModCorners<M> m;
+    mod_load<M>(F, X, m);
+    return mod_value<M>(m);
 }
 
 // B <- B * m(X) when the field carries a modulation grid.
@@ -230,14 +252,39 @@ __device__ __forceinline__ void modulate(const FieldDev &F, const double X[3], d
     B[2] = B[2] * m;
 }
 
+// Field value times modulation at X, the same arithmetic as lookup() then
+// modulate(), with both grids' corner loads issued before either
+// interpolation: the lookup waits for memory once, the two gathers' latencies
+// overlap instead of adding up.
+template <class T, int LAYOUT, class M>
+__device__ __forceinline__ void lookup_mod(const FieldDev &F, const double X[3], double B[3]) {
+    ModCorners<M> m;
+    mod_load<M>(F, X, m);
+    double tx, ty, tz;
+    int i = cell_axis(X[0], F.origin[0], F.inv_spacing, F.n[0], F.pow2, tx);
+    int j = cell_axis(X[1], F.origin[1], F.inv_spacing, F.n[1], F.pow2, ty);
+    int k = cell_axis(X[2], F.origin[2], F.inv_spacing, F.n[2], F.pow2, tz);
+    T v[24];
+    load_corners<T, LAYOUT>(F, i, j, k, v);
+    interp_corners<T>(F, v, tx, ty, tz, B);
+    const double mv = mod_value<M>(m);
+    B[0] = B[0] * mv;
+    B[1] = B[1] * mv;
+    B[2] = B[2] * mv;
+}
+
 // MOD: the launch has modulated fields (then each field's modulation, if any,
 // multiplies its value); without it no modulation code is compiled in.
 template <class T, int LAYOUT, bool CACHE, bool MOD = false>
 __device__ __forceinline__ void lookup_cached(const FieldDev &F, int fid, const double X[3], double B[3],
                                               CellCache<T> &cache) {
     if (!CACHE) {
-        lookup<T, LAYOUT>(F, X, B);
-        if (MOD) modulate(F, X, B);
+        if (!MOD || !F.mod_data)
+            lookup<T, LAYOUT>(F, X, B);
+        else if (F.mod_dtype == CRP_F64)
+            lookup_mod<T, LAYOUT, double>(F, X, B);
+        else
+            lookup_mod<T, LAYOUT, float>(F, X, B);
         cache.misses++;
         return;
     }

@@ -362,6 +362,8 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
     a.n = n;
     a.fields = reinterpret_cast<const crp::FieldDev *>(ws + wl.fields);
     a.params = reinterpret_cast<const crp::ParamsDev *>(ws + wl.params);
+    a.F0 = fd[params[0].field_index];  // the field of the single parameter group
+    a.P0 = pd[0];
     a.order = order;
     a.queue = reinterpret_cast<unsigned long long *>(ws);
     a.counters = reinterpret_cast<unsigned long long *>(counters);

@@ -100,6 +100,11 @@ struct PropArgs {
     int32_t n_params;
     int32_t modulated;               // some field carries a modulation grid
     int32_t reflective;              // some parameter group has a reflective box
+    // The first field and parameter group by value: a launch with one of each
+    // reads them from the kernel arguments with scalar loads, which never wait
+    // behind the lanes' field gathers as vector loads of the tables would.
+    FieldDev F0;
+    ParamsDev P0;
 };
 
 // Kernel arguments of the adjoint kernel.

@@ -178,7 +178,7 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
         a.status[p] = CRP_ST_BAD_INPUT;
         return false;
     }
-    const ParamsDev &P = a.params[MULTI ? s.pidx : 0];
+    const ParamsDev &P = MULTI ? a.params[s.pidx] : a.P0;
     double E = a.energy[p];
     int Z = a.charge[p];
     s.y[0] = a.x[p];
@@ -239,9 +239,9 @@ template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE, bool MOD, bool
 __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, CellCache<T> &cache, EventLDS &e,
                                        int &flags) {
     const int t = threadIdx.x;
-    const ParamsDev &P = a.params[MULTI ? s.pidx : 0];
+    const ParamsDev &P = MULTI ? a.params[s.pidx] : a.P0;
     const int fid = MULTI ? P.field_index : 0;
-    const FieldDev &F = a.fields[fid];
+    const FieldDev &F = MULTI ? a.fields[fid] : a.F0;
     double y5[6], ex, eu;
     ck_eval<T, LAYOUT, CACHE, NoStageRecord, MOD>(F, fid, cache, s.kap, s.y, s.h, y5, ex, eu);
     flags = F_EVAL;

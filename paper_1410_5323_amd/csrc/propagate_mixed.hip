@@ -340,7 +340,7 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane<ACC> &s
         a.status[p] = CRP_ST_BAD_INPUT;
         return false;
     }
-    const ParamsDev &P = a.params[MULTI ? s.pidx : 0];
+    const ParamsDev &P = MULTI ? a.params[s.pidx] : a.P0;
     double E = a.energy[p];
     int Z = a.charge[p];
     double x[3] = {a.x[p], a.y[p], a.z[p]};
@@ -396,9 +396,9 @@ template <class T, int LAYOUT, bool MULTI, int ACC, bool CACHE>
 __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &s, CellCache<T> &cache, EventLDS &e,
                                        int &flags) {
     const int t = threadIdx.x;
-    const ParamsDev &P = a.params[MULTI ? s.pidx : 0];
+    const ParamsDev &P = MULTI ? a.params[s.pidx] : a.P0;
     const int fid = MULTI ? P.field_index : 0;
-    const FieldDev &F = a.fields[fid];
+    const FieldDev &F = MULTI ? a.fields[fid] : a.F0;
     int ib[3];
     float tb[3];
     s.acc.cell(F, 0, ib[0], tb[0]);

@@ -90,6 +90,24 @@ def test_small_fp64_workload_full(dev, oracle_mod, c1):
     _say("small:", r)
 
 
+def test_single_group_uses_its_field(dev, oracle_mod, c1):
+    """One parameter group naming the second of two fields (no per-particle
+    groups): the launch must use that field."""
+    torch, crp = dev
+    w, B, P = c1
+    _say("case: one parameter group on field 1 of 2")
+    other = np.ascontiguousarray(B[::-1] * 2.0)
+    f0 = crp.make_field(other, w.spacing, dtype="f64")
+    f1 = crp.make_field(B, w.spacing, dtype="f64")
+    prm = crp.make_params(w.tol, w.h_min, w.h_max, obs_radius=1.5, l_max=20.0, field_index=1)
+    st = crp.particles_to_device(P["pos"], P["dir"], P["energy"], P["charge"])
+    crp.crp_propagate([f0, f1], [prm], st)
+    torch.cuda.synchronize()
+    g = crp.particles_to_host(st)
+    o = run_oracle(oracle_mod, B, w.spacing, w, P, radius=1.5, l_max=20.0)
+    compare(g, o, "field 1 of 2")
+
+
 @pytest.mark.parametrize("n", [1, 63, 65, 257, 3001])
 def test_ragged_sizes(dev, oracle_mod, c1, n):
     torch, crp = dev
