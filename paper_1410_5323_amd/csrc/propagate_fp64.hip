@@ -239,9 +239,17 @@ template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE, bool MOD, bool
 __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, CellCache<T> &cache, EventLDS &e,
                                        int &flags) {
     const int t = threadIdx.x;
-    const ParamsDev &P = MULTI ? a.params[s.pidx] : a.P0;
+    // per-particle groups: the lane's descriptors, read from the tables once
+    // per iteration into registers (the lanes of a wavefront may differ)
+    ParamsDev Pm;
+    FieldDev Fm;
+    if (MULTI) {
+        Pm = a.params[s.pidx];
+        Fm = a.fields[Pm.field_index];
+    }
+    const ParamsDev &P = MULTI ? Pm : a.P0;
     const int fid = MULTI ? P.field_index : 0;
-    const FieldDev &F = MULTI ? a.fields[fid] : a.F0;
+    const FieldDev &F = MULTI ? Fm : a.F0;
     double y5[6], ex, eu;
     ck_eval<T, LAYOUT, CACHE, NoStageRecord, MOD>(F, fid, cache, s.kap, s.y, s.h, y5, ex, eu);
     flags = F_EVAL;

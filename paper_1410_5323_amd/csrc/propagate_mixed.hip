@@ -396,9 +396,17 @@ template <class T, int LAYOUT, bool MULTI, int ACC, bool CACHE>
 __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &s, CellCache<T> &cache, EventLDS &e,
                                        int &flags) {
     const int t = threadIdx.x;
-    const ParamsDev &P = MULTI ? a.params[s.pidx] : a.P0;
+    // per-particle groups: the lane's descriptors, read from the tables once
+    // per iteration into registers (the lanes of a wavefront may differ)
+    ParamsDev Pm;
+    FieldDev Fm;
+    if (MULTI) {
+        Pm = a.params[s.pidx];
+        Fm = a.fields[Pm.field_index];
+    }
+    const ParamsDev &P = MULTI ? Pm : a.P0;
     const int fid = MULTI ? P.field_index : 0;
-    const FieldDev &F = MULTI ? a.fields[fid] : a.F0;
+    const FieldDev &F = MULTI ? Fm : a.F0;
     int ib[3];
     float tb[3];
     s.acc.cell(F, 0, ib[0], tb[0]);
