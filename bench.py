@@ -533,6 +533,12 @@ def main():
                    "cell_cache_hit_rate": 1.0 - int(c[6]) / max(1, 6 * evals),
                    "wave_iterations_per_launch": int(c[7]) / args.steps,
                    "lane_utilisation": evals / max(1, 64 * int(c[7])),
+                   # the longest trajectory's attempts bound the pass from below: at one
+                   # attempt per loop iteration its lane needs that many iterations in a row
+                   "max_attempts_one_particle": int(np.max(host["n_accepted"] + host["n_rejected"]))
+                   if n else 0,
+                   "launch_us_per_attempt_of_longest": avg_launch_s * 1e6
+                   / max(1, int(np.max(host["n_accepted"] + host["n_rejected"])) if n else 1),
                    "evaluations_per_s": evals / elapsed,
                    "avg_launch_ms": avg_launch_s * 1e3,
                    "algorithmic_bytes_per_evaluation": bytes_per_eval,
