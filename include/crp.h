@@ -122,7 +122,7 @@ typedef struct {
     int32_t field_index;   /* which entry of the fields array this group uses */
     int32_t reflect;       /* 1: reflective box below (FP64 precision, no tape); 0: none */
     double box_lo[3], box_hi[3];  /* Mpc, lo < hi on every axis when reflect = 1 */
-    int32_t backtrack;     /* 1: backtracking (section 3.3), no tape; 0: forward */
+    int32_t backtrack;     /* 1: backtracking (section 3.3); 0: forward */
     int32_t reserved;      /* 0 */
 } crp_params;
 
@@ -258,6 +258,10 @@ size_t crp_adjoint_workspace_bytes(int64_t n, int32_t every_k);
  * every stage of the replay, plus gbar_energy; and grad_field ([dev] FP64
  * [n0][n1][n2][3], accumulated: the caller zeroes it) with respect to the
  * grid values in nG.  Particles without a complete tape get zero gradients.
+ * A backtracked run (params->backtrack = 1) is differentiated as the forward
+ * run of the antiparticle it is: gradients and cotangents refer to the
+ * physical directions of the input and output, as crp_propagate reads and
+ * writes them.
  * workspace: [dev] crp_adjoint_workspace_bytes(n, K) bytes, 256-aligned. */
 crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *params, const crp_particles *initial,
                                  int64_t n, const crp_tape *tape, const double *gbar_dir, const double *gbar_time,

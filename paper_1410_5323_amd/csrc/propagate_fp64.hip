@@ -848,14 +848,17 @@ struct AdjLane {
 // is normalised on a fresh start.
 __device__ __forceinline__ void adj_finish(const AdjArgs &a, const AdjLane &L) {
     const int64_t p = L.p;
+    // a backtracked run is the forward run of the antiparticle with the
+    // direction reversed: its direction gradient is reversed back
+    const double sg = a.P.backtrack_on ? -1.0 : 1.0;
     if (L.flags & CRP_TAPE_FRESH) {
-        const double u0[3] = {a.ux0[p], a.uy0[p], a.uz0[p]};
+        const double u0[3] = {sg * a.ux0[p], sg * a.uy0[p], sg * a.uz0[p]};
         double un = sqrt(u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2]);
         double uh[3] = {u0[0] / un, u0[1] / un, u0[2] / un};
         double lu = L.lam[3] * uh[0] + L.lam[4] * uh[1] + L.lam[5] * uh[2];
-        for (int c = 0; c < 3; ++c) a.grad_u0[3 * p + c] = (L.lam[3 + c] - lu * uh[c]) / un;
+        for (int c = 0; c < 3; ++c) a.grad_u0[3 * p + c] = sg * ((L.lam[3 + c] - lu * uh[c]) / un);
     } else {
-        for (int c = 0; c < 3; ++c) a.grad_u0[3 * p + c] = L.lam[3 + c];
+        for (int c = 0; c < 3; ++c) a.grad_u0[3 * p + c] = sg * L.lam[3 + c];
     }
     if (a.grad_x0)
         for (int c = 0; c < 3; ++c) a.grad_x0[3 * p + c] = L.lam[c];
@@ -906,13 +909,14 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
             L.flags = (int)fin[3];
             L.N = (int64_t)fin[0];
             for (int c = 0; c < 3; ++c) L.lam[c] = 0.0;
-            for (int c = 0; c < 3; ++c) L.lam[3 + c] = a.gbar_dir[3 * p + c];
+            // backtracking: the cotangent of the antiparticle's (reversed) direction
+            for (int c = 0; c < 3; ++c) L.lam[3 + c] = a.P.backtrack_on ? -a.gbar_dir[3 * p + c] : a.gbar_dir[3 * p + c];
             if (!(L.flags & CRP_TAPE_COMPLETE) || (L.flags & CRP_TAPE_OVERFLOW)) {
                 adj_zero(a, p);
                 L.p = -1;
                 continue;
             }
-            L.kap = ((double)a.charge[p] * K_LORENTZ) / a.energy[p];
+            L.kap = ((double)(a.P.backtrack_on ? -a.charge[p] : a.charge[p]) * K_LORENTZ) / a.energy[p];
             L.kbar = 0.0;
             if (L.N == 0) {
                 adj_finish(a, L);

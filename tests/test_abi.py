@@ -261,7 +261,7 @@ def test_reflective_box_checks(crp):
 
 
 def test_backtrack_checks(crp):
-    """backtrack is 0 or 1; tapes and the adjoint refuse it."""
+    """backtrack is 0 or 1; tapes and the adjoint accept it."""
     L = crp.lib()
     f = _field(crp)
     f.data = 0x1000
@@ -279,9 +279,9 @@ def test_backtrack_checks(crp):
     assert bt.backtrack == 1
     assert call(bt) == crp.CRP_ERR_WORKSPACE
     assert call(bt, prec=crp.CRP_PREC_MIXED_F64ACC) == crp.CRP_ERR_WORKSPACE  # the mixed kernel backtracks too
-    assert call(bt, t=tape) == crp.CRP_ERR_UNSUPPORTED
+    assert call(bt, t=tape) == crp.CRP_ERR_WORKSPACE  # arguments fine, no workspace
     assert L.crp_propagate_adjoint(C.byref(f), C.byref(bt), C.byref(parts), 10, C.byref(tape), 0x6000, None, None,
-                                   0x7000, None, None, 0x8000, None, 0, None) == crp.CRP_ERR_UNSUPPORTED
+                                   0x7000, None, None, 0x8000, None, 0, None) == crp.CRP_ERR_WORKSPACE
     bad = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0)
     bad.backtrack = -1
     assert call(bad) == crp.CRP_ERR_INVALID
