@@ -373,8 +373,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the path shards "
-              "particles across GPUs by design but no multi-GPU run is part of it.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): particles are independent, so the "
+              "path shards by particles, but no multi-GPU run is measured here.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
