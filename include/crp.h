@@ -120,7 +120,7 @@ typedef struct {
     double l_max;          /* length limit, Mpc, > 0; +inf disables it (then max_steps > 0) */
     int64_t max_steps;     /* accepted steps allowed per particle in one call; 0 = no limit */
     int32_t field_index;   /* which entry of the fields array this group uses */
-    int32_t reflect;       /* 1: reflective box below (FP64 precision, no tape); 0: none */
+    int32_t reflect;       /* 1: reflective box below (no tape); 0: none */
     double box_lo[3], box_hi[3];  /* Mpc, lo < hi on every axis when reflect = 1 */
     int32_t backtrack;     /* 1: backtracking (section 3.3); 0: forward */
     int32_t reserved;      /* 0 */

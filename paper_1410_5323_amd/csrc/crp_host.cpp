@@ -284,8 +284,6 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
         return fail(CRP_ERR_UNSUPPORTED, "%s: modulated fields need F64 or F32 storage", fn);
     bool reflective = false;
     for (int i = 0; i < n_params; ++i) reflective = reflective || params[i].reflect != 0;
-    if (reflective && precision != CRP_PREC_FP64)
-        return fail(CRP_ERR_UNSUPPORTED, "%s: a reflective box needs FP64 precision", fn);
     if (tape) {
         if (precision != CRP_PREC_FP64) return fail(CRP_ERR_UNSUPPORTED, "%s: a tape needs FP64 precision", fn);
         if (modulated) return fail(CRP_ERR_UNSUPPORTED, "%s: no tape (adjoint) for modulated fields", fn);

@@ -91,6 +91,20 @@ template <> struct Acc<ACC_F64> {
         t = (float)(f - fl);
         i = wrap((int)fl, F.n[a], F.pow2);
     }
+    // reflective box: mirror the position on a face it crossed, negate that
+    // direction component
+    __device__ __forceinline__ void reflect(const ParamsDev &P, float u[3]) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (x[a] > P.box_hi[a]) {
+                x[a] = 2.0 * P.box_hi[a] - x[a];
+                u[a] = -u[a];
+            } else if (x[a] < P.box_lo[a]) {
+                x[a] = 2.0 * P.box_lo[a] - x[a];
+                u[a] = -u[a];
+            }
+        }
+    }
     // |x + d - c|^2 - R^2
     __device__ __forceinline__ double sphere(const ParamsDev &P, const float d[3]) const {
         double q0 = (x[0] + (double)d[0]) - P.center[0];
@@ -139,6 +153,23 @@ template <> struct Acc<ACC_DF> {
         }
         t = fr;
         i = wrap((int)fl, F.n[a], F.pow2);
+    }
+    // reflective box: the mirrored position in FP64, split again into hi + lo
+    __device__ __forceinline__ void reflect(const ParamsDev &P, float u[3]) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double v = df_val(x[a]);
+            double m = v;
+            if (v > P.box_hi[a])
+                m = 2.0 * P.box_hi[a] - v;
+            else if (v < P.box_lo[a])
+                m = 2.0 * P.box_lo[a] - v;
+            if (m != v) {
+                x[a].hi = (float)m;
+                x[a].lo = (float)(m - (double)x[a].hi);
+                u[a] = -u[a];
+            }
+        }
     }
     __device__ __forceinline__ double sphere(const ParamsDev &P, const float d[3]) const {
         float q0 = ((x[0].hi - (float)P.center[0]) + x[0].lo) + d[0];
@@ -275,7 +306,7 @@ struct EventLDS {
     int32_t side[MAX_BLOCK], eit[MAX_BLOCK];
 };
 
-template <int ACC>
+template <int ACC, bool RFL>
 __device__ __forceinline__ void bid(const ParamsDev &P, Lane<ACC> &s) {
     float h = s.hctrl;
     const float hmax = (float)P.h_max, hmin = (float)P.h_min;
@@ -286,6 +317,16 @@ __device__ __forceinline__ void bid(const ParamsDev &P, Lane<ACC> &s) {
         double r = sqrt(g + P.r2);
         float dist = (float)(P.radius - r);
         if (dist < h) h = dist;
+    }
+    if (RFL && P.reflect_on) {
+        // the distance to the nearest face of the reflective box bids too
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double xa = s.acc.X(a);
+            const float dlo = (float)(xa - P.box_lo[a]), dhi = (float)(P.box_hi[a] - xa);
+            if (dlo < h) h = dlo;
+            if (dhi < h) h = dhi;
+        }
     }
     if (h < hmin) h = hmin;
     s.binding = 0;
@@ -310,7 +351,9 @@ __device__ __forceinline__ void store(const PropArgs &a, const ParamsDev &P, int
     a.ux[p] = sg * (double)s.u[0];
     a.uy[p] = sg * (double)s.u[1];
     a.uz[p] = sg * (double)s.u[2];
-    double L = s.acc.len();
+    // a length stop lands on l_max exactly, as in the FP64 path (a double-float
+    // length cannot hold every FP64 l_max)
+    double L = st == CRP_ST_MAX_LENGTH && P.lmax_on ? P.l_max : s.acc.len();
     a.length[p] = L;
     a.h_next[p] = hnext;
     if (s.dacc) a.n_acc[p] += s.dacc;
@@ -332,7 +375,7 @@ __device__ __forceinline__ void event_next(const ParamsDev &P, Lane<ACC> &s, Eve
     }
 }
 
-template <bool MULTI, int ACC>
+template <bool MULTI, int ACC, bool RFL>
 __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane<ACC> &s) {
     if (a.status[p] != CRP_ST_ACTIVE) return false;
     s.pidx = MULTI && a.param_index ? a.param_index[p] : 0;
@@ -388,11 +431,11 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane<ACC> &s
     s.hctrl = hn == 0.0 ? (float)P.h_max : (float)hn;
     s.kap = (float)(((double)(P.backtrack_on ? -Z : Z) * K_LORENTZ) / E);
     s.mode = MODE_NORMAL;
-    bid(P, s);
+    bid<ACC, RFL>(P, s);
     return true;
 }
 
-template <class T, int LAYOUT, bool MULTI, int ACC, bool CACHE>
+template <class T, int LAYOUT, bool MULTI, int ACC, bool CACHE, bool RFL>
 __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &s, CellCache<T> &cache, EventLDS &e,
                                        int &flags) {
     const int t = threadIdx.x;
@@ -475,7 +518,10 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &
         s.u[0] = u5[0] / un;
         s.u[1] = u5[1] / un;
         s.u[2] = u5[2] / un;
-        if (P.lmax_on && s.acc.len() >= P.l_max) {
+        if (RFL && P.reflect_on) s.acc.reflect(P, s.u);
+        // the step that took the remaining length ends the particle: a double-float
+        // length may stay a rounding below an l_max it cannot represent
+        if (P.lmax_on && (s.binding || s.acc.len() >= P.l_max)) {
             store(a, P, p, s, (double)s.hctrl, CRP_ST_MAX_LENGTH);
             return CRP_ST_MAX_LENGTH;
         }
@@ -483,7 +529,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &
             store(a, P, p, s, (double)s.hctrl, CRP_ST_MAX_STEPS);
             return CRP_ST_MAX_STEPS;
         }
-        bid(P, s);
+        bid<ACC, RFL>(P, s);
         return CRP_ST_ACTIVE;
     }
 
@@ -522,7 +568,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &
     return CRP_ST_ARRIVED;
 }
 
-template <class T, int LAYOUT, bool MULTI, int ACC, bool CACHE>
+template <class T, int LAYOUT, bool MULTI, int ACC, bool CACHE, bool RFL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_propagate_mixed(PropArgs a) {
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
@@ -551,7 +597,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                 if (q < (unsigned long long)a.n) {
                     int64_t p = a.order ? (int64_t)a.order[q] : (int64_t)q;
                     got = 1;
-                    pid = start<MULTI, ACC>(a, p, s) ? p : -1;
+                    pid = start<MULTI, ACC, RFL>(a, p, s) ? p : -1;
                 } else {
                     pid = -2;
                 }
@@ -565,7 +611,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
         n_iter++;
         int flags = 0;
         if (pid >= 0) {
-            int st = advance<T, LAYOUT, MULTI, ACC, CACHE>(a, pid, s, cache, ev, flags);
+            int st = advance<T, LAYOUT, MULTI, ACC, CACHE, RFL>(a, pid, s, cache, ev, flags);
             if (st != CRP_ST_ACTIVE) pid = -1;
         }
         n_eval += __popcll(__ballot(flags & F_EVAL));
@@ -589,17 +635,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
 
 template <class T, int LAYOUT, bool MULTI>
 hipError_t launch_acc(const PropArgs &a, int acc, bool cache, int blocks, int bs, hipStream_t s) {
-    if (acc == ACC_DF) {
-        if (cache)
-            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_DF, true>), dim3(blocks), dim3(bs), 0, s, a);
+    const dim3 g(blocks), b(bs);
+    if (a.reflective) {
+        // a reflective box (the cell cache, a tuning option only, is not instantiated for it)
+        if (acc == ACC_DF)
+            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_DF, false, true>), g, b, 0, s, a);
         else
-            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_DF, false>), dim3(blocks), dim3(bs), 0, s, a);
+            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_F64, false, true>), g, b, 0, s, a);
+    } else if (acc == ACC_DF) {
+        if (cache)
+            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_DF, true, false>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_DF, false, false>), g, b, 0, s, a);
     } else {
         if (cache)
-            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_F64, true>), dim3(blocks), dim3(bs), 0, s, a);
+            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_F64, true, false>), g, b, 0, s, a);
         else
-            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_F64, false>), dim3(blocks), dim3(bs), 0, s,
-                               a);
+            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_F64, false, false>), g, b, 0, s, a);
     }
     return hipGetLastError();
 }

@@ -126,3 +126,22 @@ def test_mixed_resume_and_statuses(dev, setup):
     g = crp.particles_to_host(st)
     assert set(np.unique(g["status"])) <= {1, 2}
     assert np.all(np.abs(np.linalg.norm(g["dir"], axis=1) - 1) < 1e-6)
+
+
+@pytest.mark.parametrize("acc", ["f64acc", "dfacc"])
+def test_length_stop_lands_on_l_max(dev, acc):
+    """A length limit that a double-float length cannot hold (7.3 Mpc): every
+    particle stops at it, with the length written as l_max exactly."""
+    torch, crp = dev
+    w = ci.get_config(0)
+    fs, ps, _ = ci.config_seeds(0)
+    B = ci.kolmogorov_field(w.grid_n, w.spacing, w.l_min, w.l_max, w.b_rms, fs, dtype=np.float32)
+    P = ci.isotropic_particles(512, 1e18, 1e20, (1, 26), ps)
+    pv = crp.CRP_PREC_MIXED_F64ACC if acc == "f64acc" else crp.CRP_PREC_MIXED_DFACC
+    _say(f"case: mixed precision ({acc}), l_max = 7.3 Mpc")
+    f = crp.make_field(B, w.spacing, dtype="f16")
+    st = crp.particles_to_device(P["pos"], P["dir"], P["energy"], P["charge"])
+    crp.crp_propagate([f], [crp.make_params(1e-4, 1e-4, 0.5, l_max=7.3)], st, precision=pv)
+    torch.cuda.synchronize()
+    g = crp.particles_to_host(st)
+    assert np.all(g["status"] == 2) and np.all(g["length"] == 7.3)

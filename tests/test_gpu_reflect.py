@@ -217,3 +217,45 @@ def test_reflective_workload_sample(dev, oracle_mod):
                 sel=sel)
     r = compare({k: v[sel] for k, v in g.items()}, o, "reflective workload sample")
     _say(f"  bitwise fraction {r['bitwise_fraction']}")
+
+
+@pytest.mark.parametrize("prec", ["mixed_f64acc", "mixed_dfacc"])
+def test_mixed_kernel_reflects(dev, small, prec):
+    """The mixed-precision kernel (FP16 grid, FP32 stages) in a reflective box:
+    the zero-field billiard against its closed form within the FP32 stage
+    rounding, and in a field every particle stays in the box with unit
+    direction and the exact length stop."""
+    torch, crp = dev
+    w, B, P = small
+    pv = {"mixed_f64acc": crp.CRP_PREC_MIXED_F64ACC, "mixed_dfacc": crp.CRP_PREC_MIXED_DFACC}[prec]
+    _say(f"case: mixed kernel ({prec}) in a reflective box")
+    rng = np.random.default_rng(15)
+    n = 2000
+    u0 = rng.standard_normal((n, 3))
+    u0 /= np.linalg.norm(u0, axis=1, keepdims=True)
+    x0 = rng.uniform(-0.5, 0.5, size=(n, 3))
+    lo, hi, L = np.array([-1.0, -0.75, -1.25]), np.array([1.0, 1.25, 0.5]), 7.3
+    f0 = crp.make_field(np.zeros((4, 4, 4, 3), np.float32), 1.0, dtype="f16")
+    st = crp.particles_to_device(x0, u0, np.full(n, 1e18), np.ones(n, np.int32))
+    crp.crp_propagate([f0], [crp.make_params(1e-6, 1e-9, 0.2, l_max=L, box=(lo, hi))], st, precision=pv)
+    torch.cuda.synchronize()
+    g = crp.particles_to_host(st)
+    assert np.all(g["status"] == 2) and np.all(g["length"] == L)
+    wdt = hi - lo
+    r = np.mod(x0 + L * u0 - lo, 2 * wdt)
+    fold = np.where(r <= wdt, lo + r, lo + 2 * wdt - r)
+    sign = np.where(np.mod(np.floor((x0 + L * u0 - lo) / wdt), 2) == 0, 1.0, -1.0)
+    near_face = np.min(np.minimum(np.abs(fold - lo), np.abs(hi - fold)), axis=1) < 1e-4
+    ok = ~near_face  # a fold within 1e-4 of a face may be taken on the other side of it
+    assert np.mean(ok) > 0.99
+    assert np.max(np.abs(g["pos"][ok] - fold[ok])) < 1e-5
+    assert np.max(np.abs(g["dir"][ok] - sign[ok] * u0[ok])) < 1e-5
+    Q = _in_box(P, BOX)
+    fm = crp.make_field(B.astype(np.float32), w.spacing, dtype="f16")
+    st = crp.particles_to_device(Q["pos"], Q["dir"], Q["energy"], Q["charge"])
+    crp.crp_propagate([fm], [crp.make_params(**PRM, box=BOX)], st, precision=pv)
+    torch.cuda.synchronize()
+    h = crp.particles_to_host(st)
+    assert np.all(h["status"] == 2) and np.all(h["length"] == PRM["l_max"])
+    assert _inside(h["pos"], BOX)
+    assert np.max(np.abs(np.linalg.norm(h["dir"], axis=1) - 1.0)) < 1e-6
