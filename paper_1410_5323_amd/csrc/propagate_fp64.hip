@@ -126,8 +126,8 @@ __device__ __forceinline__ void reflect(const ParamsDev &P, double y[6]) {
 }
 
 // Write the particle's state back (its own slots only).
-__device__ __forceinline__ void store(const PropArgs &a, const ParamsDev &P, int64_t p, const Lane &s, double hnext,
-                                     int st) {
+__device__ __forceinline__ void store(const ParamsDev &P, int64_t p, const Lane &s, double hnext, int st) {
+    KernArgs &a = kernel_args();
     a.x[p] = s.y[0];
     a.y[p] = s.y[1];
     a.z[p] = s.y[2];
@@ -164,7 +164,8 @@ enum { F_EVAL = 1, F_ACC = 2, F_REJ = 4, F_EVENT = 8, F_FLOOR = 16 };
 // Start particle p in lane state s.  Returns true if it needs steps; false if
 // it was skipped (not ACTIVE) or finished at once (its result is stored).
 template <bool MULTI, bool TAPE, bool RFL>
-__device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
+__device__ __forceinline__ bool start(const PropArgs &args, int64_t p, Lane &s) {
+    KernArgs &a = kernel_args();  // the particle arrays
     int st = a.status[p];
     if (TAPE) {
         double *f = a.tape_fin + 4 * p;  // overwritten when the particle completes
@@ -178,7 +179,7 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
         a.status[p] = CRP_ST_BAD_INPUT;
         return false;
     }
-    const ParamsDev &P = MULTI ? a.params[s.pidx] : a.P0;
+    const ParamsDev &P = MULTI ? args.params[s.pidx] : args.P0;
     double E = a.energy[p];
     int Z = a.charge[p];
     s.y[0] = a.x[p];
@@ -216,19 +217,19 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane &s) {
     }
     s.tflags = hn == 0.0 ? CRP_TAPE_FRESH : 0;
     if (P.sphere_on && sphere_g(P, s.y) >= 0.0) {
-        store(a, P, p, s, hn, CRP_ST_ARRIVED);
-        if (TAPE) tape_final(a, p, s, 0.0, CRP_TAPE_COMPLETE);
+        store(P, p, s, hn, CRP_ST_ARRIVED);
+        if (TAPE) tape_final(args, p, s, 0.0, CRP_TAPE_COMPLETE);
         return false;
     }
     if (P.lmax_on && s.L >= P.l_max) {
-        store(a, P, p, s, hn, CRP_ST_MAX_LENGTH);
-        if (TAPE) tape_final(a, p, s, 0.0, CRP_TAPE_COMPLETE);
+        store(P, p, s, hn, CRP_ST_MAX_LENGTH);
+        if (TAPE) tape_final(args, p, s, 0.0, CRP_TAPE_COMPLETE);
         return false;
     }
     s.hctrl = hn == 0.0 ? P.h_max : hn;
     s.kap = ((double)(P.backtrack_on ? -Z : Z) * K_LORENTZ) / E;
     s.mode = MODE_NORMAL;
-    if (TAPE) tape_checkpoint(a, s);
+    if (TAPE) tape_checkpoint(args, s);
     bid<RFL>(P, s);
     return true;
 }
@@ -257,7 +258,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
     if (s.mode == MODE_NORMAL) {
         double exh = ex / s.h;
         if (!isfinite(eu) || !isfinite(exh)) {
-            store(a, P, p, s, s.hctrl, CRP_ST_NONFINITE);
+            store(P, p, s, s.hctrl, CRP_ST_NONFINITE);
             if (TAPE) tape_final(a, p, s, 0.0, 0);
             return CRP_ST_NONFINITE;
         }
@@ -315,12 +316,12 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
         if (RFL && P.reflect_on) reflect(P, s.y);
         s.L = Lnew;
         if (P.lmax_on && s.L >= P.l_max) {
-            store(a, P, p, s, s.hctrl, CRP_ST_MAX_LENGTH);
+            store(P, p, s, s.hctrl, CRP_ST_MAX_LENGTH);
             if (TAPE) tape_final(a, p, s, 0.0, CRP_TAPE_COMPLETE);
             return CRP_ST_MAX_LENGTH;
         }
         if (P.max_steps > 0 && s.dacc >= P.max_steps) {
-            store(a, P, p, s, s.hctrl, CRP_ST_MAX_STEPS);
+            store(P, p, s, s.hctrl, CRP_ST_MAX_STEPS);
             if (TAPE) tape_final(a, p, s, 0.0, 0);
             return CRP_ST_MAX_STEPS;
         }
@@ -333,7 +334,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
     if (s.mode == MODE_EVENT) {
         double gs = sphere_g(P, y5);
         if (!isfinite(gs)) {
-            store(a, P, p, s, s.hctrl, CRP_ST_NONFINITE);
+            store(P, p, s, s.hctrl, CRP_ST_NONFINITE);
             if (TAPE) tape_final(a, p, s, 0.0, 0);
             return CRP_ST_NONFINITE;
         }
@@ -362,7 +363,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
     s.y[4] = y5[4] / sn;
     s.y[5] = y5[5] / sn;
     s.L = e.hi[t] == e.hacc[t] ? e.lacc[t] : s.L + e.hi[t];
-    store(a, P, p, s, s.hctrl, CRP_ST_ARRIVED);
+    store(P, p, s, s.hctrl, CRP_ST_ARRIVED);
     if (TAPE) tape_final(a, p, s, e.hi[t], CRP_TAPE_COMPLETE | CRP_TAPE_EVENT);
     return CRP_ST_ARRIVED;
 }

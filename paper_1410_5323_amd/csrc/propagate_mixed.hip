@@ -341,8 +341,8 @@ __device__ __forceinline__ void bid(const ParamsDev &P, Lane<ACC> &s) {
 }
 
 template <int ACC>
-__device__ __forceinline__ void store(const PropArgs &a, const ParamsDev &P, int64_t p, const Lane<ACC> &s,
-                                     double hnext, int st) {
+__device__ __forceinline__ void store(const ParamsDev &P, int64_t p, const Lane<ACC> &s, double hnext, int st) {
+    KernArgs &a = kernel_args();
     a.x[p] = s.acc.X(0);
     a.y[p] = s.acc.X(1);
     a.z[p] = s.acc.X(2);
@@ -376,14 +376,15 @@ __device__ __forceinline__ void event_next(const ParamsDev &P, Lane<ACC> &s, Eve
 }
 
 template <bool MULTI, int ACC, bool RFL>
-__device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane<ACC> &s) {
+__device__ __forceinline__ bool start(const PropArgs &args, int64_t p, Lane<ACC> &s) {
+    KernArgs &a = kernel_args();  // the particle arrays
     if (a.status[p] != CRP_ST_ACTIVE) return false;
     s.pidx = MULTI && a.param_index ? a.param_index[p] : 0;
     if (MULTI && (s.pidx < 0 || s.pidx >= a.n_params)) {
         a.status[p] = CRP_ST_BAD_INPUT;
         return false;
     }
-    const ParamsDev &P = MULTI ? a.params[s.pidx] : a.P0;
+    const ParamsDev &P = MULTI ? args.params[s.pidx] : args.P0;
     double E = a.energy[p];
     int Z = a.charge[p];
     double x[3] = {a.x[p], a.y[p], a.z[p]};
@@ -421,11 +422,11 @@ __device__ __forceinline__ bool start(const PropArgs &a, int64_t p, Lane<ACC> &s
     s.u[2] = (float)u[2];
     const float z[3] = {0.f, 0.f, 0.f};
     if (P.sphere_on && s.acc.sphere(P, z) >= 0.0) {
-        store(a, P, p, s, hn, CRP_ST_ARRIVED);
+        store(P, p, s, hn, CRP_ST_ARRIVED);
         return false;
     }
     if (P.lmax_on && L >= P.l_max) {
-        store(a, P, p, s, hn, CRP_ST_MAX_LENGTH);
+        store(P, p, s, hn, CRP_ST_MAX_LENGTH);
         return false;
     }
     s.hctrl = hn == 0.0 ? (float)P.h_max : (float)hn;
@@ -462,7 +463,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &
     if (s.mode == MODE_NORMAL) {
         float exh = ex / s.h;
         if (!isfinite(eu) || !isfinite(exh)) {
-            store(a, P, p, s, (double)s.hctrl, CRP_ST_NONFINITE);
+            store(P, p, s, (double)s.hctrl, CRP_ST_NONFINITE);
             return CRP_ST_NONFINITE;
         }
         float err = (eu > exh ? eu : exh) / (float)P.tol;
@@ -522,11 +523,11 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &
         // the step that took the remaining length ends the particle: a double-float
         // length may stay a rounding below an l_max it cannot represent
         if (P.lmax_on && (s.binding || s.acc.len() >= P.l_max)) {
-            store(a, P, p, s, (double)s.hctrl, CRP_ST_MAX_LENGTH);
+            store(P, p, s, (double)s.hctrl, CRP_ST_MAX_LENGTH);
             return CRP_ST_MAX_LENGTH;
         }
         if (P.max_steps > 0 && s.dacc >= P.max_steps) {
-            store(a, P, p, s, (double)s.hctrl, CRP_ST_MAX_STEPS);
+            store(P, p, s, (double)s.hctrl, CRP_ST_MAX_STEPS);
             return CRP_ST_MAX_STEPS;
         }
         bid<ACC, RFL>(P, s);
@@ -537,7 +538,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &
     if (s.mode == MODE_EVENT) {
         double gs = s.acc.sphere(P, dx5);
         if (!isfinite(gs)) {
-            store(a, P, p, s, (double)s.hctrl, CRP_ST_NONFINITE);
+            store(P, p, s, (double)s.hctrl, CRP_ST_NONFINITE);
             return CRP_ST_NONFINITE;
         }
         if (gs >= 0.0) {
@@ -564,7 +565,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &
     s.u[0] = u5[0] / sn;
     s.u[1] = u5[1] / sn;
     s.u[2] = u5[2] / sn;
-    store(a, P, p, s, (double)s.hctrl, CRP_ST_ARRIVED);
+    store(P, p, s, (double)s.hctrl, CRP_ST_ARRIVED);
     return CRP_ST_ARRIVED;
 }
 
