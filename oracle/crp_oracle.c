@@ -1086,13 +1086,16 @@ static void step_vjp(const grid_t *g, double kappa, const double y[6], double s,
         Ybar[i][0] = Ybar[i][1] = Ybar[i][2] = 0.0;
         if (cell_stencil(g, Y[i], w, idx, dw) == 0) {
             for (int kk = 0; kk < 8; ++kk) {
-                for (int c = 0; c < 3; ++c) {
-                    double val = g->v64 ? g->v64[3 * idx[kk] + c] : (double)g->v32[3 * idx[kk] + c];
-                    for (int a = 0; a < 3; ++a)
-                        Ybar[i][a] += dw[a][kk] * val * Bb[c];
-                    if (gbar)
+                double val[3];
+                for (int c = 0; c < 3; ++c)
+                    val[c] = g->v64 ? g->v64[3 * idx[kk] + c] : (double)g->v32[3 * idx[kk] + c];
+                /* X-bar += (dB/dX)^T B-bar: this corner's value dotted with B-bar, times dw */
+                double vb = val[0] * Bb[0] + val[1] * Bb[1] + val[2] * Bb[2];
+                for (int a = 0; a < 3; ++a)
+                    Ybar[i][a] += dw[a][kk] * vb;
+                if (gbar)
+                    for (int c = 0; c < 3; ++c)
                         gbar[3 * idx[kk] + c] += w[kk] * Bb[c];
-                }
             }
         }
         for (int c = 0; c < 6; ++c)

@@ -388,16 +388,18 @@ __device__ __forceinline__ void ck_eval(const FieldDev &F, int fid, CellCache<T>
     eu = norm3(d[3], d[4], d[5]);
 }
 
-// The propagation kernels' arguments (a PropArgs by value, their only
-// argument, so at the start of the kernel-argument segment) read again where
-// this is called, with scalar loads from that segment, instead of held in
-// scalar registers across the main loop: for values used only on rare paths
-// (a particle starting or ending), which would otherwise be spilled to
-// vector-register lanes.  The empty asm hides the pointer's origin, so the
-// compiler cannot hoist those loads out of the loop.
-using KernArgs = const __attribute__((address_space(4))) PropArgs;
-__device__ __forceinline__ KernArgs &kernel_args() {
-    KernArgs *q = (KernArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+// A kernel's arguments (one struct A by value, its only argument, so at the
+// start of the kernel-argument segment) read again where this is called,
+// with scalar loads from that segment, instead of held in scalar registers
+// across the main loop: for values used only on rare paths (a particle
+// starting or ending), which would otherwise be spilled to vector-register
+// lanes.  The empty asm hides the pointer's origin, so the compiler cannot
+// hoist those loads out of the loop.
+template <class A>
+using KernArg = const __attribute__((address_space(4))) A;
+template <class A>
+__device__ __forceinline__ KernArg<A> &kernel_args() {
+    KernArg<A> *q = (KernArg<A> *)__builtin_amdgcn_kernarg_segment_ptr();
     asm volatile("" : "+s"(q));
     return *q;
 }

@@ -127,7 +127,7 @@ __device__ __forceinline__ void reflect(const ParamsDev &P, double y[6]) {
 
 // Write the particle's state back (its own slots only).
 __device__ __forceinline__ void store(const ParamsDev &P, int64_t p, const Lane &s, double hnext, int st) {
-    KernArgs &a = kernel_args();
+    KernArg<PropArgs> &a = kernel_args<PropArgs>();
     a.x[p] = s.y[0];
     a.y[p] = s.y[1];
     a.z[p] = s.y[2];
@@ -165,7 +165,7 @@ enum { F_EVAL = 1, F_ACC = 2, F_REJ = 4, F_EVENT = 8, F_FLOOR = 16 };
 // it was skipped (not ACTIVE) or finished at once (its result is stored).
 template <bool MULTI, bool TAPE, bool RFL>
 __device__ __forceinline__ bool start(const PropArgs &args, int64_t p, Lane &s) {
-    KernArgs &a = kernel_args();  // the particle arrays
+    KernArg<PropArgs> &a = kernel_args<PropArgs>();  // the particle arrays
     int st = a.status[p];
     if (TAPE) {
         double *f = a.tape_fin + 4 * p;  // overwritten when the particle completes
@@ -806,15 +806,17 @@ __device__ void reverse_step(const FieldDev &F, double kap, const double *r, int
             double dw[3];
             int64_t node;
             const double w = corner_weight(F, ci, t, q, dw, node);
+            // X-bar += (dB/dX)^T B-bar: this corner's value dotted with B-bar, times dw
+            const double vb = (to_f64<T>(raw[q * 3 + 0]) * F.value_scale) * Bb[0] +
+                              (to_f64<T>(raw[q * 3 + 1]) * F.value_scale) * Bb[1] +
+                              (to_f64<T>(raw[q * 3 + 2]) * F.value_scale) * Bb[2];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double v = to_f64<T>(raw[q * 3 + c]) * F.value_scale;
+            for (int a = 0; a < 3; ++a) Yb[i][a] += dw[a] * vb;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) Yb[i][a] += dw[a] * v * Bb[c];
+            for (int c = 0; c < 3; ++c)
                 // the lane owns its slot: an LDS add without return, no wait on a read
                 __hip_atomic_fetch_add(&acc.v[3 * q + c][acc.t], w * Bb[c], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
         }
 #pragma unroll
         for (int c = 0; c < 6; ++c) yb[c] += Yb[i][c];
@@ -847,7 +849,8 @@ struct AdjLane {
 
 // Gradients of the lane's finished particle: the direction entering the map
 // is normalised on a fresh start.
-__device__ __forceinline__ void adj_finish(const AdjArgs &a, const AdjLane &L) {
+__device__ __forceinline__ void adj_finish(const AdjLane &L) {
+    KernArg<AdjArgs> &a = kernel_args<AdjArgs>();  // read here: once per particle
     const int64_t p = L.p;
     // a backtracked run is the forward run of the antiparticle with the
     // direction reversed: its direction gradient is reversed back
@@ -871,7 +874,8 @@ __device__ __forceinline__ void adj_finish(const AdjArgs &a, const AdjLane &L) {
 }
 
 // A particle with no adjoint (incomplete tape or broken record chain): zero gradients.
-__device__ __forceinline__ void adj_zero(const AdjArgs &a, int64_t p) {
+__device__ __forceinline__ void adj_zero(int64_t p) {
+    KernArg<AdjArgs> &a = kernel_args<AdjArgs>();
     for (int c = 0; c < 3; ++c) {
         a.grad_u0[3 * p + c] = 0.0;
         if (a.grad_x0) a.grad_x0[3 * p + c] = 0.0;
@@ -899,39 +903,41 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
     for (;;) {
         // take particles until one needs a sweep (or the queue is empty)
         while (L.p < 0 && !exhausted) {
-            unsigned long long q = atomicAdd(a.queue, 1ull);
-            if (q >= (unsigned long long)a.n) {
+            // the particle's inputs: kernel arguments read here, not held across the loop
+            KernArg<AdjArgs> &k = kernel_args<AdjArgs>();
+            unsigned long long q = atomicAdd(k.queue, 1ull);
+            if (q >= (unsigned long long)k.n) {
                 exhausted = true;
                 break;
             }
-            const int64_t p = a.order ? (int64_t)a.order[q] : (int64_t)q;
-            const double *fin = a.fin + 4 * p;
+            const int64_t p = k.order ? (int64_t)k.order[q] : (int64_t)q;
+            const double *fin = k.fin + 4 * p;
             L.p = p;
             L.flags = (int)fin[3];
             L.N = (int64_t)fin[0];
             for (int c = 0; c < 3; ++c) L.lam[c] = 0.0;
             // backtracking: the cotangent of the antiparticle's (reversed) direction
-            for (int c = 0; c < 3; ++c) L.lam[3 + c] = a.P.backtrack_on ? -a.gbar_dir[3 * p + c] : a.gbar_dir[3 * p + c];
+            for (int c = 0; c < 3; ++c) L.lam[3 + c] = k.P.backtrack_on ? -k.gbar_dir[3 * p + c] : k.gbar_dir[3 * p + c];
             if (!(L.flags & CRP_TAPE_COMPLETE) || (L.flags & CRP_TAPE_OVERFLOW)) {
-                adj_zero(a, p);
+                adj_zero(p);
                 L.p = -1;
                 continue;
             }
-            L.kap = ((double)(a.P.backtrack_on ? -a.charge[p] : a.charge[p]) * K_LORENTZ) / a.energy[p];
+            L.kap = ((double)(k.P.backtrack_on ? -k.charge[p] : k.charge[p]) * K_LORENTZ) / k.energy[p];
             L.kbar = 0.0;
             if (L.N == 0) {
-                adj_finish(a, L);
+                adj_finish(L);
                 L.p = -1;
                 continue;
             }
             L.slot = (int64_t)fin[2];
-            if (L.slot < 0 || L.slot >= a.cap) {  // no record although steps were taken: no adjoint
-                adj_zero(a, p);
+            if (L.slot < 0 || L.slot >= k.cap) {  // no record although steps were taken: no adjoint
+                adj_zero(p);
                 L.p = -1;
                 continue;
             }
-            L.Lbar = a.gbar_time ? a.gbar_time[p] * SEC_PER_MPC : 0.0;
-            L.seg = (L.N + a.K - 1) / a.K - 1;
+            L.Lbar = k.gbar_time ? k.gbar_time[p] * SEC_PER_MPC : 0.0;
+            L.seg = (L.N + k.K - 1) / k.K - 1;
         }
         const bool busy = L.p >= 0;
         if (__ballot(busy) == 0ull) break;
@@ -995,13 +1001,13 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
         if (busy) {
             if (--L.seg < 0) {
                 grad_flush(a.F, acc, a.grad_field);
-                adj_finish(a, L);
+                adj_finish(L);
                 L.p = -1;
             } else {
                 L.slot = a.link[L.slot];
                 if (L.slot < 0 || L.slot >= a.cap) {  // a broken chain: no adjoint for this particle
                     grad_flush(a.F, acc, a.grad_field);
-                    adj_zero(a, L.p);
+                    adj_zero(L.p);
                     L.p = -1;
                 }
             }

@@ -342,7 +342,7 @@ __device__ __forceinline__ void bid(const ParamsDev &P, Lane<ACC> &s) {
 
 template <int ACC>
 __device__ __forceinline__ void store(const ParamsDev &P, int64_t p, const Lane<ACC> &s, double hnext, int st) {
-    KernArgs &a = kernel_args();
+    KernArg<PropArgs> &a = kernel_args<PropArgs>();
     a.x[p] = s.acc.X(0);
     a.y[p] = s.acc.X(1);
     a.z[p] = s.acc.X(2);
@@ -377,7 +377,7 @@ __device__ __forceinline__ void event_next(const ParamsDev &P, Lane<ACC> &s, Eve
 
 template <bool MULTI, int ACC, bool RFL>
 __device__ __forceinline__ bool start(const PropArgs &args, int64_t p, Lane<ACC> &s) {
-    KernArgs &a = kernel_args();  // the particle arrays
+    KernArg<PropArgs> &a = kernel_args<PropArgs>();  // the particle arrays
     if (a.status[p] != CRP_ST_ACTIVE) return false;
     s.pidx = MULTI && a.param_index ? a.param_index[p] : 0;
     if (MULTI && (s.pidx < 0 || s.pidx >= a.n_params)) {
