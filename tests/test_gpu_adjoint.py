@@ -5,10 +5,10 @@ rotation in a uniform field and the tape's edge cases.
 The derivative is that of the replayed map (accepted step sizes frozen, the
 sphere crossing differentiated through its defining equation).  The GPU
 replays from checkpoints with the forward kernel's step logic, so its states
-are those of the forward run bit for bit; its reverse sweep sums in another
-order than the oracle's, so gradients agree to a relative tolerance:
-1e-8 of the gradient's norm per particle (direction and position), 1e-8 of
-the norm for the grid gradient (which the GPU accumulates with atomics).
+are those of the forward run bit for bit, and its reverse sweep takes the
+oracle's operations in the oracle's order: the direction, position and
+energy gradients are bitwise the oracle's.  The grid gradient is accumulated
+with atomics in another order; it agrees to 1e-8 of its norm.
 """
 import math
 import sys
@@ -108,7 +108,7 @@ def _check_against_oracle(O, r, B, spacing, prm_arr, P, sel, gdir, gtime, center
     ee = _rel_scalar(r["ge"], _oracle_adjoint.last_ge)
     _say(f"{label}: steps {steps.min()}..{steps.max()}, max rel err grad_u0 {eu.max():.2e}, "
          f"grad_x0 {ex.max():.2e}, grad_energy {ee.max():.2e}, grid {eg:.2e}")
-    assert eu.max() <= GRAD_TOL and ex.max() <= GRAD_TOL and eg <= GRAD_TOL and ee.max() <= GRAD_TOL
+    assert eu.max() == 0.0 and ex.max() == 0.0 and ee.max() == 0.0 and eg <= GRAD_TOL
 
 
 def test_adjoint_matches_oracle_small_grid(dev, oracle_mod):
@@ -348,7 +348,7 @@ def test_full_adjoint_workload_sampled(dev, oracle_mod):
     eu = _rel(r["gu"][sel], gu)
     ee = _rel_scalar(r["ge"][sel], _oracle_adjoint.last_ge)
     _say(f"sampled steps {ost.min()}..{ost.max()}, max rel err grad_u0 {eu.max():.2e}, grad_energy {ee.max():.2e}")
-    assert eu.max() <= GRAD_TOL and ee.max() <= GRAD_TOL
+    assert eu.max() == 0.0 and ee.max() == 0.0
     # the gradients that overflow on the GPU overflow in the oracle's adjoint too
     bad = np.nonzero(~fin)[0]
     if len(bad):
@@ -398,7 +398,7 @@ def test_backtracked_adjoint(dev, oracle_mod):
     eg = _rel_all(r["gg"], gbar)
     _say(f"backtracked: max rel err grad_u0 {eu.max():.2e}, grad_x0 {ex.max():.2e}, grad_energy {ee.max():.2e}, "
          f"grid {eg:.2e}")
-    assert eu.max() <= GRAD_TOL and ex.max() <= GRAD_TOL and ee.max() <= GRAD_TOL and eg <= GRAD_TOL
+    assert eu.max() == 0.0 and ex.max() == 0.0 and ee.max() == 0.0 and eg <= GRAD_TOL
 
 
 def test_autograd_backtracking_central_differences(dev):
