@@ -548,9 +548,9 @@ def main():
     }
 
     mixed_host = None
-    if prec == 0 and not args.no_mixed and not batched and mod is None and w.reflect_box is None and not w.lens_nside:
+    if prec == 0 and not args.no_mixed and not batched and not w.lens_nside:
         mdt = args.mixed_grid_dtype
-        mfields = [crp.make_field(g, w.spacing, dtype=mdt, layout=layout) for g in grids]
+        mfields = [crp.make_field(g, w.spacing, dtype=mdt, layout=layout, modulation=mod) for g in grids]
         mix = timed(mfields, PRECISIONS["mixed_f64acc"], mixed_tuning, args.steps, 1, f"mixed_f64acc/{mdt}/{layout}")
         del mfields
         torch.cuda.empty_cache()

@@ -97,7 +97,7 @@ typedef struct {
     double spacing;        /* Mpc, > 0 */
     double value_scale;    /* nG per stored unit (1 for F64/F32 grids) */
     void *data;            /* [dev] crp_field_bytes(this) bytes, written by crp_field_upload */
-    const crp_modulation *modulation;  /* host pointer, NULL for none; FP64 precision only, no tape */
+    const crp_modulation *modulation;  /* host pointer, NULL for none; no tape */
 } crp_field;
 
 /* Bidding and stopping parameters of one particle group (section 3.1).

@@ -278,10 +278,8 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
         return fail(CRP_ERR_INVALID, "%s: unknown precision %d", fn, precision);
     bool modulated = false;
     for (int i = 0; i < n_fields; ++i) modulated = modulated || fields[i].modulation != nullptr;
-    if (modulated && precision != CRP_PREC_FP64)
-        return fail(CRP_ERR_UNSUPPORTED, "%s: modulated fields need FP64 precision", fn);
-    if (modulated && fields[0].dtype != CRP_F64 && fields[0].dtype != CRP_F32)
-        return fail(CRP_ERR_UNSUPPORTED, "%s: modulated fields need F64 or F32 storage", fn);
+    if (modulated && precision == CRP_PREC_FP64 && fields[0].dtype != CRP_F64 && fields[0].dtype != CRP_F32)
+        return fail(CRP_ERR_UNSUPPORTED, "%s: modulated fields in FP64 precision need F64 or F32 storage", fn);
     bool reflective = false;
     for (int i = 0; i < n_params; ++i) reflective = reflective || params[i].reflect != 0;
     if (tape) {

@@ -51,6 +51,14 @@ __device__ __forceinline__ int wrap(int i, int n, int pow2) {
     return r < 0 ? r + n : r;
 }
 
+// Base cell of a step's start in the modulation grid (section 3.2, modulated
+// grids), with the FP32 fraction: the stages add their offsets to it in FP32
+// as they do for the vector grid.
+struct ModRel {
+    int ib[3];
+    float tb[3];
+};
+
 // Double-float helpers (Knuth two-sum; Dekker split replaced by fma).
 struct df {
     float hi, lo;
@@ -90,6 +98,13 @@ template <> struct Acc<ACC_F64> {
         double fl = floor(f);
         t = (float)(f - fl);
         i = wrap((int)fl, F.n[a], F.pow2);
+    }
+    // base cell and FP32 fraction in the modulation grid
+    __device__ __forceinline__ void mod_cell(const FieldDev &F, int a, int &i, float &t) const {
+        double f = (x[a] - F.mod_origin[a]) * F.mod_inv_spacing;
+        double fl = floor(f);
+        t = (float)(f - fl);
+        i = wrap((int)fl, F.mod_n[a], F.mod_pow2);
     }
     // reflective box: mirror the position on a face it crossed, negate that
     // direction component
@@ -154,6 +169,13 @@ template <> struct Acc<ACC_DF> {
         t = fr;
         i = wrap((int)fl, F.n[a], F.pow2);
     }
+    // base cell and FP32 fraction in the modulation grid (from the FP64 value)
+    __device__ __forceinline__ void mod_cell(const FieldDev &F, int a, int &i, float &t) const {
+        double f = (df_val(x[a]) - F.mod_origin[a]) * F.mod_inv_spacing;
+        double fl = floor(f);
+        t = (float)(f - fl);
+        i = wrap((int)fl, F.mod_n[a], F.mod_pow2);
+    }
     // reflective box: the mirrored position in FP64, split again into hi + lo
     __device__ __forceinline__ void reflect(const ParamsDev &P, float u[3]) {
 #pragma unroll
@@ -182,9 +204,35 @@ template <> struct Acc<ACC_DF> {
 // Cell-relative FP32 lookup: base cell ib, fraction tb, stage offset d (Mpc).
 // With CACHE, the last cell's corner values are kept in LDS (key in registers)
 // and a repeated lookup of that cell reads no global memory.
-template <class T, int LAYOUT, bool CACHE>
+template <class T, int LAYOUT, bool CACHE, bool MOD>
 __device__ __forceinline__ void lookup_rel(const FieldDev &F, int fid, const int ib[3], const float tb[3],
-                                           const float d[3], float B[3], CellCache<T> &cache) {
+                                           const ModRel &mr, const float d[3], float B[3], CellCache<T> &cache) {
+    // modulation corners first, so that their loads and the vector grid's are in flight together
+    float mv[8], mt[3];
+    const bool mod = MOD && F.mod_data != nullptr;
+    if (mod) {
+        int mc[3];
+        const float minv = (float)F.mod_inv_spacing;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float f = fmaf(d[a], minv, mr.tb[a]);
+            float fl = floorf(f);
+            mt[a] = f - fl;
+            mc[a] = wrap(mr.ib[a] + (int)fl, F.mod_n[a], F.mod_pow2);
+        }
+        const uint32_t o = (uint32_t)mc[0] * F.mod_sx + (uint32_t)mc[1] * F.mod_sy + (uint32_t)mc[2];
+        const uint32_t sx = F.mod_sx, sy = F.mod_sy;
+        const uint32_t off[8] = {0, 1, sx, sx + 1, sy, sy + 1, sx + sy, sx + sy + 1};
+        if (F.mod_dtype == CRP_F64) {
+            const global_ptr<double> q = as_global<double>(F.mod_data) + o;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) mv[k] = (float)q[off[k]];
+        } else {
+            const global_ptr<float> q = as_global<float>(F.mod_data) + o;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) mv[k] = q[off[k]];
+        }
+    }
     const float inv = (float)F.inv_spacing;
     int ci[3];
     float t[3];
@@ -225,6 +273,17 @@ __device__ __forceinline__ void lookup_rel(const FieldDev &F, int fid, const int
     B[0] *= sc;
     B[1] *= sc;
     B[2] *= sc;
+    if (mod) {
+        // trilinear as the FP64 path: along x, then y, then z
+        const float c00 = lerpf(mv[0], mv[2], mt[0]);  // (y, z) = (0, 0)
+        const float c10 = lerpf(mv[4], mv[6], mt[0]);  // (1, 0)
+        const float c01 = lerpf(mv[1], mv[3], mt[0]);  // (0, 1)
+        const float c11 = lerpf(mv[5], mv[7], mt[0]);  // (1, 1)
+        const float m = lerpf(lerpf(c00, c10, mt[1]), lerpf(c01, c11, mt[1]), mt[2]);
+        B[0] *= m;
+        B[1] *= m;
+        B[2] *= m;
+    }
 }
 
 __device__ __forceinline__ void lorentz(float kap, const float U[3], const float B[3], float F[3]) {
@@ -235,50 +294,50 @@ __device__ __forceinline__ void lorentz(float kap, const float U[3], const float
 
 // One FP32 Cash-Karp evaluation from (x, u) with step h: the position offset
 // dx5, the new direction u5 (unnormalised), and the error norms.
-template <class T, int LAYOUT, bool CACHE>
+template <class T, int LAYOUT, bool CACHE, bool MOD>
 __device__ __forceinline__ void ck_eval_f32(const FieldDev &F, int fid, CellCache<T> &cache, const int ib[3],
-                                            const float tb[3], float kap, const float u[3], float h, float dx5[3],
+                                            const float tb[3], const ModRel &mr, float kap, const float u[3], float h, float dx5[3],
                                             float u5[3], float &ex, float &eu) {
     float U2[3], U3[3], U4[3], U5[3], U6[3];
     float F1[3], F2[3], F3[3], F4[3], F5[3], F6[3];
     float d[3], B[3];
     const float z[3] = {0.f, 0.f, 0.f};
-    lookup_rel<T, LAYOUT, CACHE>(F, fid, ib, tb, z, B, cache);
+    lookup_rel<T, LAYOUT, CACHE, MOD>(F, fid, ib, tb, mr, z, B, cache);
     lorentz(kap, u, B, F1);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         d[c] = h * (a21 * u[c]);
         U2[c] = fmaf(h, a21 * F1[c], u[c]);
     }
-    lookup_rel<T, LAYOUT, CACHE>(F, fid, ib, tb, d, B, cache);
+    lookup_rel<T, LAYOUT, CACHE, MOD>(F, fid, ib, tb, mr, d, B, cache);
     lorentz(kap, U2, B, F2);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         d[c] = h * fmaf(a32, U2[c], a31 * u[c]);
         U3[c] = fmaf(h, fmaf(a32, F2[c], a31 * F1[c]), u[c]);
     }
-    lookup_rel<T, LAYOUT, CACHE>(F, fid, ib, tb, d, B, cache);
+    lookup_rel<T, LAYOUT, CACHE, MOD>(F, fid, ib, tb, mr, d, B, cache);
     lorentz(kap, U3, B, F3);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         d[c] = h * fmaf(a43, U3[c], fmaf(a42, U2[c], a41 * u[c]));
         U4[c] = fmaf(h, fmaf(a43, F3[c], fmaf(a42, F2[c], a41 * F1[c])), u[c]);
     }
-    lookup_rel<T, LAYOUT, CACHE>(F, fid, ib, tb, d, B, cache);
+    lookup_rel<T, LAYOUT, CACHE, MOD>(F, fid, ib, tb, mr, d, B, cache);
     lorentz(kap, U4, B, F4);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         d[c] = h * fmaf(a54, U4[c], fmaf(a53, U3[c], fmaf(a52, U2[c], a51 * u[c])));
         U5[c] = fmaf(h, fmaf(a54, F4[c], fmaf(a53, F3[c], fmaf(a52, F2[c], a51 * F1[c]))), u[c]);
     }
-    lookup_rel<T, LAYOUT, CACHE>(F, fid, ib, tb, d, B, cache);
+    lookup_rel<T, LAYOUT, CACHE, MOD>(F, fid, ib, tb, mr, d, B, cache);
     lorentz(kap, U5, B, F5);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         d[c] = h * fmaf(a65, U5[c], fmaf(a64, U4[c], fmaf(a63, U3[c], fmaf(a62, U2[c], a61 * u[c]))));
         U6[c] = fmaf(h, fmaf(a65, F5[c], fmaf(a64, F4[c], fmaf(a63, F3[c], fmaf(a62, F2[c], a61 * F1[c])))), u[c]);
     }
-    lookup_rel<T, LAYOUT, CACHE>(F, fid, ib, tb, d, B, cache);
+    lookup_rel<T, LAYOUT, CACHE, MOD>(F, fid, ib, tb, mr, d, B, cache);
     lorentz(kap, U6, B, F6);
     float exx[3], euu[3];
 #pragma unroll
@@ -436,7 +495,7 @@ __device__ __forceinline__ bool start(const PropArgs &args, int64_t p, Lane<ACC>
     return true;
 }
 
-template <class T, int LAYOUT, bool MULTI, int ACC, bool CACHE, bool RFL>
+template <class T, int LAYOUT, bool MULTI, int ACC, bool CACHE, bool RFL, bool MOD>
 __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &s, CellCache<T> &cache, EventLDS &e,
                                        int &flags) {
     const int t = threadIdx.x;
@@ -456,8 +515,14 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &
     s.acc.cell(F, 0, ib[0], tb[0]);
     s.acc.cell(F, 1, ib[1], tb[1]);
     s.acc.cell(F, 2, ib[2], tb[2]);
+    ModRel mr;
+    if (MOD && F.mod_data) {
+        s.acc.mod_cell(F, 0, mr.ib[0], mr.tb[0]);
+        s.acc.mod_cell(F, 1, mr.ib[1], mr.tb[1]);
+        s.acc.mod_cell(F, 2, mr.ib[2], mr.tb[2]);
+    }
     float dx5[3], u5[3], ex, eu;
-    ck_eval_f32<T, LAYOUT, CACHE>(F, fid, cache, ib, tb, s.kap, s.u, s.h, dx5, u5, ex, eu);
+    ck_eval_f32<T, LAYOUT, CACHE, MOD>(F, fid, cache, ib, tb, mr, s.kap, s.u, s.h, dx5, u5, ex, eu);
     flags = F_EVAL;
 
     if (s.mode == MODE_NORMAL) {
@@ -569,7 +634,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &
     return CRP_ST_ARRIVED;
 }
 
-template <class T, int LAYOUT, bool MULTI, int ACC, bool CACHE, bool RFL>
+template <class T, int LAYOUT, bool MULTI, int ACC, bool CACHE, bool RFL, bool MOD>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_propagate_mixed(PropArgs a) {
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
@@ -612,7 +677,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
         n_iter++;
         int flags = 0;
         if (pid >= 0) {
-            int st = advance<T, LAYOUT, MULTI, ACC, CACHE, RFL>(a, pid, s, cache, ev, flags);
+            int st = advance<T, LAYOUT, MULTI, ACC, CACHE, RFL, MOD>(a, pid, s, cache, ev, flags);
             if (st != CRP_ST_ACTIVE) pid = -1;
         }
         n_eval += __popcll(__ballot(flags & F_EVAL));
@@ -634,27 +699,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     }
 }
 
+template <class T, int LAYOUT, bool MULTI, int ACC>
+hipError_t launch_feat(const PropArgs &a, bool cache, const dim3 &g, const dim3 &b, hipStream_t s) {
+    // the reflective box and the modulation each have their own instances (the
+    // cell cache, a tuning option only, is not instantiated with them)
+    if (a.reflective && a.modulated)
+        hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, false, true, true>), g, b, 0, s, a);
+    else if (a.reflective)
+        hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, false, true, false>), g, b, 0, s, a);
+    else if (a.modulated)
+        hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, false, false, true>), g, b, 0, s, a);
+    else if (cache)
+        hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, true, false, false>), g, b, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, false, false, false>), g, b, 0, s, a);
+    return hipGetLastError();
+}
+
 template <class T, int LAYOUT, bool MULTI>
 hipError_t launch_acc(const PropArgs &a, int acc, bool cache, int blocks, int bs, hipStream_t s) {
     const dim3 g(blocks), b(bs);
-    if (a.reflective) {
-        // a reflective box (the cell cache, a tuning option only, is not instantiated for it)
-        if (acc == ACC_DF)
-            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_DF, false, true>), g, b, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_F64, false, true>), g, b, 0, s, a);
-    } else if (acc == ACC_DF) {
-        if (cache)
-            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_DF, true, false>), g, b, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_DF, false, false>), g, b, 0, s, a);
-    } else {
-        if (cache)
-            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_F64, true, false>), g, b, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC_F64, false, false>), g, b, 0, s, a);
-    }
-    return hipGetLastError();
+    return acc == ACC_DF ? launch_feat<T, LAYOUT, MULTI, ACC_DF>(a, cache, g, b, s)
+                         : launch_feat<T, LAYOUT, MULTI, ACC_F64>(a, cache, g, b, s);
 }
 
 template <class T>

@@ -118,3 +118,39 @@ def test_modulated_workload_sample(dev, oracle_mod):
     o = _oracle(oracle_mod, B, w.spacing, prm_kw, P, M, w.mod_spacing, o0, sel=sel)
     r = compare({k: v[sel] for k, v in g.items()}, o, "modulated workload sample")
     _say(f"  bitwise fraction {r['bitwise_fraction']}")
+
+
+@pytest.mark.parametrize("prec", ["mixed_f64acc", "mixed_dfacc"])
+def test_mixed_kernel_modulation(dev, oracle_mod, small, prec):
+    """The mixed-precision kernel (FP16 grid, FP32 stages) with a modulation:
+    a modulation of ones changes nothing, bit for bit; with the log-normal
+    modulation the deflections follow the FP64 path's distribution."""
+    from scipy.stats import ks_2samp
+    torch, crp = dev
+    w, B, M, P = small
+    pv = {"mixed_f64acc": crp.CRP_PREC_MIXED_F64ACC, "mixed_dfacc": crp.CRP_PREC_MIXED_DFACC}[prec]
+    _say(f"case: mixed kernel ({prec}) with a modulation")
+    B32 = B.astype(np.float32)
+
+    def run(mod, precision, dtype):
+        f = crp.make_field(B32, w.spacing, dtype=dtype, modulation=mod)
+        st = crp.particles_to_device(P["pos"], P["dir"], P["energy"], P["charge"])
+        crp.crp_propagate([f], [crp.make_params(**PRM)], st, precision=precision)
+        torch.cuda.synchronize()
+        return crp.particles_to_host(st)
+
+    ones = crp.make_modulation(np.ones((7, 9, 11), np.float32), 0.31, origin=(-1.0, 0.2, 0.4))
+    a, b = run(None, pv, "f16"), run(ones, pv, "f16")
+    for k in ("pos", "dir", "length", "status", "n_accepted", "n_rejected", "h_next"):
+        assert np.array_equal(a[k], b[k]), k
+    mod = crp.make_modulation(M.astype(np.float32), 0.25, origin=(-3.0, -3.0, -3.0))
+    g = run(mod, pv, "f16")
+    ref = run(mod, crp.CRP_PREC_FP64, "f32")
+    assert set(np.unique(g["status"])) <= {1, 2}
+    defl = lambda r: np.arccos(np.clip(np.sum(r["dir"] * P["dir"], axis=1), -1, 1))  # noqa: E731
+    ks = ks_2samp(defl(g), defl(ref))
+    _say(f"  KS deflection p = {ks.pvalue:.3f}; arrived {np.mean(g['status'] == 1):.3f} vs {np.mean(ref['status'] == 1):.3f}")
+    assert ks.pvalue > 0.01
+    assert abs(np.mean(g["status"] == 1) - np.mean(ref["status"] == 1)) < 0.02
+    # unmodulated versus modulated: the modulation does change the result
+    assert not np.array_equal(g["dir"], a["dir"])
