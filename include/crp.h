@@ -120,7 +120,7 @@ typedef struct {
     double l_max;          /* length limit, Mpc, > 0; +inf disables it (then max_steps > 0) */
     int64_t max_steps;     /* accepted steps allowed per particle in one call; 0 = no limit */
     int32_t field_index;   /* which entry of the fields array this group uses */
-    int32_t reflect;       /* 1: reflective box below (no tape); 0: none */
+    int32_t reflect;       /* 1: reflective box below; 0: none */
     double box_lo[3], box_hi[3];  /* Mpc, lo < hi on every axis when reflect = 1 */
     int32_t backtrack;     /* 1: backtracking (section 3.3); 0: forward */
     int32_t reserved;      /* 0 */
@@ -261,7 +261,11 @@ size_t crp_adjoint_workspace_bytes(int64_t n, int32_t every_k);
  * A backtracked run (params->backtrack = 1) is differentiated as the forward
  * run of the antiparticle it is: gradients and cotangents refer to the
  * physical directions of the input and output, as crp_propagate reads and
- * writes them.
+ * writes them.  In a reflective box (params->reflect = 1) the replay mirrors
+ * where the forward run mirrored, and the mirrors are held fixed like the
+ * step sizes: on each mirrored axis the position and direction cotangents
+ * change sign (x -> 2 face - x, u -> -u).  The box faces themselves get no
+ * gradient.
  * workspace: [dev] crp_adjoint_workspace_bytes(n, K) bytes, 256-aligned. */
 crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *params, const crp_particles *initial,
                                  int64_t n, const crp_tape *tape, const double *gbar_dir, const double *gbar_time,

@@ -724,7 +724,7 @@ int64_t oracle_propagate_taped(const void *grid, int dtype, int64_t n0, int64_t 
     params_t p;
     if (read_params(prm, &p))
         return -1;
-    if (p.reflect || p.backtrack) /* the replayed map has no mirror and no reversal */
+    if (p.backtrack) /* the replayed map has no reversal (the caller reverses the particle) */
         return -1;
     p.max_steps = 0;
     if (!isfinite(p.l_max))
@@ -750,6 +750,12 @@ int64_t oracle_propagate_taped(const void *grid, int dtype, int64_t n0, int64_t 
  * theorem for its derivative).  Outputs: final direction u_N and path length
  * L = sum of the steps (time = L * Mpc / c).  The energy is unchanged, so its
  * derivative is zero.
+ *
+ * In a reflective box every step but an event step is followed by the mirror
+ * of the forward run, decided on the replayed state's value as the propagator
+ * decides it and then held fixed: on each mirrored axis the position becomes
+ * 2 face - x and the direction component changes sign, so the tangent and
+ * the cotangent of both change sign there.
  *
  * Jacobians: f(Y) = (U, kappa U x B(X)); for a cotangent (kx, ku) of f,
  *   U-bar = kx + kappa B x ku,  B-bar = kappa ku x U,
@@ -878,6 +884,52 @@ static void normalize_dual(dual y[6])
     y[5] = d_div(y[5], n);
 }
 
+/* Axes on which a reflective box (box = lo x, y, z, hi x, y, z; NULL: none)
+ * mirrors a step ending at x: bit a for axis a (the test of reflect_state). */
+static int mirror_mask(const double *box, const double x[3])
+{
+    int m = 0;
+    if (box)
+        for (int a = 0; a < 3; ++a)
+            if (x[a] > box[3 + a] || x[a] < box[a])
+                m |= 1 << a;
+    return m;
+}
+
+/* The mirror of reflect_state on the axes of mask m: position 2 face - x,
+ * direction component negated. */
+static void mirror_apply(const double *box, int m, double y[6])
+{
+    for (int a = 0; a < 3; ++a)
+        if (m >> a & 1) {
+            y[a] = 2.0 * (y[a] > box[3 + a] ? box[3 + a] : box[a]) - y[a];
+            y[3 + a] = -y[3 + a];
+        }
+}
+
+/* The same on a state with tangents: the tangents of the mirrored components
+ * change sign. */
+static void mirror_apply_dual(const double *box, dual y[6])
+{
+    double v[3] = {y[0].v, y[1].v, y[2].v};
+    int m = mirror_mask(box, v);
+    for (int a = 0; a < 3; ++a)
+        if (m >> a & 1) {
+            y[a] = dl(2.0 * (y[a].v > box[3 + a] ? box[3 + a] : box[a]) - y[a].v, -y[a].d);
+            y[3 + a] = dl(-y[3 + a].v, -y[3 + a].d);
+        }
+}
+
+/* Cotangent through the mirror of mask m: the mirrored components change sign. */
+static void mirror_cotangent(int m, double lam[6])
+{
+    for (int a = 0; a < 3; ++a)
+        if (m >> a & 1) {
+            lam[a] = -lam[a];
+            lam[3 + a] = -lam[3 + a];
+        }
+}
+
 static double sphere_g_xyz(const double c[3], double R, const double x[3])
 {
     double d0 = x[0] - c[0], d1 = x[1] - c[1], d2 = x[2] - c[2];
@@ -952,12 +1004,13 @@ static int crossing_newton(const grid_t *g, double kappa, const double y[6], con
  * (h[n-1] is the last accepted step), event != 0 for a sphere crossing in the
  * last step (centre c, radius R; s* found here: by the propagator's Illinois
  * iteration when [0, h[n-1]] brackets it, else by Newton's method on the
- * step map continued to small negative s).  out: [u_N(3), L, du_N(3), dL,
- * x_N(3), s*].  Returns 0, or -1 on bad arguments or no root. */
+ * step map continued to small negative s), box: the reflective box (lo x, y,
+ * z, hi x, y, z) or NULL.  out: [u_N(3), L, du_N(3), dL, x_N(3), s*].
+ * Returns 0, or -1 on bad arguments or no root. */
 int oracle_replay_tangent(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2, const double *origin,
                           double spacing, const void *mod, const double *mod_desc, double kappa, const double *x0, const double *u0, const double *du0,
                           const double *vg, const double *h, int64_t n, int event, const double *c, double R,
-                          double *out)
+                          const double *box, double *out)
 {
     grid_t g;
     if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing, mod, mod_desc) || n < 1)
@@ -975,6 +1028,7 @@ int oracle_replay_tangent(const void *grid, int dtype, int64_t n0, int64_t n1, i
         dual y5[6];
         ck_eval_dual(&g, vg, kappa, y, dl(h[s], 0.0), y5);
         normalize_dual(y5);
+        mirror_apply_dual(box, y5);
         memcpy(y, y5, sizeof y);
         L += h[s];
     }
@@ -1009,6 +1063,8 @@ int oracle_replay_tangent(const void *grid, int dtype, int64_t n0, int64_t n1, i
         ck_eval_dual(&g, vg, kappa, y, dl(sstar, 0.0), z);
     }
     normalize_dual(z);
+    if (!event) /* an event step ends on the sphere, unmirrored */
+        mirror_apply_dual(box, z);
     L += sstar;
     for (int a = 0; a < 3; ++a) {
         out[a] = z[3 + a].v;
@@ -1103,7 +1159,8 @@ static void step_vjp(const grid_t *g, double kappa, const double y[6], double s,
     }
 }
 
-/* Reverse-mode replay (full tape).  ubar: cotangent of u_N (3); Lbar:
+/* Reverse-mode replay (full tape; box: the reflective box or NULL, as in
+ * oracle_replay_tangent).  ubar: cotangent of u_N (3); Lbar:
  * cotangent of the path length (t-bar * Mpc / c).  Outputs: u0bar (cotangent
  * of the raw initial direction), x0bar; gbar (3 n0 n1 n2, FP64) accumulated if
  * not NULL; kappabar (may be NULL): the cotangent of kappa = Z K / E, summed
@@ -1112,8 +1169,8 @@ static void step_vjp(const grid_t *g, double kappa, const double y[6], double s,
  * energy gradient is kappabar * (-kappa / E).  Returns 0 or -1. */
 int oracle_replay_adjoint(const void *grid, int dtype, int64_t n0, int64_t n1, int64_t n2, const double *origin,
                           double spacing, const void *mod, const double *mod_desc, double kappa, const double *x0, const double *u0, const double *h,
-                          int64_t n, int event, const double *c, double R, const double *ubar, double Lbar,
-                          double *u0bar, double *x0bar, double *gbar, double *kappabar)
+                          int64_t n, int event, const double *c, double R, const double *box, const double *ubar,
+                          double Lbar, double *u0bar, double *x0bar, double *gbar, double *kappabar)
 {
     grid_t g;
     if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing, mod, mod_desc) || n < 1)
@@ -1121,8 +1178,12 @@ int oracle_replay_adjoint(const void *grid, int dtype, int64_t n0, int64_t n1, i
     if (g.mod.present) /* derivatives of modulated fields are not provided */
         return -1;
     double *ys = (double *)malloc(sizeof(double) * 6 * (size_t)n);
-    if (!ys)
+    unsigned char *mir = (unsigned char *)malloc((size_t)n); /* mirror mask after each step */
+    if (!ys || !mir) {
+        free(ys);
+        free(mir);
         return -1;
+    }
     double un = sqrt(u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2]);
     double y[6] = {x0[0], x0[1], x0[2], u0[0] / un, u0[1] / un, u0[2] / un};
     for (int64_t s = 0; s < n; ++s) {
@@ -1137,10 +1198,19 @@ int oracle_replay_adjoint(const void *grid, int dtype, int64_t n0, int64_t n1, i
             y[3] = y5[3] / m;
             y[4] = y5[4] / m;
             y[5] = y5[5] / m;
+            mir[s] = (unsigned char)mirror_mask(box, y);
+            mirror_apply(box, mir[s], y);
         }
     }
     const double *yl = ys + 6 * (n - 1);
     double lam[6] = {0.0, 0.0, 0.0, ubar[0], ubar[1], ubar[2]};
+    mir[n - 1] = 0;
+    if (!event && box) { /* the last step of a length stop is mirrored too */
+        double y5[6], d5[6];
+        ck_eval(&g, kappa, yl, h[n - 1], y5, d5);
+        mir[n - 1] = (unsigned char)mirror_mask(box, y5);
+        mirror_cotangent(mir[n - 1], lam);
+    }
     double ybar[6];
     double kb = 0.0;
     double sstar = h[n - 1];
@@ -1149,6 +1219,7 @@ int oracle_replay_adjoint(const void *grid, int dtype, int64_t n0, int64_t n1, i
         ck_eval(&g, kappa, yl, h[n - 1], y5, d5);
         if (!(sphere_g_xyz(c, R, yl) < 0.0 && sphere_g_xyz(c, R, y5) >= 0.0)) {
             free(ys);
+            free(mir);
             return -1;
         }
         sstar = locate_crossing(&g, kappa, yl, h[n - 1], c, R);
@@ -1178,6 +1249,7 @@ int oracle_replay_adjoint(const void *grid, int dtype, int64_t n0, int64_t n1, i
     }
     for (int64_t s = n - 2; s >= 0; --s) {
         double nb[6];
+        mirror_cotangent(mir[s], ybar);
         step_vjp(&g, kappa, ys + 6 * s, h[s], ybar, NULL, nb, gbar, &kb);
         memcpy(ybar, nb, sizeof nb);
     }
@@ -1191,5 +1263,6 @@ int oracle_replay_adjoint(const void *grid, int dtype, int64_t n0, int64_t n1, i
     if (kappabar)
         *kappabar = kb;
     free(ys);
+    free(mir);
     return 0;
 }

@@ -47,10 +47,10 @@ def lib():
         L.oracle_propagate_taped.restype = C.c_int64
         _pdn = C.c_void_p  # optional double arrays (NULL allowed)
         L.oracle_replay_tangent.argtypes = _GRID_ARGS + [C.c_double, _pd, _pd, _pdn, _pdn, _pd, C.c_int64,
-                                                         C.c_int, _pd, C.c_double, _pd]
+                                                         C.c_int, _pd, C.c_double, _pdn, _pd]
         L.oracle_replay_tangent.restype = C.c_int
         L.oracle_replay_adjoint.argtypes = _GRID_ARGS + [C.c_double, _pd, _pd, _pd, C.c_int64, C.c_int, _pd,
-                                                         C.c_double, _pd, C.c_double, _pd, _pd, _pdn, _pd]
+                                                         C.c_double, _pdn, _pd, C.c_double, _pd, _pd, _pdn, _pd]
         L.oracle_replay_adjoint.restype = C.c_int
         for f in (L.oracle_field_at, L.oracle_ck_eval, L.oracle_fixed_steps, L.oracle_propagate):
             f.restype = C.c_int
@@ -201,17 +201,31 @@ def _opt(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64).ctypes.data
 
 
+def _box(box):
+    """Reflective box ((lo x, y, z), (hi x, y, z)) as the 6 doubles the
+    replays take, or None."""
+    if box is None:
+        return None
+    b = np.ascontiguousarray(np.concatenate([np.asarray(box[0], np.float64), np.asarray(box[1], np.float64)]))
+    if b.shape != (6,):
+        raise ValueError("box: ((lo x, y, z), (hi x, y, z))")
+    return b
+
+
 def replay_tangent(grid: Grid, kap: float, x0, u0, h, event: bool, center=(0.0, 0.0, 0.0), radius=0.0,
-                   du0=None, vgrid=None) -> dict:
+                   du0=None, vgrid=None, box=None) -> dict:
     """Frozen-step replay with forward-mode derivatives (tangent du0 of the raw
-    initial direction and vgrid of the grid values)."""
+    initial direction and vgrid of the grid values), in the reflective box
+    ((lo), (hi)) if one is given."""
     out = np.zeros(12)
     du = None if du0 is None else np.ascontiguousarray(du0, dtype=np.float64)
     vg = None if vgrid is None else np.ascontiguousarray(vgrid, dtype=np.float64)
+    bx = _box(box)
     rc = lib().oracle_replay_tangent(*grid.args(), float(kap), np.ascontiguousarray(x0, np.float64),
                                      np.ascontiguousarray(u0, np.float64), None if du is None else du.ctypes.data,
                                      None if vg is None else vg.ctypes.data, np.ascontiguousarray(h, np.float64),
-                                     len(h), int(bool(event)), np.asarray(center, np.float64), float(radius), out)
+                                     len(h), int(bool(event)), np.asarray(center, np.float64), float(radius),
+                                     None if bx is None else bx.ctypes.data, out)
     if rc:
         raise ValueError("oracle_replay_tangent: no crossing bracketed or bad arguments")
     return {"u": out[0:3].copy(), "length": out[3], "du": out[4:7].copy(), "dlength": out[7],
@@ -219,18 +233,21 @@ def replay_tangent(grid: Grid, kap: float, x0, u0, h, event: bool, center=(0.0, 
 
 
 def replay_adjoint(grid: Grid, kap: float, x0, u0, h, event: bool, ubar, lbar: float, center=(0.0, 0.0, 0.0),
-                   radius=0.0, gbar=None) -> dict:
-    """Full-tape reverse sweep of the frozen-step replay.  gbar (FP64 array of
-    the grid's shape) is accumulated in place when given.  kappabar: the
-    cotangent of kappa (the energy gradient is kappabar * (-kappa / E))."""
+                   radius=0.0, gbar=None, box=None) -> dict:
+    """Full-tape reverse sweep of the frozen-step replay (in the reflective
+    box ((lo), (hi)) if one is given).  gbar (FP64 array of the grid's shape)
+    is accumulated in place when given.  kappabar: the cotangent of kappa (the
+    energy gradient is kappabar * (-kappa / E))."""
     u0b = np.zeros(3)
     x0b = np.zeros(3)
     kb = np.zeros(1)
     if gbar is not None:
         assert gbar.dtype == np.float64 and gbar.flags.c_contiguous
+    bx = _box(box)
     rc = lib().oracle_replay_adjoint(*grid.args(), float(kap), np.ascontiguousarray(x0, np.float64),
                                      np.ascontiguousarray(u0, np.float64), np.ascontiguousarray(h, np.float64),
                                      len(h), int(bool(event)), np.asarray(center, np.float64), float(radius),
+                                     None if bx is None else bx.ctypes.data,
                                      np.ascontiguousarray(ubar, np.float64), float(lbar), u0b, x0b,
                                      None if gbar is None else gbar.ctypes.data, kb)
     if rc:

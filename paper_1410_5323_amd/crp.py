@@ -480,7 +480,7 @@ def make_field(values, spacing: float, origin=(0.0, 0.0, 0.0), dtype="f32", layo
 def make_params(tol, h_min, h_max, obs_radius=0.0, l_max=math.inf, obs_center=(0.0, 0.0, 0.0),
                 max_steps=0, field_index=0, box=None, backtrack=False) -> crp_params:
     """One parameter group; ``box`` = ((lo x, y, z), (hi x, y, z)) in Mpc turns on
-    the reflective box (no tape); ``backtrack`` traces the
+    the reflective box; ``backtrack`` traces the
     particles back from where they were observed."""
     p = crp_params()
     p.backtrack = 1 if backtrack else 0

@@ -285,7 +285,6 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
     if (tape) {
         if (precision != CRP_PREC_FP64) return fail(CRP_ERR_UNSUPPORTED, "%s: a tape needs FP64 precision", fn);
         if (modulated) return fail(CRP_ERR_UNSUPPORTED, "%s: no tape (adjoint) for modulated fields", fn);
-        if (reflective) return fail(CRP_ERR_UNSUPPORTED, "%s: no tape (adjoint) with a reflective box", fn);
         if (n_params > 1 || (n > 0 && p->param_index) || n_fields > 1)
             return fail(CRP_ERR_UNSUPPORTED, "%s: a tape is recorded for one field and one parameter group", fn);
         if (fields[0].dtype != CRP_F64 && fields[0].dtype != CRP_F32)
@@ -409,7 +408,6 @@ crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *param
     if (!params) return fail(CRP_ERR_INVALID, "%s: null params", fn);
     st = check_params(params, 1, 0);
     if (st != CRP_OK) return st;
-    if (params->reflect) return fail(CRP_ERR_UNSUPPORTED, "%s: no adjoint with a reflective box", fn);
     if (!initial || !tape) return fail(CRP_ERR_INVALID, "%s: null particles or tape", fn);
     if (n < 0 || n > (int64_t)0x7fffffff) return fail(CRP_ERR_INVALID, "%s: n out of range", fn);
     if (tape->every_k < 1 || tape->every_k > 4096) return fail(CRP_ERR_INVALID, "%s: bad tape interval", fn);

@@ -129,9 +129,9 @@ struct AdjArgs {
 };
 
 // Adjoint replay record: doubles per accepted step (pre-step state 6, step 1,
-// stage states 30, stage fields 18, output direction 3), and the
-// crossing-derivative scratch.
-constexpr int ADJ_RECORD_DOUBLES = 58;
+// stage states 30, stage fields 18, output direction 3, mirrored axes 1), and
+// the crossing-derivative scratch.
+constexpr int ADJ_RECORD_DOUBLES = 59;
 constexpr int ADJ_SCRATCH_DOUBLES = 36;
 
 inline size_t adjoint_ws_bytes(int64_t n, int32_t K, int64_t lanes) {

@@ -111,18 +111,23 @@ __device__ __forceinline__ void bid(const ParamsDev &P, Lane &s) {
 }
 
 // Reflective box: an accepted step that ends outside the box on an axis is
-// mirrored on that face (position 2 face - x, that direction component negated).
-__device__ __forceinline__ void reflect(const ParamsDev &P, double y[6]) {
+// mirrored on that face (position 2 face - x, that direction component
+// negated).  Returns the mirrored axes (bit c for axis c).
+__device__ __forceinline__ int reflect(const ParamsDev &P, double y[6]) {
+    int m = 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         if (y[c] > P.box_hi[c]) {
             y[c] = 2.0 * P.box_hi[c] - y[c];
             y[3 + c] = -y[3 + c];
+            m |= 1 << c;
         } else if (y[c] < P.box_lo[c]) {
             y[c] = 2.0 * P.box_lo[c] - y[c];
             y[3 + c] = -y[3 + c];
+            m |= 1 << c;
         }
     }
+    return m;
 }
 
 // Write the particle's state back (its own slots only).
@@ -454,10 +459,13 @@ template <class T, int LAYOUT, bool MULTI>
 hipError_t launch_c(const PropArgs &a, bool cache, int blocks, int bs, hipStream_t s) {
     constexpr bool wide = std::is_same<T, double>::value || std::is_same<T, float>::value;
     if (a.tape_ckpt) {
-        // taped runs (for the adjoint): one unmodulated field, FP64 or FP32 storage
-        if constexpr (!MULTI && wide)
+        // taped runs (for the adjoint): one unmodulated field, FP64 or FP32
+        // storage, with or without a reflective box
+        if constexpr (!MULTI && wide) {
+            if (a.reflective) return launch_one<T, LAYOUT, false, false, true, false, true>(a, blocks, bs, s);
             return cache ? launch_one<T, LAYOUT, false, true, true, false>(a, blocks, bs, s)
                          : launch_one<T, LAYOUT, false, false, true, false>(a, blocks, bs, s);
+        }
         return hipErrorInvalidValue;
     }
     if (a.reflective) {
@@ -505,10 +513,11 @@ hipError_t launch_layout(const PropArgs &a, int layout, bool multi, bool cache, 
 
 // Record of one accepted step, one column per thread (stride = lanes): the
 // pre-step state y (6), the step size (1), the stage states Y_1..Y_5 (30),
-// the stage field values B_0..B_5 (18) and the unnormalised output
-// direction (3).
-constexpr int REC_Y = 0, REC_H = 6, REC_STAGE = 7, REC_FIELD = 37, REC_ZU = 55, REC_SIZE = ADJ_RECORD_DOUBLES;
-static_assert(REC_ZU + 3 == REC_SIZE, "record layout");
+// the stage field values B_0..B_5 (18), the unnormalised output direction
+// (3) and, in a reflective box, the axes mirrored after the step (1).
+constexpr int REC_Y = 0, REC_H = 6, REC_STAGE = 7, REC_FIELD = 37, REC_ZU = 55, REC_MIR = 58,
+              REC_SIZE = ADJ_RECORD_DOUBLES;
+static_assert(REC_MIR + 1 == REC_SIZE, "record layout");
 
 struct RecordWriter {
     double *r;       // field 0 of the record in this thread's column
@@ -550,8 +559,9 @@ __device__ __forceinline__ double stage_k(double kap, const double Y[6], const d
 // takes it (the caller bids before a step's first attempt): one Cash-Karp
 // evaluation recorded at r (this thread's column), then either a rejection
 // (smaller step, returns false) or the acceptance (controller, normalisation,
-// the pre-step state and step size recorded; returns true).
-template <class T, int LAYOUT>
+// the mirror in a reflective box, the pre-step state, step size and mirrored
+// axes recorded; returns true).
+template <class T, int LAYOUT, bool RFL>
 __device__ bool replay_attempt(const FieldDev &F, const ParamsDev &P, Lane &s, double *r, int64_t stride) {
     CellCache<T> cache;
     cache_reset(cache, (T(*)[CACHE_BLOCK]) nullptr, 0);
@@ -596,8 +606,21 @@ __device__ bool replay_attempt(const FieldDev &F, const ParamsDev &P, Lane &s, d
     s.y[3] = y5[3] / un;
     s.y[4] = y5[4] / un;
     s.y[5] = y5[5] / un;
+    if (RFL) r[REC_MIR * stride] = (double)reflect(P, s.y);
     s.L = Lnew;
     return true;
+}
+
+// Cotangent through the mirror of a recorded step: on each mirrored axis the
+// map is x -> 2 face - x, u -> -u, so both cotangent components change sign.
+__device__ __forceinline__ void mirror_cotangent(const double *r, int64_t stride, double lam[6]) {
+    const int m = (int)r[REC_MIR * stride];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        if (m >> c & 1) {
+            lam[c] = -lam[c];
+            lam[3 + c] = -lam[3 + c];
+        }
 }
 
 // Cell of X with its trilinear fractions and the cell's stored corner values.
@@ -889,7 +912,7 @@ __device__ __forceinline__ void adj_zero(int64_t p) {
 // sweeps its records in reverse, so no lane replays while another one is in
 // the reverse sweep.  Finished lanes take the next particle from a queue
 // ordered by step count, longest first.
-template <class T, int LAYOUT>
+template <class T, int LAYOUT, bool RFL>
 __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
     const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     __shared__ double acc_lds[24][64];
@@ -956,10 +979,10 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
         }
         // one attempt per loop iteration, so a lane's rejections cost the others nothing
         int j = 0;
-        if (m > 0) bid<false>(a.P, s);
+        if (m > 0) bid<RFL>(a.P, s);
         while (__ballot(j < m) != 0ull) {
-            if (j < m && replay_attempt<T, LAYOUT>(a.F, a.P, s, col + (int64_t)j * rstride, a.lanes))
-                if (++j < m) bid<false>(a.P, s);
+            if (j < m && replay_attempt<T, LAYOUT, RFL>(a.F, a.P, s, col + (int64_t)j * rstride, a.lanes))
+                if (++j < m) bid<RFL>(a.P, s);
         }
         const int mmax = wave_max(m);
         if (event) {
@@ -992,12 +1015,15 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
             double comb[3] = {-(psi / gs) * dg[0], -(psi / gs) * dg[1], -(psi / gs) * dg[2]};
             reverse_step<T, LAYOUT>(a.F, L.kap, r, a.lanes, L.lam, comb, acc, a.grad_field, L.kbar);
         }
-        // reverse sweep (the crossing step, if any, is done above)
+        // reverse sweep (the crossing step, if any, is done above; it ends on
+        // the sphere, unmirrored)
         const int mrev = event ? m - 1 : m;
         for (int j = mmax - 1; j >= 0; --j)
-            if (j < mrev)
+            if (j < mrev) {
+                if (RFL) mirror_cotangent(col + (int64_t)j * rstride, a.lanes, L.lam);
                 reverse_step<T, LAYOUT>(a.F, L.kap, col + (int64_t)j * rstride, a.lanes, L.lam, nullptr, acc,
                                         a.grad_field, L.kbar);
+            }
         if (busy) {
             if (--L.seg < 0) {
                 grad_flush(a.F, acc, a.grad_field);
@@ -1017,15 +1043,20 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
 
 }  // namespace
 
-hipError_t launch_adjoint_fp64(const AdjArgs &a, int blocks, hipStream_t s) {
+template <bool RFL>
+hipError_t launch_adjoint_rfl(const AdjArgs &a, int blocks, hipStream_t s) {
     switch (a.F.dtype * 2 + (a.F.layout == CRP_LAYOUT_CELL8)) {
-        case CRP_F64 * 2: hipLaunchKernelGGL((k_adjoint_fp64<double, CRP_LAYOUT_LINEAR>), dim3(blocks), dim3(64), 0, s, a); break;
-        case CRP_F64 * 2 + 1: hipLaunchKernelGGL((k_adjoint_fp64<double, CRP_LAYOUT_CELL8>), dim3(blocks), dim3(64), 0, s, a); break;
-        case CRP_F32 * 2: hipLaunchKernelGGL((k_adjoint_fp64<float, CRP_LAYOUT_LINEAR>), dim3(blocks), dim3(64), 0, s, a); break;
-        case CRP_F32 * 2 + 1: hipLaunchKernelGGL((k_adjoint_fp64<float, CRP_LAYOUT_CELL8>), dim3(blocks), dim3(64), 0, s, a); break;
+        case CRP_F64 * 2: hipLaunchKernelGGL((k_adjoint_fp64<double, CRP_LAYOUT_LINEAR, RFL>), dim3(blocks), dim3(64), 0, s, a); break;
+        case CRP_F64 * 2 + 1: hipLaunchKernelGGL((k_adjoint_fp64<double, CRP_LAYOUT_CELL8, RFL>), dim3(blocks), dim3(64), 0, s, a); break;
+        case CRP_F32 * 2: hipLaunchKernelGGL((k_adjoint_fp64<float, CRP_LAYOUT_LINEAR, RFL>), dim3(blocks), dim3(64), 0, s, a); break;
+        case CRP_F32 * 2 + 1: hipLaunchKernelGGL((k_adjoint_fp64<float, CRP_LAYOUT_CELL8, RFL>), dim3(blocks), dim3(64), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_adjoint_fp64(const AdjArgs &a, int blocks, hipStream_t s) {
+    return a.P.reflect_on ? launch_adjoint_rfl<true>(a, blocks, s) : launch_adjoint_rfl<false>(a, blocks, s);
 }
 
 hipError_t launch_propagate_fp64(const PropArgs &a, int dtype, int layout, bool multi, bool cache, int blocks,

@@ -224,8 +224,8 @@ def test_modulation_descriptor_checks(crp):
 
 
 def test_reflective_box_checks(crp):
-    """A reflective box needs lo < hi on every axis; tapes and the adjoint
-    refuse it, all before any device work."""
+    """A reflective box needs lo < hi on every axis, checked before any device
+    work; tapes and the adjoint accept it."""
     L = crp.lib()
     f = _field(crp)
     f.data = 0x1000
@@ -251,9 +251,13 @@ def test_reflective_box_checks(crp):
     assert call(good, prec=crp.CRP_PREC_MIXED_F64ACC) == crp.CRP_ERR_WORKSPACE  # the mixed kernel reflects too
     assert call(good, prec=crp.CRP_PREC_MIXED_DFACC) == crp.CRP_ERR_WORKSPACE
     tape = crp.crp_tape(0x3000, 0x4000, 0x5000, 0x5800, 100, 64, 0)
-    assert call(good, tape=tape) == crp.CRP_ERR_UNSUPPORTED
+    assert call(good, tape=tape) == crp.CRP_ERR_WORKSPACE  # arguments fine, no workspace
     assert L.crp_propagate_adjoint(C.byref(f), C.byref(good), C.byref(parts), 10, C.byref(tape), 0x6000, None, None,
-                                   0x7000, None, None, 0x8000, None, 0, None) == crp.CRP_ERR_UNSUPPORTED
+                                   0x7000, None, None, 0x8000, None, 0, None) == crp.CRP_ERR_WORKSPACE
+    bad_box = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0, box=((0.0, 0.0, 0.0), (10.0, 0.0, 10.0)))
+    assert call(bad_box, tape=tape) == crp.CRP_ERR_INVALID
+    assert L.crp_propagate_adjoint(C.byref(f), C.byref(bad_box), C.byref(parts), 10, C.byref(tape), 0x6000, None,
+                                   None, 0x7000, None, None, 0x8000, None, 0, None) == crp.CRP_ERR_INVALID
     # a box that is off (reflect = 0) is not checked
     off = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0)
     off.box_lo[0] = 5.0

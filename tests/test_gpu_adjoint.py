@@ -1,6 +1,7 @@
 """GPU adjoint (crp_propagate_adjoint and the autograd function) against the
-FP64 CPU adjoint of the oracle, central finite differences, an analytic
-rotation in a uniform field and the tape's edge cases.
+FP64 CPU adjoint of the oracle (also in a reflective box and for backtracked
+runs), central finite differences, an analytic rotation in a uniform field
+and the tape's edge cases.
 
 The derivative is that of the replayed map (accepted step sizes frozen, the
 sphere crossing differentiated through its defining equation).  The GPU
@@ -63,7 +64,7 @@ def _gpu_adjoint(crp, torch, B, spacing, prm, pos, dirs, energy, charge, gdir, g
             "finals": tape.finals.view(-1, 4).cpu().numpy()}
 
 
-def _oracle_adjoint(O, B, spacing, prm_arr, pos, dirs, energy, charge, gdir, gtime, center, radius):
+def _oracle_adjoint(O, B, spacing, prm_arr, pos, dirs, energy, charge, gdir, gtime, center, radius, box=None):
     g = O.Grid(B, spacing)
     gbar = np.zeros(B.shape, dtype=np.float64)
     gu, gx, ge, steps = [], [], [], []
@@ -71,7 +72,7 @@ def _oracle_adjoint(O, B, spacing, prm_arr, pos, dirs, energy, charge, gdir, gti
         t = O.propagate_taped(g, prm_arr, pos[i], dirs[i], energy[i], charge[i])
         assert t["status"] in (1, 2)
         a = O.replay_adjoint(g, O.kappa(charge[i], energy[i]), pos[i], dirs[i], t["tape"], t["event"], gdir[i],
-                             gtime[i] * SEC_PER_MPC, center=center, radius=radius, gbar=gbar)
+                             gtime[i] * SEC_PER_MPC, center=center, radius=radius, gbar=gbar, box=box)
         gu.append(a["u0bar"])
         gx.append(a["x0bar"])
         kap = O.kappa(charge[i], energy[i])
@@ -99,9 +100,9 @@ def _rel_all(a, b):
     return float(_rel(a.reshape(1, -1), b.reshape(1, -1))[0])
 
 
-def _check_against_oracle(O, r, B, spacing, prm_arr, P, sel, gdir, gtime, center, radius, label):
+def _check_against_oracle(O, r, B, spacing, prm_arr, P, sel, gdir, gtime, center, radius, label, box=None):
     gu, gx, gbar, steps = _oracle_adjoint(O, B, spacing, prm_arr, P["pos"][sel], P["dir"][sel], P["energy"][sel],
-                                          P["charge"][sel], gdir, gtime, center, radius)
+                                          P["charge"][sel], gdir, gtime, center, radius, box=box)
     assert np.array_equal(r["finals"][:, 0].astype(np.int64), steps), f"{label}: accepted-step counts differ"
     eu, ex = _rel(r["gu"], gu), _rel(r["gx"], gx)
     eg = _rel_all(r["gg"], gbar)
@@ -364,6 +365,52 @@ def test_full_adjoint_workload_sampled(dev, oracle_mod):
     eg = _rel_all(rs["gg"], gbar)
     _say(f"sample grid gradient rel err {eg:.2e}")
     assert eg <= GRAD_TOL
+
+
+def test_adjoint_in_reflective_box(dev, oracle_mod):
+    """A reflective box around the start (faces at +-1 Mpc): the replay mirrors
+    where the forward run mirrored and the reverse sweep changes the sign of
+    the mirrored cotangent components.  A sphere of radius 1.3 Mpc, which the
+    box's edges and corners poke out of (arrivals after mirrors), and a
+    length stop; both layouts, two checkpoint intervals, a backtracked run;
+    bitwise against the oracle's reflective adjoint."""
+    torch, crp = dev
+    O = oracle_mod
+    w, B, _ = workload(0, n=1, grid_dtype="f64")
+    fs, ps, _ = ci.config_seeds(0)
+    n = 64
+    P = ci.isotropic_particles(n, 3e18, 3e19, (1, 26), ps)
+    P["pos"] = np.random.default_rng(51).uniform(-0.05, 0.05, (n, 3))
+    rng = np.random.default_rng(52)
+    gdir = rng.standard_normal((n, 3))
+    gtime = rng.standard_normal(n) * 1e-14
+    box = ((-1.0, -1.0, -1.0), (1.0, 1.0, 1.0))
+    sel = np.arange(n)
+    for R, lmax, layout, k, bt in ((1.3, 20.0, "linear", 64, False), (1.3, 20.0, "cell8", 7, False),
+                                   (0.0, 6.0, "cell8", 64, False), (1.3, 20.0, "linear", 64, True)):
+        _say(f"case: reflective adjoint, radius {R}, l_max {lmax}, {layout}, K={k}, backtrack {bt}")
+        prm = crp.make_params(1e-6, 1e-7, 0.2, obs_radius=R, l_max=lmax, box=box, backtrack=bt)
+        r = _gpu_adjoint(crp, torch, B, w.spacing, prm, P["pos"], P["dir"], P["energy"], P["charge"], gdir, gtime,
+                         every_k=k, layout=layout)
+        assert np.all(r["flags"] & 8) and not np.any(r["flags"] & 2)
+        if R > 0:
+            assert np.sum(r["flags"] & 1) >= n // 2, "want arrivals"
+        assert np.sum(r["finals"][:, 0] >= 64) >= n // 2, "want runs over several checkpoints"
+        prm_arr = O.params_array(1e-6, 1e-7, 0.2, radius=R, l_max=lmax, box=box)
+        if not bt:
+            _check_against_oracle(O, r, B, w.spacing, prm_arr, P, sel, gdir, gtime, (0.0, 0.0, 0.0), R,
+                                  f"reflective {layout} K={k}", box=box)
+            continue
+        # backtracked: the reflective adjoint of the reversed antiparticle, gradient reversed back
+        gu, gx, gbar, steps = _oracle_adjoint(O, B, w.spacing, prm_arr, P["pos"], -P["dir"], P["energy"],
+                                              -P["charge"], -gdir, gtime, (0.0, 0.0, 0.0), R, box=box)
+        assert np.array_equal(r["finals"][:, 0].astype(np.int64), steps)
+        eu, ex = _rel(r["gu"], -gu), _rel(r["gx"], gx)
+        ee = _rel_scalar(r["ge"], _oracle_adjoint.last_ge)
+        eg = _rel_all(r["gg"], gbar)
+        _say(f"reflective backtracked: max rel err grad_u0 {eu.max():.2e}, grad_x0 {ex.max():.2e}, "
+             f"grad_energy {ee.max():.2e}, grid {eg:.2e}")
+        assert eu.max() == 0.0 and ex.max() == 0.0 and ee.max() == 0.0 and eg <= GRAD_TOL
 
 
 def test_backtracked_adjoint(dev, oracle_mod):

@@ -4,8 +4,9 @@
 * forward mode (dual numbers) and reverse mode (full tape) agree through the
   dot-product identity <w, J v> = <J^T w, v>, for initial-direction and grid
   directions;
-* central finite differences of the replay map agree with forward mode where
-  the map is smooth at the difference scale (trilinear fields are only C0);
+* central finite differences of the replay map agree with forward mode (and
+  with the reverse sweep's position and kappa gradients) where the map is
+  smooth at the difference scale (trilinear fields are only C0);
 * in a uniform field with a length stop the direction map is the rotation by
   -kappa B L about B, and the time gradient is zero;
 * the grid gradient is supported on the cells the trajectory visits.
@@ -100,6 +101,45 @@ def test_central_differences(oracle_mod, kolmo):
         used += 1
         assert np.linalg.norm(d1 - jv) <= 1e-4 * np.linalg.norm(jv), (d1, jv)
     assert used >= 5
+
+
+def test_central_differences_position_and_kappa(oracle_mod, kolmo):
+    """The position and kappa gradients of the reverse sweep against central
+    differences of the replay map, from starts off the grid's nodes (at a node
+    the trilinear field has a kink and a central difference averages the
+    one-sided slopes); used where steps of 1e-7 and 1e-8 agree to 2e-6."""
+    O = oracle_mod
+    w, g, B, ps = kolmo
+    P = ci.isotropic_particles(12, 3e18, 3e19, (1, 26), ps)
+    R = 2.0
+    prm = O.params_array(1e-6, 1e-7, 0.2, radius=R, l_max=30.0)
+    rng = np.random.default_rng(13)
+    used = {"x": 0, "kappa": 0}
+    for i in range(12):
+        x0 = rng.uniform(-0.05, 0.05, 3)
+        t = _taped(O, g, prm, x0, P["dir"][i], P["energy"][i], P["charge"][i])
+        u0, kap = P["dir"][i], O.kappa(P["charge"][i], P["energy"][i])
+        ub, lb = rng.standard_normal(3), rng.standard_normal()
+        adj = O.replay_adjoint(g, kap, x0, u0, t["tape"], t["event"], ub, lb, radius=R)
+
+        def J(x=x0, k=kap):
+            r = O.replay_tangent(g, k, x, u0, t["tape"], t["event"], radius=R)
+            return ub @ r["u"] + lb * r["length"]
+
+        e = rng.standard_normal(3)
+        e /= np.linalg.norm(e)
+        for name, f, want in (("x", lambda s: J(x=x0 + s * e), adj["x0bar"] @ e),
+                              ("kappa", lambda s: J(k=kap * (1.0 + s)) / kap, adj["kappabar"])):
+            try:
+                d1 = (f(1e-7) - f(-1e-7)) / 2e-7
+                d2 = (f(1e-8) - f(-1e-8)) / 2e-8
+            except ValueError:
+                continue  # the perturbed crossing left the frozen last step
+            if abs(d1 - d2) > 2e-6 * max(abs(d2), 1e-3):
+                continue  # a cell face inside the difference interval
+            used[name] += 1
+            assert abs(d2 - want) <= 1e-5 * max(abs(d2), 1e-3), (name, d2, want)
+    assert min(used.values()) >= 6, used
 
 
 def test_uniform_field_rotation_and_zero_time_gradient(oracle_mod):

@@ -1,0 +1,174 @@
+"""Pins of the oracle's derivatives of the replayed map in a reflective box.
+
+The replay mirrors wherever the forward run mirrored, and the mirrors are then
+held fixed like the step sizes: on each mirrored axis x -> 2 face - x and
+u -> -u, so tangents and cotangents change sign there.
+
+* the replay reproduces the reflective forward run bitwise, and the runs do
+  mirror (the unmirrored replay ends elsewhere);
+* forward mode and reverse mode agree through the dot-product identity, for
+  initial-direction and grid directions;
+* central finite differences of the replay map (mirrors recomputed from the
+  perturbed states) agree with the adjoint's direction, position and kappa
+  gradients where the map is smooth at the difference scale;
+* in a field-free box the path is a straight line folded into the box: the
+  forward run ends at the folded point with the direction's components
+  negated on the axes crossed an odd number of times, the direction gradient
+  is that sign pattern projected on the sphere of directions, and the
+  position and kappa gradients are zero.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import crp_inputs as ci
+
+BOX = ((-1.0, -1.0, -1.0), (1.0, 1.0, 1.0))
+
+
+@pytest.fixture(scope="module")
+def kolmo(oracle_mod):
+    w = ci.get_config(0)
+    fs, ps, _ = ci.config_seeds(0)
+    B = ci.kolmogorov_field(w.grid_n, w.spacing, w.l_min, w.l_max, w.b_rms, fs)
+    return w, oracle_mod.Grid(B, w.spacing), B, ps
+
+
+def _cases(O, g, ps, n, R, l_max, h_min=1e-7):
+    """Particles from near the centre of the box; R > 0: a sphere of radius R
+    that the box's edges and corners poke out of (events after mirrors), else
+    a length stop.  The start is off the grid's nodes: there the trilinear
+    field has a kink, and a central difference across it averages the two
+    one-sided slopes."""
+    P = ci.isotropic_particles(n, 3e18, 3e19, (1, 26), ps)
+    prm = O.params_array(1e-6, h_min, 0.2, radius=R, l_max=l_max, box=BOX)
+    starts = np.random.default_rng(40).uniform(-0.05, 0.05, (n, 3))
+    out = []
+    for i in range(n):
+        x0 = starts[i]
+        t = O.propagate_taped(g, prm, x0, P["dir"][i], P["energy"][i], P["charge"][i])
+        assert t["status"] in (1, 2)
+        out.append((x0, P["dir"][i], O.kappa(P["charge"][i], P["energy"][i]), t))
+    return out
+
+
+def _all_cases(O, g, ps, h_min=1e-7):
+    return [(c, 1.3) for c in _cases(O, g, ps, 8, 1.3, 20.0, h_min)] + \
+        [(c, 0.0) for c in _cases(O, g, ps, 6, 0.0, 6.0, h_min)]
+
+
+def test_replay_reproduces_reflective_forward(oracle_mod, kolmo):
+    O = oracle_mod
+    w, g, B, ps = kolmo
+    mirrored = events = 0
+    for (x0, u0, kap, t), R in _all_cases(O, g, ps):
+        r = O.replay_tangent(g, kap, x0, u0, t["tape"], t["event"], radius=R, box=BOX)
+        assert np.array_equal(r["u"], t["y"][3:]) and np.array_equal(r["x"], t["y"][:3])
+        assert r["length"] == t["length"]
+        plain = O.replay_tangent(g, kap, x0, u0, t["tape"], t["event"], radius=R) if not t["event"] else None
+        mirrored += plain is not None and not np.array_equal(plain["x"], r["x"])
+        mirrored += t["event"] and t["length"] > 2.0  # no path from near the centre to the sphere is that long unmirrored
+        events += t["event"]
+    assert events >= 4 and mirrored >= 8
+
+
+def test_dot_product_identity_reflective(oracle_mod, kolmo):
+    O = oracle_mod
+    w, g, B, ps = kolmo
+    rng = np.random.default_rng(41)
+    for (x0, u0, kap, t), R in _all_cases(O, g, ps):
+        ub = rng.standard_normal(3)
+        lb = rng.standard_normal()
+        gbar = np.zeros_like(B)
+        adj = O.replay_adjoint(g, kap, x0, u0, t["tape"], t["event"], ub, lb, radius=R, gbar=gbar, box=BOX)
+        v = rng.standard_normal(3)
+        tan = O.replay_tangent(g, kap, x0, u0, t["tape"], t["event"], radius=R, du0=v, box=BOX)
+        lhs = ub @ tan["du"] + lb * tan["dlength"]
+        rhs = adj["u0bar"] @ v
+        assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + np.linalg.norm(adj["u0bar"]) * np.linalg.norm(v) + 1e-300)
+        vg = rng.standard_normal(B.shape)
+        tan = O.replay_tangent(g, kap, x0, u0, t["tape"], t["event"], radius=R, vgrid=vg, box=BOX)
+        lhs = ub @ tan["du"] + lb * tan["dlength"]
+        rhs = float(np.sum(gbar * vg))
+        assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + np.sqrt(np.sum(gbar ** 2) * np.sum(vg ** 2)))
+
+
+def test_central_differences_reflective(oracle_mod, kolmo):
+    """The face bid walks a particle up to a face until it is within h_min of
+    it, so the mirror decisions have a margin of order h_min: h_min = 1e-3
+    here, against perturbations of 1e-7 and 1e-8.  Long paths are sensitive
+    (the gradients reach 1e13): a difference is used only where the two
+    perturbation sizes agree to 2e-6, i.e. no kink or mirror decision lies
+    within the larger one."""
+    O = oracle_mod
+    w, g, B, ps = kolmo
+    rng = np.random.default_rng(42)
+    used = {"u": 0, "x": 0, "kappa": 0}
+    for (x0, u0, kap, t), R in _all_cases(O, g, ps, h_min=1e-3):
+        ub = rng.standard_normal(3)
+        lb = rng.standard_normal() * (1.0 if t["event"] else 0.0)
+        adj = O.replay_adjoint(g, kap, x0, u0, t["tape"], t["event"], ub, lb, radius=R, box=BOX)
+
+        def J(x=x0, u=u0, k=kap):
+            r = O.replay_tangent(g, k, x, u, t["tape"], t["event"], radius=R, box=BOX)
+            return ub @ r["u"] + lb * r["length"]
+
+        v = np.cross(u0, rng.standard_normal(3))
+        v /= np.linalg.norm(v)
+        e = rng.standard_normal(3)
+        e /= np.linalg.norm(e)
+        probes = [("u", lambda s: J(u=u0 + s * v), adj["u0bar"] @ v),
+                  ("x", lambda s: J(x=x0 + s * e), adj["x0bar"] @ e),
+                  ("kappa", lambda s: J(k=kap * (1.0 + s)) / kap, adj["kappabar"])]
+        for name, f, want in probes:
+            try:
+                d1 = (f(1e-7) - f(-1e-7)) / 2e-7
+                d2 = (f(1e-8) - f(-1e-8)) / 2e-8
+            except ValueError:
+                continue  # the perturbed crossing left the frozen last step
+            if abs(d1 - d2) > 2e-6 * max(abs(d2), 1e-3):
+                continue  # a cell face or a mirror decision inside the difference interval
+            used[name] += 1
+            assert abs(d2 - want) <= 1e-5 * max(abs(d2), 1e-3), (name, d2, want)
+    assert min(used.values()) >= 6, used
+
+
+def _fold(xi, lo, hi):
+    """Straight-line coordinate xi folded into [lo, hi] by mirrors: the point
+    and the number of face crossings."""
+    w = hi - lo
+    k = math.floor((xi - lo) / w)
+    f = (xi - lo) - k * w
+    return (lo + f if k % 2 == 0 else hi - f), k
+
+
+def test_straight_billiard_closed_form(oracle_mod):
+    O = oracle_mod
+    zero = np.zeros((8, 8, 8, 3))
+    g = O.Grid(zero, 0.5)
+    lo, hi = np.array([-1.0, -0.5, 0.0]), np.array([1.5, 2.0, 1.0])
+    box = (tuple(lo), tuple(hi))
+    L = 7.3
+    prm = O.params_array(1e-6, 1e-4, 0.2, l_max=L, box=box)
+    rng = np.random.default_rng(43)
+    odd = np.zeros(3, dtype=int)
+    for i in range(12):
+        x0 = lo + (hi - lo) * rng.uniform(0.1, 0.9, 3)
+        u0 = rng.standard_normal(3) * 1.7
+        uh = u0 / np.linalg.norm(u0)
+        t = O.propagate_taped(g, prm, x0, u0, 1e19, 1)
+        assert t["status"] == 2 and t["length"] == L
+        S = np.empty(3)
+        for a in range(3):
+            xa, k = _fold(x0[a] + L * uh[a], lo[a], hi[a])
+            S[a] = -1.0 if k % 2 else 1.0
+            odd[a] += k % 2
+            assert abs(t["y"][a] - xa) <= 1e-9, (a, t["y"][a], xa)
+        assert np.allclose(t["y"][3:], S * uh, rtol=0, atol=1e-12)
+        ub = rng.standard_normal(3)
+        adj = O.replay_adjoint(g, O.kappa(1, 1e19), x0, u0, t["tape"], False, ub, 0.0, box=box)
+        want = (np.eye(3) - np.outer(uh, uh)) @ (S * ub) / np.linalg.norm(u0)
+        assert np.allclose(adj["u0bar"], want, rtol=0, atol=1e-12 * np.linalg.norm(ub))
+        assert np.all(adj["x0bar"] == 0.0) and adj["kappabar"] == 0.0
+    assert np.all(odd > 0)  # every axis has runs that end mirrored
