@@ -265,7 +265,10 @@ size_t crp_adjoint_workspace_bytes(int64_t n, int32_t every_k);
  * where the forward run mirrored, and the mirrors are held fixed like the
  * step sizes: on each mirrored axis the position and direction cotangents
  * change sign (x -> 2 face - x, u -> -u).  The box faces themselves get no
- * gradient.
+ * gradient.  A modulated field (section 3.2, modulated grids: B = b m) is
+ * differentiated through both factors: grad_field is the gradient with
+ * respect to the vector grid's values (its cotangent carries the factor m);
+ * the modulation grid's own values get none.
  * workspace: [dev] crp_adjoint_workspace_bytes(n, K) bytes, 256-aligned. */
 crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *params, const crp_particles *initial,
                                  int64_t n, const crp_tape *tape, const double *gbar_dir, const double *gbar_time,

@@ -761,7 +761,10 @@ int64_t oracle_propagate_taped(const void *grid, int dtype, int64_t n0, int64_t 
  *   U-bar = kx + kappa B x ku,  B-bar = kappa ku x U,
  *   X-bar = (dB/dX)^T B-bar,    G-bar[node] += w_node B-bar,
  * with the trilinear weights w_node and gradient dB/dX of the cell in which
- * the stage was evaluated.
+ * the stage was evaluated.  For a modulated field B = b m the vector grid's
+ * value b takes the cotangent b-bar = m B-bar, so X-bar = (db/dX)^T b-bar +
+ * (b . B-bar) dm/dX and G-bar[node] += w_node b-bar (the modulation grid's
+ * own values get no gradient).
  */
 
 typedef struct {
@@ -812,19 +815,51 @@ static int cell_stencil(const grid_t *g, const double X[3], double w[8], int64_t
     return 0;
 }
 
+/* Gradient dm/dX of the modulation (trilinear in its own cell, the cell
+ * mod_at reads), summed over the corners in the order of cell_stencil. */
+static int mod_gradient(const modgrid_t *m, const double X[3], double dm[3])
+{
+    int64_t i0[3], i1[3];
+    double t[3];
+    for (int a = 0; a < 3; ++a) {
+        double f = (X[a] - m->origin[a]) * m->inv_spacing;
+        if (!(fabs(f) < 4.0e15))
+            return -1;
+        double fl = floor(f);
+        t[a] = f - fl;
+        i0[a] = pmod((int64_t)fl, m->n[a]);
+        i1[a] = pmod(i0[a] + 1, m->n[a]);
+    }
+    dm[0] = dm[1] = dm[2] = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+        double wx = dx ? t[0] : 1.0 - t[0], wy = dy ? t[1] : 1.0 - t[1], wz = dz ? t[2] : 1.0 - t[2];
+        double sx = dx ? 1.0 : -1.0, sy = dy ? 1.0 : -1.0, sz = dz ? 1.0 : -1.0;
+        int64_t k = ((dx ? i1[0] : i0[0]) * m->n[1] + (dy ? i1[1] : i0[1])) * m->n[2] + (dz ? i1[2] : i0[2]);
+        double v = m->v64 ? m->v64[k] : (double)m->v32[k];
+        dm[0] += sx * wy * wz * m->inv_spacing * v;
+        dm[1] += wx * sy * wz * m->inv_spacing * v;
+        dm[2] += wx * wy * sz * m->inv_spacing * v;
+    }
+    return 0;
+}
+
 /* Field value (bitwise the propagator's) and its tangent along X-dot, plus the
- * tangent of the grid values vg (FP64, same layout) when given. */
+ * tangent of the vector grid's values vg (FP64, same layout) when given.  A
+ * modulated field B = b m has the tangent b-dot m + b m-dot. */
 static void field_dual(const grid_t *g, const double *vg, const dual X[3], dual B[3])
 {
     double x[3] = {X[0].v, X[1].v, X[2].v}, b[3];
     field_at(g, x, b);
-    double w[8], dw[3][8];
+    double w[8], dw[3][8], dm[3] = {0.0, 0.0, 0.0};
     int64_t idx[8];
-    if (cell_stencil(g, x, w, idx, dw)) {
+    if (cell_stencil(g, x, w, idx, dw) || (g->mod.present && mod_gradient(&g->mod, x, dm))) {
         for (int c = 0; c < 3; ++c)
             B[c] = dl(NAN, NAN);
         return;
     }
+    double m = g->mod.present ? mod_at(&g->mod, x) : 1.0;
+    double mdot = dm[0] * X[0].d + dm[1] * X[1].d + dm[2] * X[2].d;
     for (int c = 0; c < 3; ++c) {
         double d = 0.0;
         for (int k = 0; k < 8; ++k) {
@@ -833,7 +868,7 @@ static void field_dual(const grid_t *g, const double *vg, const dual X[3], dual 
             if (vg)
                 d += w[k] * vg[3 * idx[k] + c];
         }
-        B[c] = dl(b[c], d);
+        B[c] = g->mod.present ? dl(b[c] * m, d * m + b[c] * mdot) : dl(b[c], d);
     }
 }
 
@@ -1015,8 +1050,6 @@ int oracle_replay_tangent(const void *grid, int dtype, int64_t n0, int64_t n1, i
     grid_t g;
     if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing, mod, mod_desc) || n < 1)
         return -1;
-    if (g.mod.present) /* derivatives of modulated fields are not provided */
-        return -1;
     dual y[6];
     for (int a = 0; a < 3; ++a) {
         y[a] = dl(x0[a], 0.0);
@@ -1125,8 +1158,13 @@ static void step_vjp(const grid_t *g, double kappa, const double y[6], double s,
                 v += s * CK_A[j][i] * Ybar[j][c];
             kb[c] = v;
         }
-        double B[3];
-        field_at(g, Y[i], B);
+        /* B = b m: the value the stage used, the vector grid's value b and the
+         * modulation m (1 without one) */
+        double B[3], b[3], m = 1.0;
+        field_at(g, Y[i], b);
+        if (g->mod.present)
+            m = mod_at(&g->mod, Y[i]);
+        field_total(g, Y[i], B);
         const double *U = Y[i] + 3;
         double w[8], dw[3][8];
         int64_t idx[8];
@@ -1140,19 +1178,28 @@ static void step_vjp(const grid_t *g, double kappa, const double y[6], double s,
         Ybar[i][4] = kb[1] + kappa * (B[2] * kb[3] - B[0] * kb[5]);
         Ybar[i][5] = kb[2] + kappa * (B[0] * kb[4] - B[1] * kb[3]);
         Ybar[i][0] = Ybar[i][1] = Ybar[i][2] = 0.0;
+        /* cotangent of the vector grid's interpolated value: b-bar = m B-bar */
+        double bb[3] = {Bb[0] * m, Bb[1] * m, Bb[2] * m};
         if (cell_stencil(g, Y[i], w, idx, dw) == 0) {
             for (int kk = 0; kk < 8; ++kk) {
                 double val[3];
                 for (int c = 0; c < 3; ++c)
                     val[c] = g->v64 ? g->v64[3 * idx[kk] + c] : (double)g->v32[3 * idx[kk] + c];
-                /* X-bar += (dB/dX)^T B-bar: this corner's value dotted with B-bar, times dw */
-                double vb = val[0] * Bb[0] + val[1] * Bb[1] + val[2] * Bb[2];
+                /* X-bar += (db/dX)^T b-bar: this corner's value dotted with b-bar, times dw */
+                double vb = val[0] * bb[0] + val[1] * bb[1] + val[2] * bb[2];
                 for (int a = 0; a < 3; ++a)
                     Ybar[i][a] += dw[a][kk] * vb;
                 if (gbar)
                     for (int c = 0; c < 3; ++c)
-                        gbar[3 * idx[kk] + c] += w[kk] * Bb[c];
+                        gbar[3 * idx[kk] + c] += w[kk] * bb[c];
             }
+        }
+        double dm[3];
+        if (g->mod.present && mod_gradient(&g->mod, Y[i], dm) == 0) {
+            /* X-bar += (b . B-bar) dm/dX */
+            double bB = b[0] * Bb[0] + b[1] * Bb[1] + b[2] * Bb[2];
+            for (int a = 0; a < 3; ++a)
+                Ybar[i][a] += dm[a] * bB;
         }
         for (int c = 0; c < 6; ++c)
             ybar[c] += Ybar[i][c];
@@ -1174,8 +1221,6 @@ int oracle_replay_adjoint(const void *grid, int dtype, int64_t n0, int64_t n1, i
 {
     grid_t g;
     if (make_grid(&g, grid, dtype, n0, n1, n2, origin, spacing, mod, mod_desc) || n < 1)
-        return -1;
-    if (g.mod.present) /* derivatives of modulated fields are not provided */
         return -1;
     double *ys = (double *)malloc(sizeof(double) * 6 * (size_t)n);
     unsigned char *mir = (unsigned char *)malloc((size_t)n); /* mirror mask after each step */

@@ -38,13 +38,14 @@ def _initial_state(u0, x0, energy, charge):
 
 class PropagateFunction(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, u0, grid, x0, energy, charge, spacing, origin, params, layout, every_k, tape_capacity):
+    def forward(ctx, u0, grid, x0, energy, charge, spacing, origin, params, layout, every_k, tape_capacity,
+                modulation):
         if u0.dtype != torch.float64 or x0.dtype != torch.float64 or energy.dtype != torch.float64:
             raise TypeError("u0, x0 and energy must be float64")
         if grid.dtype not in (torch.float64, torch.float32):
             raise TypeError("the grid must be float64 or float32")
         dt = "f64" if grid.dtype == torch.float64 else "f32"
-        field = crp.make_field(grid.detach(), spacing, origin=origin, dtype=dt, layout=layout)
+        field = crp.make_field(grid.detach(), spacing, origin=origin, dtype=dt, layout=layout, modulation=modulation)
         u0d, x0d, charge = u0.detach(), x0.detach(), charge.to(torch.int32)
         init = _initial_state(u0d, x0d, energy.detach(), charge)
         n = u0.shape[0]
@@ -80,11 +81,11 @@ class PropagateFunction(torch.autograd.Function):
         gg = grad_field.to(ctx.grid_dtype) if ctx.needs_input_grad[1] else None
         gx = grad_x0 if ctx.needs_input_grad[2] else None
         gE = grad_e if ctx.needs_input_grad[3] else None
-        return gu, gg, gx, gE, None, None, None, None, None, None, None
+        return gu, gg, gx, gE, None, None, None, None, None, None, None, None
 
 
 def propagate(u0, grid, x0, energy, charge, spacing: float, params, layout: str = "linear", every_k: int = 64,
-              origin=(0.0, 0.0, 0.0), tape_capacity: int | None = None):
+              origin=(0.0, 0.0, 0.0), tape_capacity: int | None = None, modulation=None):
     """Differentiable propagation of n particles from a fresh start.
 
     u0, x0: (n, 3) float64 device tensors (direction need not be normalised;
@@ -95,6 +96,9 @@ def propagate(u0, grid, x0, energy, charge, spacing: float, params, layout: str 
     Returns (direction (n, 3), time (n,) s, energy (n,) eV, status (n,)).
     tape_capacity: checkpoint records to allocate (default 64 per particle);
     a run that needs more is repeated once with the exact number.
+    modulation: a crp.Modulation multiplying the grid (section 3.2, modulated
+    grids); the gradient is taken with respect to the vector grid only.  A
+    reflective box or backtracking is set in params.
     """
     return PropagateFunction.apply(u0, grid, x0, energy, charge, float(spacing), tuple(float(o) for o in origin),
-                                   params, layout, int(every_k), tape_capacity)
+                                   params, layout, int(every_k), tape_capacity, modulation)

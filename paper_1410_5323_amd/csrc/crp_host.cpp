@@ -284,7 +284,6 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
     for (int i = 0; i < n_params; ++i) reflective = reflective || params[i].reflect != 0;
     if (tape) {
         if (precision != CRP_PREC_FP64) return fail(CRP_ERR_UNSUPPORTED, "%s: a tape needs FP64 precision", fn);
-        if (modulated) return fail(CRP_ERR_UNSUPPORTED, "%s: no tape (adjoint) for modulated fields", fn);
         if (n_params > 1 || (n > 0 && p->param_index) || n_fields > 1)
             return fail(CRP_ERR_UNSUPPORTED, "%s: a tape is recorded for one field and one parameter group", fn);
         if (fields[0].dtype != CRP_F64 && fields[0].dtype != CRP_F32)
@@ -404,7 +403,6 @@ crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *param
     if (st != CRP_OK) return st;
     if (field->dtype != CRP_F64 && field->dtype != CRP_F32)
         return fail(CRP_ERR_UNSUPPORTED, "%s: the adjoint reads F64 or F32 grids", fn);
-    if (field->modulation) return fail(CRP_ERR_UNSUPPORTED, "%s: no adjoint for modulated fields", fn);
     if (!params) return fail(CRP_ERR_INVALID, "%s: null params", fn);
     st = check_params(params, 1, 0);
     if (st != CRP_OK) return st;

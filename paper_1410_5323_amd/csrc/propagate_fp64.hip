@@ -459,9 +459,12 @@ template <class T, int LAYOUT, bool MULTI>
 hipError_t launch_c(const PropArgs &a, bool cache, int blocks, int bs, hipStream_t s) {
     constexpr bool wide = std::is_same<T, double>::value || std::is_same<T, float>::value;
     if (a.tape_ckpt) {
-        // taped runs (for the adjoint): one unmodulated field, FP64 or FP32
-        // storage, with or without a reflective box
+        // taped runs (for the adjoint): one field, FP64 or FP32 storage, with
+        // or without a modulation and a reflective box
         if constexpr (!MULTI && wide) {
+            if (a.modulated)
+                return a.reflective ? launch_one<T, LAYOUT, false, false, true, true, true>(a, blocks, bs, s)
+                                    : launch_one<T, LAYOUT, false, false, true, true, false>(a, blocks, bs, s);
             if (a.reflective) return launch_one<T, LAYOUT, false, false, true, false, true>(a, blocks, bs, s);
             return cache ? launch_one<T, LAYOUT, false, true, true, false>(a, blocks, bs, s)
                          : launch_one<T, LAYOUT, false, false, true, false>(a, blocks, bs, s);
@@ -561,13 +564,13 @@ __device__ __forceinline__ double stage_k(double kap, const double Y[6], const d
 // (smaller step, returns false) or the acceptance (controller, normalisation,
 // the mirror in a reflective box, the pre-step state, step size and mirrored
 // axes recorded; returns true).
-template <class T, int LAYOUT, bool RFL>
+template <class T, int LAYOUT, bool RFL, bool MOD>
 __device__ bool replay_attempt(const FieldDev &F, const ParamsDev &P, Lane &s, double *r, int64_t stride) {
     CellCache<T> cache;
     cache_reset(cache, (T(*)[CACHE_BLOCK]) nullptr, 0);
     const RecordWriter rec{r, stride};
     double y5[6], ex, eu;
-    ck_eval<T, LAYOUT, false, RecordWriter>(F, 0, cache, s.kap, s.y, s.h, y5, ex, eu, rec);
+    ck_eval<T, LAYOUT, false, RecordWriter, MOD>(F, 0, cache, s.kap, s.y, s.h, y5, ex, eu, rec);
     double exh = ex / s.h;
     double em = eu > exh ? eu : exh;
     double err = em / P.tol;
@@ -649,6 +652,33 @@ __device__ __forceinline__ double corner_weight(const FieldDev &F, const int ci[
     return wx * wy * wz;
 }
 
+// Modulation at X (section 3.2, modulated grids) as the forward lookup
+// computes it, and its gradient dm/dX (per Mpc) summed over the corners
+// (dx fastest, then dy, then dz).
+template <class M>
+__device__ __forceinline__ double mod_value_grad_t(const FieldDev &F, const double X[3], double dm[3]) {
+    ModCorners<M> mc;
+    mod_load<M>(F, X, mc);
+    const double v[8] = {(double)mc.v000, (double)mc.v100, (double)mc.v010, (double)mc.v110,
+                         (double)mc.v001, (double)mc.v101, (double)mc.v011, (double)mc.v111};
+    dm[0] = dm[1] = dm[2] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int dx = q & 1, dy = (q >> 1) & 1, dz = (q >> 2) & 1;
+        const double wx = dx ? mc.t[0] : 1.0 - mc.t[0], wy = dy ? mc.t[1] : 1.0 - mc.t[1],
+                     wz = dz ? mc.t[2] : 1.0 - mc.t[2];
+        const double sx = dx ? 1.0 : -1.0, sy = dy ? 1.0 : -1.0, sz = dz ? 1.0 : -1.0;
+        dm[0] += sx * wy * wz * F.mod_inv_spacing * v[q];
+        dm[1] += wx * sy * wz * F.mod_inv_spacing * v[q];
+        dm[2] += wx * wy * sz * F.mod_inv_spacing * v[q];
+    }
+    return mod_value<M>(mc);
+}
+
+__device__ __forceinline__ double mod_value_grad(const FieldDev &F, const double X[3], double dm[3]) {
+    return F.mod_dtype == CRP_F64 ? mod_value_grad_t<double>(F, X, dm) : mod_value_grad_t<float>(F, X, dm);
+}
+
 constexpr double ADJ_A[6][5] = {{0, 0, 0, 0, 0},
                                 {A21, 0, 0, 0, 0},
                                 {A31, A32, 0, 0, 0},
@@ -676,8 +706,9 @@ __device__ __forceinline__ void rec_output(double kap, const double *r, int64_t 
 
 // Derivative in the step size of the recorded step's output, dz/ds at s = h
 // (forward mode through the stages; dB/ds from the trilinear gradient of the
-// stage's cell).  kd: scratch column of 36 values for the stage derivatives.
-template <class T, int LAYOUT>
+// stage's cell, and for a modulated field B = b m, b-dot m + b m-dot).  kd:
+// scratch column of 36 values for the stage derivatives.
+template <class T, int LAYOUT, bool MOD>
 __device__ void rec_output_ds(const FieldDev &F, double kap, const double *r, int64_t stride, double *kd,
                               double zs[6]) {
     const double s = r[REC_H * stride];
@@ -705,17 +736,25 @@ __device__ void rec_output_ds(const FieldDev &F, double kap, const double *r, in
         double t[3];
         T raw[24];
         cell_of<T, LAYOUT>(F, Y, ci, t, raw);
-        double Bs[3] = {0.0, 0.0, 0.0}, Bd[3] = {0.0, 0.0, 0.0};
+        // the vector grid's value, interpolated as the forward lookup does
+        double Bs[3], Bd[3] = {0.0, 0.0, 0.0};
+        interp_corners<T>(F, raw, t[0], t[1], t[2], Bs);
         for (int q = 0; q < 8; ++q) {
             double dw[3];
             int64_t node;
-            const double w = corner_weight(F, ci, t, q, dw, node);
+            corner_weight(F, ci, t, q, dw, node);
             const double gd = dw[0] * Yd[0] + dw[1] * Yd[1] + dw[2] * Yd[2];
 #pragma unroll
+            for (int c = 0; c < 3; ++c) Bd[c] += gd * (to_f64<T>(raw[q * 3 + c]) * F.value_scale);
+        }
+        if constexpr (MOD) {
+            double dm[3];
+            const double mv = mod_value_grad(F, Y, dm);
+            const double mdot = dm[0] * Yd[0] + dm[1] * Yd[1] + dm[2] * Yd[2];
+#pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double v = to_f64<T>(raw[q * 3 + c]) * F.value_scale;
-                Bs[c] += w * v;
-                Bd[c] += gd * v;
+                Bd[c] = Bd[c] * mv + Bs[c] * mdot;
+                Bs[c] = Bs[c] * mv;
             }
         }
         const double *U = Y + 3, *Ud = Yd + 3;
@@ -777,8 +816,10 @@ __device__ __forceinline__ void grad_select(const FieldDev &F, GradAccum &g, con
 // Reverse sweep of one recorded step y -> normalise(Phi(y, h)).  lam: in, the
 // cotangent of the normalised output; out, the cotangent of y.  comb (three
 // values or NULL): extra cotangent of the unnormalised output position (the
-// crossing term).  Grid-gradient contributions go to gbar.
-template <class T, int LAYOUT>
+// crossing term).  Grid-gradient contributions go to gbar.  A modulated field
+// B = b m (MOD): the vector grid's value takes b-bar = m B-bar, the position
+// also (b . B-bar) dm/dX.
+template <class T, int LAYOUT, bool MOD>
 __device__ void reverse_step(const FieldDev &F, double kap, const double *r, int64_t stride, double lam[6],
                              const double *comb, GradAccum &acc, double *gbar, double &kbar) {
     const double s = r[REC_H * stride];
@@ -824,22 +865,37 @@ __device__ void reverse_step(const FieldDev &F, double kap, const double *r, int
         T raw[24];
         cell_of<T, LAYOUT>(F, Y, ci, t, raw);
         grad_select(F, acc, ci, gbar);
+        // cotangent of the vector grid's interpolated value: b-bar = m B-bar
+        double bb[3] = {Bb[0], Bb[1], Bb[2]}, dm[3], bB = 0.0;
+        if constexpr (MOD) {
+            const double mv = mod_value_grad(F, Y, dm);
+            double b[3];
+            interp_corners<T>(F, raw, t[0], t[1], t[2], b);
+            bB = b[0] * Bb[0] + b[1] * Bb[1] + b[2] * Bb[2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) bb[c] = Bb[c] * mv;
+        }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             double dw[3];
             int64_t node;
             const double w = corner_weight(F, ci, t, q, dw, node);
-            // X-bar += (dB/dX)^T B-bar: this corner's value dotted with B-bar, times dw
-            const double vb = (to_f64<T>(raw[q * 3 + 0]) * F.value_scale) * Bb[0] +
-                              (to_f64<T>(raw[q * 3 + 1]) * F.value_scale) * Bb[1] +
-                              (to_f64<T>(raw[q * 3 + 2]) * F.value_scale) * Bb[2];
+            // X-bar += (db/dX)^T b-bar: this corner's value dotted with b-bar, times dw
+            const double vb = (to_f64<T>(raw[q * 3 + 0]) * F.value_scale) * bb[0] +
+                              (to_f64<T>(raw[q * 3 + 1]) * F.value_scale) * bb[1] +
+                              (to_f64<T>(raw[q * 3 + 2]) * F.value_scale) * bb[2];
 #pragma unroll
             for (int a = 0; a < 3; ++a) Yb[i][a] += dw[a] * vb;
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 // the lane owns its slot: an LDS add without return, no wait on a read
-                __hip_atomic_fetch_add(&acc.v[3 * q + c][acc.t], w * Bb[c], __ATOMIC_RELAXED,
+                __hip_atomic_fetch_add(&acc.v[3 * q + c][acc.t], w * bb[c], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        if constexpr (MOD) {
+            // X-bar += (b . B-bar) dm/dX
+#pragma unroll
+            for (int a = 0; a < 3; ++a) Yb[i][a] += dm[a] * bB;
         }
 #pragma unroll
         for (int c = 0; c < 6; ++c) yb[c] += Yb[i][c];
@@ -912,7 +968,7 @@ __device__ __forceinline__ void adj_zero(int64_t p) {
 // sweeps its records in reverse, so no lane replays while another one is in
 // the reverse sweep.  Finished lanes take the next particle from a queue
 // ordered by step count, longest first.
-template <class T, int LAYOUT, bool RFL>
+template <class T, int LAYOUT, bool RFL, bool MOD>
 __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
     const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     __shared__ double acc_lds[24][64];
@@ -981,7 +1037,7 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
         int j = 0;
         if (m > 0) bid<RFL>(a.P, s);
         while (__ballot(j < m) != 0ull) {
-            if (j < m && replay_attempt<T, LAYOUT, RFL>(a.F, a.P, s, col + (int64_t)j * rstride, a.lanes))
+            if (j < m && replay_attempt<T, LAYOUT, RFL, MOD>(a.F, a.P, s, col + (int64_t)j * rstride, a.lanes))
                 if (++j < m) bid<RFL>(a.P, s);
         }
         const int mmax = wave_max(m);
@@ -993,14 +1049,14 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
             for (int c = 0; c < 6; ++c) y[c] = r[(REC_Y + c) * a.lanes];
             CellCache<T> cache;
             cache_reset(cache, (T(*)[CACHE_BLOCK]) nullptr, 0);
-            ck_eval<T, LAYOUT, false, RecordWriter>(a.F, 0, cache, L.kap, y, sstar, y5, ex, eu,
+            ck_eval<T, LAYOUT, false, RecordWriter, MOD>(a.F, 0, cache, L.kap, y, sstar, y5, ex, eu,
                                                     RecordWriter{r, a.lanes});
             r[REC_H * a.lanes] = sstar;
             for (int c = 0; c < 3; ++c) r[(REC_ZU + c) * a.lanes] = y5[3 + c];
             // crossing: psi = zbar . Phi_s + Lbar, cotangent zbar - (psi / g_s) dg/dz
             double z[6], zs[6];
             rec_output(L.kap, r, a.lanes, z);
-            rec_output_ds<T, LAYOUT>(a.F, L.kap, r, a.lanes, kdcol, zs);
+            rec_output_ds<T, LAYOUT, MOD>(a.F, L.kap, r, a.lanes, kdcol, zs);
             double zn = sqrt(z[3] * z[3] + z[4] * z[4] + z[5] * z[5]);
             double u[3] = {z[3] / zn, z[4] / zn, z[5] / zn};
             double lu = L.lam[3] * u[0] + L.lam[4] * u[1] + L.lam[5] * u[2];
@@ -1013,7 +1069,7 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
                 gs += dg[c] * zs[c];
             }
             double comb[3] = {-(psi / gs) * dg[0], -(psi / gs) * dg[1], -(psi / gs) * dg[2]};
-            reverse_step<T, LAYOUT>(a.F, L.kap, r, a.lanes, L.lam, comb, acc, a.grad_field, L.kbar);
+            reverse_step<T, LAYOUT, MOD>(a.F, L.kap, r, a.lanes, L.lam, comb, acc, a.grad_field, L.kbar);
         }
         // reverse sweep (the crossing step, if any, is done above; it ends on
         // the sphere, unmirrored)
@@ -1021,7 +1077,7 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
         for (int j = mmax - 1; j >= 0; --j)
             if (j < mrev) {
                 if (RFL) mirror_cotangent(col + (int64_t)j * rstride, a.lanes, L.lam);
-                reverse_step<T, LAYOUT>(a.F, L.kap, col + (int64_t)j * rstride, a.lanes, L.lam, nullptr, acc,
+                reverse_step<T, LAYOUT, MOD>(a.F, L.kap, col + (int64_t)j * rstride, a.lanes, L.lam, nullptr, acc,
                                         a.grad_field, L.kbar);
             }
         if (busy) {
@@ -1043,20 +1099,24 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
 
 }  // namespace
 
-template <bool RFL>
-hipError_t launch_adjoint_rfl(const AdjArgs &a, int blocks, hipStream_t s) {
+template <bool RFL, bool MOD>
+hipError_t launch_adjoint_feat(const AdjArgs &a, int blocks, hipStream_t s) {
     switch (a.F.dtype * 2 + (a.F.layout == CRP_LAYOUT_CELL8)) {
-        case CRP_F64 * 2: hipLaunchKernelGGL((k_adjoint_fp64<double, CRP_LAYOUT_LINEAR, RFL>), dim3(blocks), dim3(64), 0, s, a); break;
-        case CRP_F64 * 2 + 1: hipLaunchKernelGGL((k_adjoint_fp64<double, CRP_LAYOUT_CELL8, RFL>), dim3(blocks), dim3(64), 0, s, a); break;
-        case CRP_F32 * 2: hipLaunchKernelGGL((k_adjoint_fp64<float, CRP_LAYOUT_LINEAR, RFL>), dim3(blocks), dim3(64), 0, s, a); break;
-        case CRP_F32 * 2 + 1: hipLaunchKernelGGL((k_adjoint_fp64<float, CRP_LAYOUT_CELL8, RFL>), dim3(blocks), dim3(64), 0, s, a); break;
+        case CRP_F64 * 2: hipLaunchKernelGGL((k_adjoint_fp64<double, CRP_LAYOUT_LINEAR, RFL, MOD>), dim3(blocks), dim3(64), 0, s, a); break;
+        case CRP_F64 * 2 + 1: hipLaunchKernelGGL((k_adjoint_fp64<double, CRP_LAYOUT_CELL8, RFL, MOD>), dim3(blocks), dim3(64), 0, s, a); break;
+        case CRP_F32 * 2: hipLaunchKernelGGL((k_adjoint_fp64<float, CRP_LAYOUT_LINEAR, RFL, MOD>), dim3(blocks), dim3(64), 0, s, a); break;
+        case CRP_F32 * 2 + 1: hipLaunchKernelGGL((k_adjoint_fp64<float, CRP_LAYOUT_CELL8, RFL, MOD>), dim3(blocks), dim3(64), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+// Instances per feature: a reflective box (RFL) and a modulated field (MOD).
 hipError_t launch_adjoint_fp64(const AdjArgs &a, int blocks, hipStream_t s) {
-    return a.P.reflect_on ? launch_adjoint_rfl<true>(a, blocks, s) : launch_adjoint_rfl<false>(a, blocks, s);
+    const bool mod = a.F.mod_data != nullptr;
+    if (a.P.reflect_on)
+        return mod ? launch_adjoint_feat<true, true>(a, blocks, s) : launch_adjoint_feat<true, false>(a, blocks, s);
+    return mod ? launch_adjoint_feat<false, true>(a, blocks, s) : launch_adjoint_feat<false, false>(a, blocks, s);
 }
 
 hipError_t launch_propagate_fp64(const PropArgs &a, int dtype, int layout, bool multi, bool cache, int blocks,

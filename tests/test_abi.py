@@ -202,7 +202,7 @@ def test_modulation_descriptor_checks(crp):
     assert L.crp_modulation_upload(C.byref(m), 0x100008, crp.CRP_F64, None) == crp.CRP_ERR_INVALID  # overlap
     m.spacing = -1.0
     assert L.crp_modulation_bytes(C.byref(m)) == 0
-    # a modulated field: tapes and the adjoint are refused before any device work; mixed precision takes it
+    # a modulated field: tapes, the adjoint and mixed precision take it (arguments fine, no workspace)
     m.spacing = 0.3
     f = _field(crp)
     f.data = 0x1000
@@ -215,7 +215,11 @@ def test_modulation_descriptor_checks(crp):
                            0, None) == crp.CRP_ERR_WORKSPACE
     tape = crp.crp_tape(0x3000, 0x4000, 0x5000, 0x5800, 100, 64, 0)
     assert L.crp_propagate(farr, 1, parr, 1, C.byref(parts), 10, C.byref(tape), 0, None, None, None, 0,
-                           None) == crp.CRP_ERR_UNSUPPORTED
+                           None) == crp.CRP_ERR_WORKSPACE
+    assert L.crp_propagate(farr, 1, parr, 1, C.byref(parts), 10, C.byref(tape), crp.CRP_PREC_MIXED_F64ACC, None,
+                           None, None, 0, None) == crp.CRP_ERR_UNSUPPORTED  # a tape needs FP64 precision
+    assert L.crp_propagate_adjoint(C.byref(f), C.byref(parr[0]), C.byref(parts), 10, C.byref(tape), 0x6000, None,
+                                   None, 0x7000, None, None, 0x8000, None, 0, None) == crp.CRP_ERR_WORKSPACE
     assert L.crp_propagate(farr, 1, parr, 1, C.byref(parts), 10, None, 0, None, None, None, 0,
                            None) == crp.CRP_ERR_WORKSPACE
     m.data = None

@@ -108,14 +108,3 @@ def test_lognormal_generator_statistics():
     assert abs(slope / (-l * l / 2.0) - 1.0) < 0.1
     # the same seed gives the same grid; FP32 output is the rounded FP64 one
     assert np.array_equal(ci.lognormal_modulation(n, dx, l, sigma, 11, dtype=np.float32), m.astype(np.float32))
-
-
-def test_derivatives_of_modulated_fields_are_refused(oracle_mod, small):
-    O = oracle_mod
-    w, B, P = small
-    grid = O.Grid(B, w.spacing, modulation=O.Modulation(np.ones((4, 4, 4)), 1.0))
-    with pytest.raises(ValueError):
-        O.replay_tangent(grid, 0.1, np.zeros(3), np.array([1.0, 0, 0]), np.array([0.1, 0.1]), False)
-    with pytest.raises(ValueError):
-        O.replay_adjoint(grid, 0.1, np.zeros(3), np.array([1.0, 0, 0]), np.array([0.1, 0.1]), False,
-                         np.ones(3), 0.0)
