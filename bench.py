@@ -21,6 +21,7 @@ peak), the mixed-precision kernel on the same inputs, and the CPU oracle timed
 on a bounded sample of the same workload.
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -365,6 +366,9 @@ def main():
     ap.add_argument("--no-order", action="store_true")
     ap.add_argument("--autotune", type=int, default=None, help="1: tune the launch (default on for batches)")
     ap.add_argument("--graph", type=int, default=None, help="1: replay a captured hipGraph (default on for batches)")
+    ap.add_argument("--tol", type=float, default=None,
+                    help="integrator tolerance in place of the workload's (e.g. to see where the mixed kernel's "
+                         "direction error falls below 1e-4 rad)")
     ap.add_argument("--cpu-sample", type=int, default=200000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost leg")
@@ -402,6 +406,11 @@ def main():
         return
 
     w = ci.get_config(args.workload)
+    if args.tol is not None:
+        if not args.tol > 0.0:
+            print("bench.py: --tol must be positive", file=sys.stderr)
+            sys.exit(2)
+        w = dataclasses.replace(w, tol=args.tol)
     batched = w.n_realisations > 0
     use_graph = bool(args.graph if args.graph is not None else batched)
     use_tuner = bool(args.autotune if args.autotune is not None else batched)
