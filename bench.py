@@ -34,7 +34,8 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-steps/s + gather GB/s vs roofline; adjoint/forward time; err vs FP64"
 HBM_PEAK_GBPS = 8000.0
 BYTES_PER_VALUE = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
-KERNEL_SOURCES = ["crp_device.h", "propagate_fp64.hip", "crp_internal.h"]
+# the kernels' sources and the host code that picks the instance a launch runs
+KERNEL_SOURCES = ["crp_device.h", "propagate_fp64.hip", "crp_internal.h", "crp_host.cpp"]
 PRECISIONS = {"fp64": 0, "mixed_f64acc": 1, "mixed_dfacc": 2}
 
 

@@ -1,9 +1,12 @@
 """Launch-configuration autotuner for crp_propagate.
 
 Searches the crp_tuning knobs (block size, persistent blocks per CU, refill
-threshold, cell cache, longest-first order) on a random subset of the
-particles, one knob at a time (coordinate descent from the defaults), timing
-each candidate with HIP events on the launch stream.  The winner is cached
+threshold, cell cache, longest-first order) on the particles (a random subset
+of ``sample`` of them when there are more), one knob at a time (coordinate
+descent from the defaults), timing each candidate with HIP events on the
+launch stream.  A launch is often set by its longest trajectories, which a
+subset may not hold, so the default sample covers whole workloads of up to a
+million particles.  The winner is cached
 per device architecture and workload signature.  For the FP64 path every
 configuration must give bit-identical results; the winner is checked against
 the defaults on the subset before it is returned.
@@ -68,7 +71,7 @@ def _time(fields, params, pristine, precision, tuning, reps):
     return best, state
 
 
-def autotune(fields, params, particles: dict, precision: int = crp.CRP_PREC_FP64, sample: int = 100_000,
+def autotune(fields, params, particles: dict, precision: int = crp.CRP_PREC_FP64, sample: int = 1_000_000,
              reps: int = 1, use_cache: bool = True, cache_path: str | None = None, seed: int = 0,
              log=None) -> crp.crp_tuning:
     """Return the fastest crp_tuning found for this workload (cached)."""

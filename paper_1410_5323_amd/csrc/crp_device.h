@@ -174,29 +174,24 @@ __device__ __forceinline__ void lookup(const FieldDev &F, const double X[3], dou
     interp_corners<T>(F, v, tx, ty, tz, B);
 }
 
-// Per-lane cache of the corner values of the last cell looked up.  A particle
-// whose steps are small compared with the grid spacing looks up the same cell
-// many times in a row; those lookups then read no global memory.  The key
-// (cell and field) lives in registers, the 24 values in LDS, one column per
-// thread ([value][thread], so the reads of a wavefront hit distinct banks).
-// The values are the stored ones: results are bit-identical with or without it.
-constexpr int CACHE_BLOCK = 256;
-
+// Per-lane cache of the corner values of the last cell looked up, held in the
+// lane's registers.  A particle whose steps are small compared with the grid
+// spacing looks up the same cell many times in a row; those lookups then
+// issue no memory instruction at all, so the longest trajectories' dependent
+// lookups skip the texture path's queues.  The values are the stored ones:
+// results are bit-identical with or without it.
 template <class T>
 struct CellCache {
     uint32_t key;   // cell index (i*n1 + j)*n2 + k, 0xffffffff = empty
     int32_t field;  // field the cell belongs to
-    T (*v)[CACHE_BLOCK];  // LDS [24][CACHE_BLOCK]
-    int t;          // thread's column
+    T v[24];        // the cell's stored corner values
     int misses;     // lookups that read global memory (diagnostic)
 };
 
 template <class T>
-__device__ __forceinline__ void cache_reset(CellCache<T> &c, T (*lds)[CACHE_BLOCK], int t) {
+__device__ __forceinline__ void cache_reset(CellCache<T> &c) {
     c.key = 0xffffffffu;
     c.field = -1;
-    c.v = lds;
-    c.t = t;
     c.misses = 0;
 }
 
@@ -293,19 +288,13 @@ __device__ __forceinline__ void lookup_cached(const FieldDev &F, int fid, const 
     int j = cell_axis(X[1], F.origin[1], F.inv_spacing, F.n[1], F.pow2, ty);
     int k = cell_axis(X[2], F.origin[2], F.inv_spacing, F.n[2], F.pow2, tz);
     uint32_t key = ((uint32_t)i * (uint32_t)F.n[1] + (uint32_t)j) * (uint32_t)F.n[2] + (uint32_t)k;
-    T v[24];
     if (key != cache.key || fid != cache.field) {
-        load_corners<T, LAYOUT>(F, i, j, k, v);
-#pragma unroll
-        for (int w = 0; w < 24; ++w) cache.v[w][cache.t] = v[w];
+        load_corners<T, LAYOUT>(F, i, j, k, cache.v);
         cache.key = key;
         cache.field = fid;
         cache.misses++;
-    } else {
-#pragma unroll
-        for (int w = 0; w < 24; ++w) v[w] = cache.v[w][cache.t];
     }
-    interp_corners<T>(F, v, tx, ty, tz, B);
+    interp_corners<T>(F, cache.v, tx, ty, tz, B);
     if (MOD) modulate(F, X, B);
 }
 

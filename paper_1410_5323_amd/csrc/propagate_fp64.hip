@@ -386,10 +386,9 @@ k_propagate_fp64(PropArgs a) {
     const unsigned long long below = (1ull << lane) - 1ull;
     int64_t pid = -1;  // >= 0 working, -1 wants work, -2 queue exhausted
     __shared__ EventLDS ev;
-    __shared__ T cache_lds[CACHE ? 24 : 1][CACHE_BLOCK];
     Lane s;
     CellCache<T> cache;
-    cache_reset(cache, cache_lds, threadIdx.x);
+    cache_reset(cache);
     // wave-uniform counters, summed from ballots (scalar registers)
     unsigned long long n_eval = 0, n_acc = 0, n_rej = 0, n_ev = 0, n_fl = 0, n_taken = 0, n_iter = 0;
 
@@ -567,7 +566,7 @@ __device__ __forceinline__ double stage_k(double kap, const double Y[6], const d
 template <class T, int LAYOUT, bool RFL, bool MOD>
 __device__ bool replay_attempt(const FieldDev &F, const ParamsDev &P, Lane &s, double *r, int64_t stride) {
     CellCache<T> cache;
-    cache_reset(cache, (T(*)[CACHE_BLOCK]) nullptr, 0);
+    cache_reset(cache);
     const RecordWriter rec{r, stride};
     double y5[6], ex, eu;
     ck_eval<T, LAYOUT, false, RecordWriter, MOD>(F, 0, cache, s.kap, s.y, s.h, y5, ex, eu, rec);
@@ -1048,7 +1047,7 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
             double y[6], y5[6], ex, eu;
             for (int c = 0; c < 6; ++c) y[c] = r[(REC_Y + c) * a.lanes];
             CellCache<T> cache;
-            cache_reset(cache, (T(*)[CACHE_BLOCK]) nullptr, 0);
+            cache_reset(cache);
             ck_eval<T, LAYOUT, false, RecordWriter, MOD>(a.F, 0, cache, L.kap, y, sstar, y5, ex, eu,
                                                     RecordWriter{r, a.lanes});
             r[REC_H * a.lanes] = sstar;
