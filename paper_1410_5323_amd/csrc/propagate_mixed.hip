@@ -201,38 +201,13 @@ template <> struct Acc<ACC_DF> {
     }
 };
 
-// Per-lane cache of the corner values of the last cell looked up: the key
-// (cell and field) in registers, the 24 values in LDS, one column per thread
-// ([value][thread], so the reads of a wavefront hit distinct banks).  This
-// kernel runs at 4 waves per SIMD, whose register budget has no room for the
-// values (the FP64 kernel keeps them in registers).  The values are the stored
-// ones: results are bit-identical with or without it.
-constexpr int CACHE_BLOCK = 256;
-
-template <class T>
-struct LdsCellCache {
-    uint32_t key;         // cell index (i*n1 + j)*n2 + k, 0xffffffff = empty
-    int32_t field;        // field the cell belongs to
-    T (*v)[CACHE_BLOCK];  // LDS [24][CACHE_BLOCK]
-    int t;                // thread's column
-    int misses;           // lookups that read global memory (diagnostic)
-};
-
-template <class T>
-__device__ __forceinline__ void lds_cache_reset(LdsCellCache<T> &c, T (*lds)[CACHE_BLOCK], int t) {
-    c.key = 0xffffffffu;
-    c.field = -1;
-    c.v = lds;
-    c.t = t;
-    c.misses = 0;
-}
-
 // Cell-relative FP32 lookup: base cell ib, fraction tb, stage offset d (Mpc).
-// With CACHE, the last cell's corner values are kept in LDS (key in registers)
-// and a repeated lookup of that cell reads no global memory.
+// With CACHE, the last cell's corner values are kept in the lane's registers
+// and a repeated lookup of that cell reads no global memory; those instances
+// run at 2 waves per SIMD, whose register budget holds the cell unspilled.
 template <class T, int LAYOUT, bool CACHE, bool MOD>
 __device__ __forceinline__ void lookup_rel(const FieldDev &F, int fid, const int ib[3], const float tb[3],
-                                           const ModRel &mr, const float d[3], float B[3], LdsCellCache<T> &cache) {
+                                           const ModRel &mr, const float d[3], float B[3], CellCache<T> &cache) {
     // modulation corners first, so that their loads and the vector grid's are in flight together
     float mv[8], mt[3];
     const bool mod = MOD && F.mod_data != nullptr;
@@ -270,19 +245,16 @@ __device__ __forceinline__ void lookup_rel(const FieldDev &F, int fid, const int
         ci[a] = wrap(ib[a] + (int)fl, F.n[a], F.pow2);
     }
     T v[24];
-    if (CACHE) {
+    if constexpr (CACHE) {
         uint32_t key = ((uint32_t)ci[0] * (uint32_t)F.n[1] + (uint32_t)ci[1]) * (uint32_t)F.n[2] + (uint32_t)ci[2];
         if (key != cache.key || fid != cache.field) {
-            load_corners<T, LAYOUT>(F, ci[0], ci[1], ci[2], v);
-#pragma unroll
-            for (int w = 0; w < 24; ++w) cache.v[w][cache.t] = v[w];
+            load_corners<T, LAYOUT>(F, ci[0], ci[1], ci[2], cache.v);
             cache.key = key;
             cache.field = fid;
             cache.misses++;
-        } else {
-#pragma unroll
-            for (int w = 0; w < 24; ++w) v[w] = cache.v[w][cache.t];
         }
+#pragma unroll
+        for (int w = 0; w < 24; ++w) v[w] = cache.v[w];
     } else {
         load_corners<T, LAYOUT>(F, ci[0], ci[1], ci[2], v);
         cache.misses++;
@@ -321,7 +293,7 @@ __device__ __forceinline__ void lorentz(float kap, const float U[3], const float
 // One FP32 Cash-Karp evaluation from (x, u) with step h: the position offset
 // dx5, the new direction u5 (unnormalised), and the error norms.
 template <class T, int LAYOUT, bool CACHE, bool MOD>
-__device__ __forceinline__ void ck_eval_f32(const FieldDev &F, int fid, LdsCellCache<T> &cache, const int ib[3],
+__device__ __forceinline__ void ck_eval_f32(const FieldDev &F, int fid, CellCache<T> &cache, const int ib[3],
                                             const float tb[3], const ModRel &mr, float kap, const float u[3], float h, float dx5[3],
                                             float u5[3], float &ex, float &eu) {
     float U2[3], U3[3], U4[3], U5[3], U6[3];
@@ -522,7 +494,7 @@ __device__ __forceinline__ bool start(const PropArgs &args, int64_t p, Lane<ACC>
 }
 
 template <class T, int LAYOUT, bool MULTI, int ACC, bool CACHE, bool RFL, bool MOD>
-__device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &s, LdsCellCache<T> &cache, EventLDS &e,
+__device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &s, CellCache<T> &cache, EventLDS &e,
                                        int &flags) {
     const int t = threadIdx.x;
     // per-particle groups: the lane's descriptors, read from the tables once
@@ -661,14 +633,13 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &
 }
 
 template <class T, int LAYOUT, bool MULTI, int ACC, bool CACHE, bool RFL, bool MOD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_propagate_mixed(PropArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CACHE ? 2 : 4, 8))) k_propagate_mixed(PropArgs a) {
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
     int64_t pid = -1;
     __shared__ EventLDS ev;
-    __shared__ T cache_lds[CACHE ? 24 : 1][CACHE_BLOCK];
-    LdsCellCache<T> cache;
-    lds_cache_reset(cache, cache_lds, threadIdx.x);
+    CellCache<T> cache;
+    cache_reset(cache);
     Lane<ACC> s;
     unsigned long long n_eval = 0, n_acc = 0, n_rej = 0, n_ev = 0, n_fl = 0, n_taken = 0, n_iter = 0;
 
