@@ -162,6 +162,35 @@ def test_results_independent_of_launch_configuration(dev, c2_field, tuning):
         assert np.array_equal(ref[k], g[k]), k
 
 
+def test_automatic_cell_cache_choice(dev):
+    """cache_cells = 0 (automatic): on for LINEAR; for CELL8 only above 2048
+    particles per compute unit; off with per-particle parameter groups.  Read
+    from the launch counters: with the cache fewer than 6 cell loads per
+    evaluation, without it exactly 6."""
+    torch, crp = dev
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    w, B, P = workload(1, n=2048 * cus + 4096)
+    f_lin = crp.make_field(B, w.spacing, dtype="f32", layout="linear")
+    f_c8 = crp.make_field(B, w.spacing, dtype="f32", layout="cell8")
+    prm = crp.make_params(w.tol, w.h_min, w.h_max, obs_radius=w.obs_radius, l_max=2.0)
+
+    def loads_per_eval(field, n, groups=1):
+        s = crp.particles_to_device(P["pos"][:n], P["dir"][:n], P["energy"][:n], P["charge"][:n],
+                                    param_index=None if groups == 1 else np.zeros(n, dtype=np.int32))
+        c = torch.zeros(crp.NCOUNTERS, dtype=torch.int64, device="cuda")
+        crp.crp_propagate([field], [prm] * groups, s, counters=c)
+        torch.cuda.synchronize()
+        c = c.cpu().numpy()
+        return c[6] / (6.0 * c[0])
+
+    small, large = 4096, 2048 * cus + 4096
+    _say(f"case: automatic cell cache, {cus} compute units, {small} and {large} particles")
+    assert loads_per_eval(f_lin, small) < 0.9
+    assert loads_per_eval(f_c8, small) == 1.0
+    assert loads_per_eval(f_c8, large) < 0.9
+    assert loads_per_eval(f_c8, large, groups=2) == 1.0
+
+
 def test_cell8_layout_bitwise_equal_to_linear(dev, c2_field):
     torch, crp = dev
     w, B, P = c2_field
