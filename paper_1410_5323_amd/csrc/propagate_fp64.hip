@@ -471,12 +471,19 @@ hipError_t launch_c(const PropArgs &a, bool cache, int blocks, int bs, hipStream
         return hipErrorInvalidValue;
     }
     if (a.reflective) {
-        // a reflective box (the cell cache, a tuning option only, is not
-        // instantiated for it); with or without modulation
+        // a reflective box, with or without modulation; the cell cache is
+        // instantiated for one parameter group only (with per-particle groups
+        // its registers spill, and the automatic setting leaves it off)
         if (a.modulated) {
-            if constexpr (wide) return launch_one<T, LAYOUT, MULTI, false, false, true, true>(a, blocks, bs, s);
+            if constexpr (wide) {
+                if constexpr (!MULTI)
+                    if (cache) return launch_one<T, LAYOUT, false, true, false, true, true>(a, blocks, bs, s);
+                return launch_one<T, LAYOUT, MULTI, false, false, true, true>(a, blocks, bs, s);
+            }
             return hipErrorInvalidValue;
         }
+        if constexpr (!MULTI)
+            if (cache) return launch_one<T, LAYOUT, false, true, false, false, true>(a, blocks, bs, s);
         return launch_one<T, LAYOUT, MULTI, false, false, false, true>(a, blocks, bs, s);
     }
     if (a.modulated) {
