@@ -180,10 +180,10 @@ typedef struct {
     int32_t blocks_per_cu;    /* persistent blocks per compute unit (default 4); 0 = one lane per particle */
     int32_t refill_threshold; /* refill a wavefront when at least this many lanes are idle (default 32) */
     int32_t order_by_rigidity;/* 1: hand out low-rigidity particles first (longest first); default 1 */
-    int32_t cache_cells;      /* keep each lane's last cell in its registers and skip repeated
-                                 loads: 1 on, -1 off, 0 automatic (default, for one parameter
-                                 group: on for LINEAR; for CELL8 on with more than 2048
-                                 particles per compute unit; off with per-particle groups) */
+    int32_t cache_cells;      /* keep each lane's last cell (in registers; in LDS for FP64 with
+                                 per-particle groups) and skip repeated loads: 1 on, -1 off,
+                                 0 automatic (default: on for LINEAR; for CELL8 on with more
+                                 than 2048 particles per compute unit) */
     int32_t reserved[3];
 } crp_tuning;
 

@@ -174,13 +174,17 @@ __device__ __forceinline__ void lookup(const FieldDev &F, const double X[3], dou
     interp_corners<T>(F, v, tx, ty, tz, B);
 }
 
-// Per-lane cache of the corner values of the last cell looked up, held in the
-// lane's registers.  A particle whose steps are small compared with the grid
-// spacing looks up the same cell many times in a row; those lookups then
-// issue no memory instruction at all, so the longest trajectories' dependent
-// lookups skip the texture path's queues.  The values are the stored ones:
-// results are bit-identical with or without it.
-template <class T>
+// Per-lane cache of the corner values of the last cell looked up.  A particle
+// whose steps are small compared with the grid spacing looks up the same cell
+// many times in a row; those lookups then issue no global memory instruction,
+// so the longest trajectories' dependent lookups skip the texture path's
+// queues.  The values are held in the lane's registers, or (IN_LDS) in one
+// LDS column per lane ([value][thread], so the reads of a wavefront hit
+// distinct banks) where the kernel has no registers to spare.  The values are
+// the stored ones: results are bit-identical with or without it.
+constexpr int CACHE_BLOCK = 256;
+
+template <class T, bool IN_LDS = false>
 struct CellCache {
     uint32_t key;   // cell index (i*n1 + j)*n2 + k, 0xffffffff = empty
     int32_t field;  // field the cell belongs to
@@ -189,9 +193,27 @@ struct CellCache {
 };
 
 template <class T>
-__device__ __forceinline__ void cache_reset(CellCache<T> &c) {
+struct CellCache<T, true> {
+    uint32_t key;
+    int32_t field;
+    T (*v)[CACHE_BLOCK];  // LDS [24][CACHE_BLOCK]
+    int t;                // the thread's column
+    int misses;
+};
+
+template <class T>
+__device__ __forceinline__ void cache_reset(CellCache<T, false> &c) {
     c.key = 0xffffffffu;
     c.field = -1;
+    c.misses = 0;
+}
+
+template <class T>
+__device__ __forceinline__ void cache_reset(CellCache<T, true> &c, T (*lds)[CACHE_BLOCK], int t) {
+    c.key = 0xffffffffu;
+    c.field = -1;
+    c.v = lds;
+    c.t = t;
     c.misses = 0;
 }
 
@@ -270,9 +292,9 @@ __device__ __forceinline__ void lookup_mod(const FieldDev &F, const double X[3],
 
 // MOD: the launch has modulated fields (then each field's modulation, if any,
 // multiplies its value); without it no modulation code is compiled in.
-template <class T, int LAYOUT, bool CACHE, bool MOD = false>
+template <class T, int LAYOUT, bool CACHE, bool MOD = false, bool L = false>
 __device__ __forceinline__ void lookup_cached(const FieldDev &F, int fid, const double X[3], double B[3],
-                                              CellCache<T> &cache) {
+                                              CellCache<T, L> &cache) {
     if (!CACHE) {
         if (!MOD || !F.mod_data)
             lookup<T, LAYOUT>(F, X, B);
@@ -288,19 +310,35 @@ __device__ __forceinline__ void lookup_cached(const FieldDev &F, int fid, const 
     int j = cell_axis(X[1], F.origin[1], F.inv_spacing, F.n[1], F.pow2, ty);
     int k = cell_axis(X[2], F.origin[2], F.inv_spacing, F.n[2], F.pow2, tz);
     uint32_t key = ((uint32_t)i * (uint32_t)F.n[1] + (uint32_t)j) * (uint32_t)F.n[2] + (uint32_t)k;
-    if (key != cache.key || fid != cache.field) {
-        load_corners<T, LAYOUT>(F, i, j, k, cache.v);
-        cache.key = key;
-        cache.field = fid;
-        cache.misses++;
+    if constexpr (L) {
+        T v[24];
+        if (key != cache.key || fid != cache.field) {
+            load_corners<T, LAYOUT>(F, i, j, k, v);
+#pragma unroll
+            for (int w = 0; w < 24; ++w) cache.v[w][cache.t] = v[w];
+            cache.key = key;
+            cache.field = fid;
+            cache.misses++;
+        } else {
+#pragma unroll
+            for (int w = 0; w < 24; ++w) v[w] = cache.v[w][cache.t];
+        }
+        interp_corners<T>(F, v, tx, ty, tz, B);
+    } else {
+        if (key != cache.key || fid != cache.field) {
+            load_corners<T, LAYOUT>(F, i, j, k, cache.v);
+            cache.key = key;
+            cache.field = fid;
+            cache.misses++;
+        }
+        interp_corners<T>(F, cache.v, tx, ty, tz, B);
     }
-    interp_corners<T>(F, cache.v, tx, ty, tz, B);
     if (MOD) modulate(F, X, B);
 }
 
 // Right-hand side in path length: k = (U, kappa * U x B(X)) for Y = (X, U).
-template <class T, int LAYOUT, bool CACHE, bool MOD = false>
-__device__ __forceinline__ void rhs(const FieldDev &F, int fid, CellCache<T> &cache, double kap, const double Y[6],
+template <class T, int LAYOUT, bool CACHE, bool MOD = false, bool L = false>
+__device__ __forceinline__ void rhs(const FieldDev &F, int fid, CellCache<T, L> &cache, double kap, const double Y[6],
                                     double k[6], double B[3]) {
     lookup_cached<T, LAYOUT, CACHE, MOD>(F, fid, Y, B, cache);
     k[0] = Y[3];
@@ -329,8 +367,8 @@ struct NoStageRecord {
 // position (ex) and direction (eu) parts.  Stage sums accumulate over j in
 // increasing order with fma starting from zero; terms with a zero weight are
 // omitted (they only add a signed zero).
-template <class T, int LAYOUT, bool CACHE, class Rec = NoStageRecord, bool MOD = false>
-__device__ __forceinline__ void ck_eval(const FieldDev &F, int fid, CellCache<T> &cache, double kap,
+template <class T, int LAYOUT, bool CACHE, class Rec = NoStageRecord, bool MOD = false, bool L = false>
+__device__ __forceinline__ void ck_eval(const FieldDev &F, int fid, CellCache<T, L> &cache, double kap,
                                         const double y[6], double h, double y5[6], double &ex, double &eu,
                                         const Rec &rec = Rec()) {
     double k1[6], k2[6], k3[6], k4[6], k5[6], k6[6], Y[6], B[3];

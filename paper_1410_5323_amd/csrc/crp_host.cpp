@@ -372,16 +372,16 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
     int64_t blocks = t.blocks_per_cu == 0 ? need_blocks : (int64_t)cus * t.blocks_per_cu;
     if (blocks > need_blocks) blocks = need_blocks;
     bool multi = n_params > 1 || p->param_index != nullptr;
-    // Cell cache (the last cell's values in each lane's registers),
-    // automatic, for one parameter group only (with the per-particle group
-    // tables the FP64 kernel spills them).  The LINEAR layout spreads a cell
-    // over several lines and gains.  A CELL8 record is one line; there the
-    // cache pays only with more than 2048 particles per compute unit: then the
-    // texture path is congested, and skipping it shortens the longest
-    // trajectories' dependent lookups, which set the launch time.  With fewer
-    // particles its extra instructions cost more than the queues it avoids
-    // (measured break-even between 2000 and 2900 particles per compute unit).
-    const bool cache_auto = !multi && (fields[0].layout == CRP_LAYOUT_LINEAR || n > 2048 * (int64_t)cus);
+    // Cell cache (the last cell's values in each lane's registers, or in LDS
+    // for the FP64 kernel with per-particle groups), automatic.  The LINEAR
+    // layout spreads a cell over several lines and gains.  A CELL8 record is
+    // one line; there the cache pays only with more than 2048 particles per
+    // compute unit: then the texture path is congested, and skipping it
+    // shortens the longest trajectories' dependent lookups, which set the
+    // launch time.  With fewer particles its extra instructions cost more than
+    // the queues it avoids (measured break-even between 2000 and 2900
+    // particles per compute unit).
+    const bool cache_auto = fields[0].layout == CRP_LAYOUT_LINEAR || n > 2048 * (int64_t)cus;
     const bool cache = t.cache_cells == 0 ? cache_auto : t.cache_cells > 0;
     if (precision == CRP_PREC_FP64)
         e = crp::launch_propagate_fp64(a, fields[0].dtype, fields[0].layout, multi, cache, (int)blocks,

@@ -242,7 +242,7 @@ __device__ __forceinline__ bool start(const PropArgs &args, int64_t p, Lane &s) 
 // One loop iteration of a working lane.  Returns a status != ACTIVE when the
 // particle ended (its result already stored).
 template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE, bool MOD, bool RFL>
-__device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, CellCache<T> &cache, EventLDS &e,
+__device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, CellCache<T, MULTI> &cache, EventLDS &e,
                                        int &flags) {
     const int t = threadIdx.x;
     // per-particle groups: the lane's descriptors, read from the tables once
@@ -387,8 +387,14 @@ k_propagate_fp64(PropArgs a) {
     int64_t pid = -1;  // >= 0 working, -1 wants work, -2 queue exhausted
     __shared__ EventLDS ev;
     Lane s;
-    CellCache<T> cache;
-    cache_reset(cache);
+    // the cell cache in registers; with per-particle group tables (MULTI)
+    // the registers are taken, and it lives in LDS
+    __shared__ T cache_lds[CACHE && MULTI ? 24 : 1][CACHE_BLOCK];
+    CellCache<T, MULTI> cache;
+    if constexpr (MULTI)
+        cache_reset(cache, cache_lds, threadIdx.x);
+    else
+        cache_reset(cache);
     // wave-uniform counters, summed from ballots (scalar registers)
     unsigned long long n_eval = 0, n_acc = 0, n_rej = 0, n_ev = 0, n_fl = 0, n_taken = 0, n_iter = 0;
 
