@@ -698,15 +698,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CACHE 
 
 template <class T, int LAYOUT, bool MULTI, int ACC>
 hipError_t launch_feat(const PropArgs &a, bool cache, const dim3 &g, const dim3 &b, hipStream_t s) {
-    // the reflective box and the modulation each have their own instances (the
-    // cell cache, a tuning option only, is not instantiated with them)
-    if (a.reflective && a.modulated)
-        hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, false, true, true>), g, b, 0, s, a);
-    else if (a.reflective)
-        hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, false, true, false>), g, b, 0, s, a);
-    else if (a.modulated)
-        hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, false, false, true>), g, b, 0, s, a);
-    else if (cache)
+    // the reflective box and the modulation each have their own instances;
+    // with them the cell cache is instantiated for one parameter group only
+    constexpr bool C = !MULTI;
+    if (a.reflective && a.modulated) {
+        if (C && cache)
+            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, C, true, true>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, false, true, true>), g, b, 0, s, a);
+    } else if (a.reflective) {
+        if (C && cache)
+            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, C, true, false>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, false, true, false>), g, b, 0, s, a);
+    } else if (a.modulated) {
+        if (C && cache)
+            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, C, false, true>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, false, false, true>), g, b, 0, s, a);
+    } else if (cache)
         hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, true, false, false>), g, b, 0, s, a);
     else
         hipLaunchKernelGGL((k_propagate_mixed<T, LAYOUT, MULTI, ACC, false, false, false>), g, b, 0, s, a);
