@@ -435,8 +435,8 @@ def test_adjoint_in_reflective_box(dev, oracle_mod):
     where the forward run mirrored and the reverse sweep changes the sign of
     the mirrored cotangent components.  A sphere of radius 1.3 Mpc, which the
     box's edges and corners poke out of (arrivals after mirrors), and a
-    length stop; both layouts, two checkpoint intervals, a backtracked run;
-    bitwise against the oracle's reflective adjoint."""
+    length stop; both layouts, two checkpoint intervals, a backtracked run, FP64
+    and FP32 grids; bitwise against the oracle's reflective adjoint."""
     torch, crp = dev
     O = oracle_mod
     w, B, _ = workload(0, n=1, grid_dtype="f64")
@@ -449,9 +449,12 @@ def test_adjoint_in_reflective_box(dev, oracle_mod):
     gtime = rng.standard_normal(n) * 1e-14
     box = ((-1.0, -1.0, -1.0), (1.0, 1.0, 1.0))
     sel = np.arange(n)
-    for R, lmax, layout, k, bt in ((1.3, 20.0, "linear", 64, False), (1.3, 20.0, "cell8", 7, False),
-                                   (0.0, 6.0, "cell8", 64, False), (1.3, 20.0, "linear", 64, True)):
-        _say(f"case: reflective adjoint, radius {R}, l_max {lmax}, {layout}, K={k}, backtrack {bt}")
+    B64 = B
+    for R, lmax, layout, k, bt, gdt in ((1.3, 20.0, "linear", 64, False, "f64"), (1.3, 20.0, "cell8", 7, False, "f64"),
+                                        (0.0, 6.0, "cell8", 64, False, "f64"), (1.3, 20.0, "linear", 64, True, "f64"),
+                                        (1.3, 20.0, "cell8", 64, False, "f32")):
+        _say(f"case: reflective adjoint, radius {R}, l_max {lmax}, {layout}, K={k}, backtrack {bt}, grid {gdt}")
+        B = B64 if gdt == "f64" else B64.astype(np.float32)
         prm = crp.make_params(1e-6, 1e-7, 0.2, obs_radius=R, l_max=lmax, box=box, backtrack=bt)
         r = _gpu_adjoint(crp, torch, B, w.spacing, prm, P["pos"], P["dir"], P["energy"], P["charge"], gdir, gtime,
                          every_k=k, layout=layout)
@@ -462,7 +465,7 @@ def test_adjoint_in_reflective_box(dev, oracle_mod):
         prm_arr = O.params_array(1e-6, 1e-7, 0.2, radius=R, l_max=lmax, box=box)
         if not bt:
             _check_against_oracle(O, r, B, w.spacing, prm_arr, P, sel, gdir, gtime, (0.0, 0.0, 0.0), R,
-                                  f"reflective {layout} K={k}", box=box)
+                                  f"reflective {layout} K={k} {gdt}", box=box)
             continue
         # backtracked: the reflective adjoint of the reversed antiparticle, gradient reversed back
         gu, gx, gbar, steps = _oracle_adjoint(O, B, w.spacing, prm_arr, P["pos"], -P["dir"], P["energy"],
