@@ -267,7 +267,12 @@ size_t crp_adjoint_workspace_bytes(int64_t n, int32_t every_k);
  * where the forward run mirrored, and the mirrors are held fixed like the
  * step sizes: on each mirrored axis the position and direction cotangents
  * change sign (x -> 2 face - x, u -> -u).  The box faces themselves get no
- * gradient.  A modulated field (section 3.2, modulated grids: B = b m) is
+ * gradient.  This is the derivative of the replayed map.  In a field-free box
+ * it equals that of the forward run, and so it does for particles that never
+ * reflect; for particles that reflect in a field it can differ from the
+ * forward run's own derivative by large factors (mirrors act at step ends,
+ * and next to a face the forward run's step sizes follow the state, so its
+ * result depends on the whole step sequence).  A modulated field (section 3.2, modulated grids: B = b m) is
  * differentiated through both factors: grad_field is the gradient with
  * respect to the vector grid's values (its cotangent carries the factor m);
  * the modulation grid's own values get none.
