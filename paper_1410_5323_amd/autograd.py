@@ -98,7 +98,10 @@ def propagate(u0, grid, x0, energy, charge, spacing: float, params, layout: str 
     a run that needs more is repeated once with the exact number.
     modulation: a crp.Modulation multiplying the grid (section 3.2, modulated
     grids); the gradient is taken with respect to the vector grid only.  A
-    reflective box or backtracking is set in params.
+    reflective box or backtracking is set in params.  In a reflective box the
+    derivative is that of the replayed map (steps and mirrors held fixed): it
+    equals the forward run's in a field-free box and for particles that never
+    reflect, not for particles that reflect in a field.
     """
     return PropagateFunction.apply(u0, grid, x0, energy, charge, float(spacing), tuple(float(o) for o in origin),
                                    params, layout, int(every_k), tape_capacity, modulation)
