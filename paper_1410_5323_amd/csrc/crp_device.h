@@ -189,6 +189,8 @@ struct CellCache {
     uint32_t key;   // cell index (i*n1 + j)*n2 + k, 0xffffffff = empty
     int32_t field;  // field the cell belongs to
     T v[24];        // the cell's stored corner values
+    uint32_t mkey;  // FP32 modulation grid: its last cell, 0xffffffff = empty
+    float mv[8];    // that cell's 8 stored values
     int misses;     // lookups that read global memory (diagnostic)
 };
 
@@ -205,6 +207,7 @@ template <class T>
 __device__ __forceinline__ void cache_reset(CellCache<T, false> &c) {
     c.key = 0xffffffffu;
     c.field = -1;
+    c.mkey = 0xffffffffu;
     c.misses = 0;
 }
 
@@ -333,7 +336,49 @@ __device__ __forceinline__ void lookup_cached(const FieldDev &F, int fid, const 
         }
         interp_corners<T>(F, cache.v, tx, ty, tz, B);
     }
-    if (MOD) modulate(F, X, B);
+    if (MOD) {
+        if constexpr (!L) {
+            // an FP32 modulation grid's last cell is kept too (its cells are
+            // larger than the vector grid's, so it is revisited longer)
+            if (F.mod_data && F.mod_dtype == CRP_F32) {
+                ModCorners<float> mc;
+                int c[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    c[a] = cell_axis(X[a], F.mod_origin[a], F.mod_inv_spacing, F.mod_n[a], F.mod_pow2, mc.t[a]);
+                const uint32_t mkey = ((uint32_t)c[0] * (uint32_t)F.mod_n[1] + (uint32_t)c[1]) * (uint32_t)F.mod_n[2] +
+                                      (uint32_t)c[2];
+                if (mkey != cache.mkey) {
+                    const global_ptr<float> p = as_global<float>(F.mod_data) +
+                                                ((uint32_t)c[0] * F.mod_sx + (uint32_t)c[1] * F.mod_sy + (uint32_t)c[2]);
+                    const uint32_t sx = F.mod_sx, sy = F.mod_sy;
+                    cache.mv[0] = p[0];
+                    cache.mv[1] = p[1];
+                    cache.mv[2] = p[sx];
+                    cache.mv[3] = p[sx + 1];
+                    cache.mv[4] = p[sy];
+                    cache.mv[5] = p[sy + 1];
+                    cache.mv[6] = p[sx + sy];
+                    cache.mv[7] = p[sx + sy + 1];
+                    cache.mkey = mkey;
+                }
+                mc.v000 = cache.mv[0];
+                mc.v001 = cache.mv[1];
+                mc.v100 = cache.mv[2];
+                mc.v101 = cache.mv[3];
+                mc.v010 = cache.mv[4];
+                mc.v011 = cache.mv[5];
+                mc.v110 = cache.mv[6];
+                mc.v111 = cache.mv[7];
+                const double m = mod_value<float>(mc);
+                B[0] = B[0] * m;
+                B[1] = B[1] * m;
+                B[2] = B[2] * m;
+                return;
+            }
+        }
+        modulate(F, X, B);
+    }
 }
 
 // Right-hand side in path length: k = (U, kappa * U x B(X)) for Y = (X, U).
