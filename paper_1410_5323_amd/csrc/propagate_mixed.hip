@@ -224,14 +224,28 @@ __device__ __forceinline__ void lookup_rel(const FieldDev &F, int fid, const int
         const uint32_t o = (uint32_t)mc[0] * F.mod_sx + (uint32_t)mc[1] * F.mod_sy + (uint32_t)mc[2];
         const uint32_t sx = F.mod_sx, sy = F.mod_sy;
         const uint32_t off[8] = {0, 1, sx, sx + 1, sy, sy + 1, sx + sy, sx + sy + 1};
-        if (F.mod_dtype == CRP_F64) {
-            const global_ptr<double> q = as_global<double>(F.mod_data) + o;
+        // with CACHE the modulation's last cell is kept too (as the FP32 values
+        // used here); its cells are larger than the vector grid's
+        const uint32_t mkey = ((uint32_t)mc[0] * (uint32_t)F.mod_n[1] + (uint32_t)mc[1]) * (uint32_t)F.mod_n[2] +
+                              (uint32_t)mc[2];
+        if (!CACHE || mkey != cache.mkey) {
+            if (F.mod_dtype == CRP_F64) {
+                const global_ptr<double> q = as_global<double>(F.mod_data) + o;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) mv[k] = (float)q[off[k]];
+                for (int k = 0; k < 8; ++k) mv[k] = (float)q[off[k]];
+            } else {
+                const global_ptr<float> q = as_global<float>(F.mod_data) + o;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) mv[k] = q[off[k]];
+            }
+            if constexpr (CACHE) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) cache.mv[k] = mv[k];
+                cache.mkey = mkey;
+            }
         } else {
-            const global_ptr<float> q = as_global<float>(F.mod_data) + o;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) mv[k] = q[off[k]];
+            for (int k = 0; k < 8; ++k) mv[k] = cache.mv[k];
         }
     }
     const float inv = (float)F.inv_spacing;
