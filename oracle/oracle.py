@@ -46,7 +46,7 @@ def lib():
                                                           _pd, _pd, C.c_int64, _pd]
         L.oracle_propagate_taped.restype = C.c_int64
         _pdn = C.c_void_p  # optional double arrays (NULL allowed)
-        L.oracle_replay_tangent.argtypes = _GRID_ARGS + [C.c_double, _pd, _pd, _pdn, _pdn, _pd, C.c_int64,
+        L.oracle_replay_tangent.argtypes = _GRID_ARGS + [C.c_double, _pd, _pd, _pdn, _pdn, _pdn, _pd, C.c_int64,
                                                          C.c_int, _pd, C.c_double, _pdn, _pd]
         L.oracle_replay_tangent.restype = C.c_int
         L.oracle_replay_adjoint.argtypes = _GRID_ARGS + [C.c_double, _pd, _pd, _pd, C.c_int64, C.c_int, _pd,
@@ -213,16 +213,18 @@ def _box(box):
 
 
 def replay_tangent(grid: Grid, kap: float, x0, u0, h, event: bool, center=(0.0, 0.0, 0.0), radius=0.0,
-                   du0=None, vgrid=None, box=None) -> dict:
-    """Frozen-step replay with forward-mode derivatives (tangent du0 of the raw
-    initial direction and vgrid of the grid values), in the reflective box
-    ((lo), (hi)) if one is given."""
+                   du0=None, vgrid=None, box=None, dx0=None) -> dict:
+    """Frozen-step replay with forward-mode derivatives (tangents du0 of the
+    raw initial direction, dx0 of the initial position and vgrid of the grid
+    values), in the reflective box ((lo), (hi)) if one is given."""
     out = np.zeros(12)
     du = None if du0 is None else np.ascontiguousarray(du0, dtype=np.float64)
+    dx = None if dx0 is None else np.ascontiguousarray(dx0, dtype=np.float64)
     vg = None if vgrid is None else np.ascontiguousarray(vgrid, dtype=np.float64)
     bx = _box(box)
     rc = lib().oracle_replay_tangent(*grid.args(), float(kap), np.ascontiguousarray(x0, np.float64),
                                      np.ascontiguousarray(u0, np.float64), None if du is None else du.ctypes.data,
+                                     None if dx is None else dx.ctypes.data,
                                      None if vg is None else vg.ctypes.data, np.ascontiguousarray(h, np.float64),
                                      len(h), int(bool(event)), np.asarray(center, np.float64), float(radius),
                                      None if bx is None else bx.ctypes.data, out)

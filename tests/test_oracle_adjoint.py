@@ -2,8 +2,8 @@
 
 * the replay reproduces the forward run bitwise;
 * forward mode (dual numbers) and reverse mode (full tape) agree through the
-  dot-product identity <w, J v> = <J^T w, v>, for initial-direction and grid
-  directions;
+  dot-product identity <w, J v> = <J^T w, v>, for initial-direction,
+  initial-position and grid directions;
 * central finite differences of the replay map agree with forward mode (and
   with the reverse sweep's position and kappa gradients) where the map is
   smooth at the difference scale (trilinear fields are only C0);
@@ -73,6 +73,35 @@ def test_dot_product_identity_direction_and_grid(oracle_mod, kolmo):
         lhs = ub @ tan["du"] + lb * tan["dlength"]
         rhs = float(np.sum(gbar * vg))
         assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + np.sqrt(np.sum(gbar ** 2) * np.sum(vg ** 2)))
+
+
+def test_dot_product_identity_position(oracle_mod, kolmo):
+    """The reverse sweep's position cotangent against forward mode in the
+    initial position.  Forward mode forms (dB/dX) X-dot component by
+    component, sum over corners of (grad w . X-dot) G; the reverse sweep
+    forms (dB/dX)^T B-bar as the sum over corners of grad w (G . B-bar).  The
+    two orders differ only in rounding, so the identity holds to rounding
+    whatever grouping either side uses."""
+    O = oracle_mod
+    w, g, B, ps = kolmo
+    P = ci.isotropic_particles(8, 3e18, 3e19, (1, 26), ps)
+    R = 2.0
+    prm = O.params_array(1e-6, 1e-7, 0.2, radius=R, l_max=30.0)
+    rng = np.random.default_rng(14)
+    for i in range(8):
+        x0 = rng.uniform(-0.05, 0.05, 3)
+        t = _taped(O, g, prm, x0, P["dir"][i], P["energy"][i], P["charge"][i])
+        u0, kap = P["dir"][i], O.kappa(P["charge"][i], P["energy"][i])
+        ub, lb = rng.standard_normal(3), rng.standard_normal()
+        adj = O.replay_adjoint(g, kap, x0, u0, t["tape"], t["event"], ub, lb, radius=R)
+        v = rng.standard_normal(3)
+        tan = O.replay_tangent(g, kap, x0, u0, t["tape"], t["event"], radius=R, dx0=v)
+        lhs = ub @ tan["du"] + lb * tan["dlength"]
+        rhs = adj["x0bar"] @ v
+        assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + np.linalg.norm(adj["x0bar"]) * np.linalg.norm(v)), (lhs, rhs)
+        # the position tangent alone moves nothing else: du0 = 0 gives the same
+        tan0 = O.replay_tangent(g, kap, x0, u0, t["tape"], t["event"], radius=R)
+        assert np.all(tan0["du"] == 0.0) and tan0["dlength"] == 0.0
 
 
 def test_central_differences(oracle_mod, kolmo):

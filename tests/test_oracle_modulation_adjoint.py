@@ -7,7 +7,7 @@ no gradient.
 
 * the replay reproduces the modulated forward run bitwise;
 * forward mode and reverse mode agree through the dot-product identity, for
-  initial-direction and grid directions;
+  initial-direction, initial-position and grid directions;
 * central differences of the replay map agree with the adjoint's direction,
   position and kappa gradients where the map is smooth at the difference
   scale (starts off both grids' nodes);
@@ -81,6 +81,12 @@ def test_dot_product_identity_modulated(oracle_mod, modf):
         lhs = ub @ tan["du"] + lb * tan["dlength"]
         rhs = float(np.sum(gbar * vg))
         assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + np.sqrt(np.sum(gbar ** 2) * np.sum(vg ** 2)))
+        # the position cotangent against forward mode in the initial position
+        v = rng.standard_normal(3)
+        tan = O.replay_tangent(g, kap, x0, u0, t["tape"], t["event"], radius=R, dx0=v)
+        lhs = ub @ tan["du"] + lb * tan["dlength"]
+        rhs = adj["x0bar"] @ v
+        assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + np.linalg.norm(adj["x0bar"]) * np.linalg.norm(v) + 1e-300)
 
 
 def test_central_differences_modulated(oracle_mod, modf):

@@ -7,7 +7,7 @@ u -> -u, so tangents and cotangents change sign there.
 * the replay reproduces the reflective forward run bitwise, and the runs do
   mirror (the unmirrored replay ends elsewhere);
 * forward mode and reverse mode agree through the dot-product identity, for
-  initial-direction and grid directions;
+  initial-direction, initial-position and grid directions;
 * central finite differences of the replay map (mirrors recomputed from the
   perturbed states) agree with the adjoint's direction, position and kappa
   gradients where the map is smooth at the difference scale;
@@ -97,6 +97,12 @@ def test_dot_product_identity_reflective(oracle_mod, kolmo):
         lhs = ub @ tan["du"] + lb * tan["dlength"]
         rhs = float(np.sum(gbar * vg))
         assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + np.sqrt(np.sum(gbar ** 2) * np.sum(vg ** 2)))
+        # the position cotangent against forward mode in the initial position
+        v = rng.standard_normal(3)
+        tan = O.replay_tangent(g, kap, x0, u0, t["tape"], t["event"], radius=R, dx0=v, box=BOX)
+        lhs = ub @ tan["du"] + lb * tan["dlength"]
+        rhs = adj["x0bar"] @ v
+        assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + np.linalg.norm(adj["x0bar"]) * np.linalg.norm(v) + 1e-300)
 
 
 def test_central_differences_reflective(oracle_mod, kolmo):
