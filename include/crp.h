@@ -72,9 +72,6 @@ enum {
     CRP_ST_BAD_INPUT = 6    /* E <= 0, zero or non-finite direction or position, bad h_next */
 };
 
-/* One periodic vector grid (section 3.2: regular grids; section 4: a vector
- * grid with a random Kolmogorov realisation).  Node (i,j,k) sits at
- * origin + spacing*(i,j,k); the field repeats with period n*spacing. */
 /* A periodic scalar modulation grid (section 3.2, modulated grids: a small
  * high-resolution vector grid repeated periodically, times a large
  * low-resolution grid that carries the large-scale structure).  The field at
@@ -88,6 +85,9 @@ typedef struct {
     void *data;            /* [dev] crp_modulation_bytes(this) bytes, written by crp_modulation_upload */
 } crp_modulation;
 
+/* One periodic vector grid (section 3.2: regular grids; section 4: a vector
+ * grid with a random Kolmogorov realisation).  Node (i,j,k) sits at
+ * origin + spacing*(i,j,k); the field repeats with period n*spacing. */
 typedef struct {
     int32_t n[3];          /* nodes per axis, each >= 2 */
     int32_t dtype;         /* crp_dtype of the stored values */
@@ -302,8 +302,9 @@ crp_status crp_graph_destroy(crp_graph *g);
 /* Device arithmetic conformance: apply operation op to n inputs in[] ([dev]
  * FP64) writing out[] ([dev] FP64).  op: 0 sqrt, 1 reciprocal (1/x), 2 fma(x, y,
  * z) on triples (n triples, in has 3n values), 3 floor, 4 the controller's
- * fifth root x^(-1/5), 5 the controller's shrink factor 1/sqrt(sqrt(x)).  Used
- * to check that the device rounds exactly like the host. */
+ * fifth root x^(-1/5), 5 the controller's shrink factor 1/sqrt(sqrt(x)), 6 the
+ * quotient x/y on pairs (n pairs, in has 2n values).  Used to check that the
+ * device rounds exactly like the host. */
 crp_status crp_selftest_arith(const double *in, double *out, int64_t n, int32_t op, void *stream);
 
 /* Gather microbenchmark (measurement only): lanes threads each perform

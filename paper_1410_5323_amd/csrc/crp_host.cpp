@@ -190,6 +190,15 @@ int cu_count() {
 
 }  // namespace
 
+namespace crp {
+
+crp_status report(crp_status st, const char *msg) {
+    if (st == CRP_OK) return ok();
+    return fail(st, "%s", msg);
+}
+
+}  // namespace crp
+
 extern "C" {
 
 const char *crp_last_error(void) { return g_last_error.c_str(); }
@@ -254,7 +263,23 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
                          const crp_particles *p, int64_t n, const crp_tape *tape, int32_t precision,
                          const crp_tuning *tuning, int64_t *counters, void *workspace, size_t workspace_bytes,
                          void *stream) {
-    const char *fn = "crp_propagate";
+    if (!fields || n_fields < 1 || n_fields > 4096) return fail(CRP_ERR_INVALID, "crp_propagate: need 1..4096 fields");
+    if (!params || n_params < 1 || n_params > 65536)
+        return fail(CRP_ERR_INVALID, "crp_propagate: need 1..65536 params");
+    std::vector<crp::FieldDev> fd(n_fields);
+    std::vector<crp::ParamsDev> pd(n_params);
+    return crp::propagate_impl("crp_propagate", fields, n_fields, params, n_params, p, n, tape, precision, tuning,
+                               counters, workspace, workspace_bytes, stream, fd.data(), pd.data(), false);
+}
+
+}  // extern "C"
+
+namespace crp {
+
+crp_status propagate_impl(const char *fn, const crp_field *fields, int32_t n_fields, const crp_params *params,
+                          int32_t n_params, const crp_particles *p, int64_t n, const crp_tape *tape,
+                          int32_t precision, const crp_tuning *tuning, int64_t *counters, void *workspace,
+                          size_t workspace_bytes, void *stream, FieldDev *fd, ParamsDev *pd, bool check_only) {
     if (!fields || n_fields < 1 || n_fields > 4096) return fail(CRP_ERR_INVALID, "%s: need 1..4096 fields", fn);
     if (!params || n_params < 1 || n_params > 65536) return fail(CRP_ERR_INVALID, "%s: need 1..65536 params", fn);
     if (!p) return fail(CRP_ERR_INVALID, "%s: null particles", fn);
@@ -305,7 +330,7 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
     if (t.cache_cells < -1 || t.cache_cells > 1)
         return fail(CRP_ERR_INVALID, "%s: cache_cells must be -1, 0 or 1", fn);
     crp::WsLayout wl = crp::ws_layout(n, n_fields, n_params);
-    if (n == 0) return ok();
+    if (n == 0 || check_only) return ok();
     if (!workspace || workspace_bytes < wl.total)
         return fail(CRP_ERR_WORKSPACE, "%s: workspace of %zu bytes needed, %zu given", fn, wl.total,
                     workspace ? workspace_bytes : (size_t)0);
@@ -317,12 +342,10 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
-    std::vector<crp::FieldDev> fd(n_fields);
     for (int i = 0; i < n_fields; ++i) fd[i] = make_field_dev(fields[i]);
-    std::vector<crp::ParamsDev> pd(n_params);
     for (int i = 0; i < n_params; ++i) pd[i] = make_params_dev(params[i]);
-    hipError_t e = crp::launch_write_table(ws + wl.fields, fd.data(), fd.size() * sizeof(crp::FieldDev), s);
-    if (e == hipSuccess) e = crp::launch_write_table(ws + wl.params, pd.data(), pd.size() * sizeof(crp::ParamsDev), s);
+    hipError_t e = crp::launch_write_table(ws + wl.fields, fd, size_t(n_fields) * sizeof(crp::FieldDev), s);
+    if (e == hipSuccess) e = crp::launch_write_table(ws + wl.params, pd, size_t(n_params) * sizeof(crp::ParamsDev), s);
     if (e == hipSuccess) e = crp::launch_fill_u64(reinterpret_cast<unsigned long long *>(ws), 0ull, 1, s);
     int32_t *order = nullptr;
     if (e == hipSuccess && t.order_by_rigidity) {
@@ -392,6 +415,10 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
     if (e != hipSuccess) return device_error(e, fn);
     return ok();
 }
+
+}  // namespace crp
+
+extern "C" {
 
 // Threads of an adjoint launch (each keeps a column of replay records).
 static int64_t adjoint_lanes(int64_t n) { return n < 65536 ? ((n + 63) / 64) * 64 : 65536; }
@@ -527,7 +554,7 @@ crp_status crp_graph_destroy(crp_graph *g) {
 crp_status crp_selftest_arith(const double *in, double *out, int64_t n, int32_t op, void *stream) {
     if (n < 0) return fail(CRP_ERR_INVALID, "crp_selftest_arith: n < 0");
     if (n > 0 && (!in || !out)) return fail(CRP_ERR_INVALID, "crp_selftest_arith: null pointer");
-    if (op < 0 || op > 5) return fail(CRP_ERR_INVALID, "crp_selftest_arith: unknown op %d", op);
+    if (op < 0 || op > 6) return fail(CRP_ERR_INVALID, "crp_selftest_arith: unknown op %d", op);
     hipError_t e = crp::launch_selftest(in, out, n, op, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return device_error(e, "crp_selftest_arith");
     return ok();

@@ -64,9 +64,11 @@ struct WsLayout {
     size_t fields, params, order, buckets, total;
 };
 
-inline WsLayout ws_layout(int64_t n, int32_t nf, int32_t np) {
-    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
-    WsLayout w;
+constexpr size_t ws_round_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+constexpr WsLayout ws_layout(int64_t n, int32_t nf, int32_t np) {
+    auto up = ws_round_up;
+    WsLayout w{};
     w.fields = 256;
     w.params = up(w.fields + sizeof(FieldDev) * size_t(nf));
     w.order = up(w.params + sizeof(ParamsDev) * size_t(np));
@@ -143,6 +145,19 @@ inline size_t adjoint_ws_bytes(int64_t n, int32_t K, int64_t lanes) {
     b = up(b + 8 * ADJ_SCRATCH_DOUBLES * size_t(lanes));             // crossing-derivative scratch
     return b;
 }
+
+// crp_propagate's checks and launches (crp_host.cpp), given host staging
+// arrays fd and pd of at least n_fields and n_params descriptors.  fn names
+// the entry point in error messages.  check_only: validate the arguments
+// (everything but the workspace) and return without touching the device.
+crp_status propagate_impl(const char *fn, const crp_field *fields, int32_t n_fields, const crp_params *params,
+                          int32_t n_params, const crp_particles *p, int64_t n, const crp_tape *tape,
+                          int32_t precision, const crp_tuning *tuning, int64_t *counters, void *workspace,
+                          size_t workspace_bytes, void *stream, FieldDev *fd, ParamsDev *pd, bool check_only);
+
+// Sets the thread's last-error message (msg) for a failing status, clears it
+// for CRP_OK; returns st.
+crp_status report(crp_status st, const char *msg);
 
 // Launchers (defined in the .hip files, called by crp_host.cpp).
 hipError_t launch_write_table(void *dst, const void *src, size_t bytes, hipStream_t s);

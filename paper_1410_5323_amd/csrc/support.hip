@@ -114,7 +114,8 @@ __global__ void k_selftest(const double *in, double *out, int64_t n, int op) {
         case 2: r = fma(in[3 * i], in[3 * i + 1], in[3 * i + 2]); break;
         case 3: r = floor(in[i]); break;
         case 4: r = dev::inv_fifth_root(in[i]); break;
-        default: r = 1.0 / sqrt(sqrt(in[i])); break;
+        case 5: r = 1.0 / sqrt(sqrt(in[i])); break;
+        default: r = in[2 * i] / in[2 * i + 1]; break;
     }
     out[i] = r;
 }

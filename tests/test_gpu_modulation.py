@@ -64,7 +64,7 @@ def test_unit_modulation_is_bitwise_neutral(dev, small):
 
 
 @pytest.mark.parametrize("layout,mdtype,cache", [("linear", "f64", 0), ("cell8", "f32", 0), ("cell8", "f64", 1),
-                                                 ("linear", "f32", -1)])
+                                                 ("linear", "f32", -1), ("cell8", "f32", 1), ("linear", "f32", 1)])
 def test_modulated_small_grid_matches_oracle(dev, oracle_mod, small, layout, mdtype, cache):
     torch, crp = dev
     w, B, M, P = small
@@ -145,6 +145,18 @@ def test_mixed_kernel_modulation(dev, oracle_mod, small, prec):
         assert np.array_equal(a[k], b[k]), k
     mod = crp.make_modulation(M.astype(np.float32), 0.25, origin=(-3.0, -3.0, -3.0))
     g = run(mod, pv, "f16")
+    # the cell cache (vector cell and FP32 modulation cell) holds stored
+    # values: the same results bit for bit with it forced on and off
+    for cache in (1, -1):
+        f = crp.make_field(B32, w.spacing, dtype="f16", layout="cell8", modulation=mod)
+        st = crp.particles_to_device(P["pos"], P["dir"], P["energy"], P["charge"])
+        crp.crp_propagate([f], [crp.make_params(**PRM)], st, precision=pv, tuning=crp.make_tuning(cache_cells=cache))
+        torch.cuda.synchronize()
+        r = crp.particles_to_host(st)
+        if cache == 1:
+            c_on = r
+    for k in ("pos", "dir", "length", "status", "n_accepted", "n_rejected", "h_next"):
+        assert np.array_equal(c_on[k], r[k]), k
     ref = run(mod, crp.CRP_PREC_FP64, "f32")
     assert set(np.unique(g["status"])) <= {1, 2}
     defl = lambda r: np.arccos(np.clip(np.sum(r["dir"] * P["dir"], axis=1), -1, 1))  # noqa: E731

@@ -1,0 +1,178 @@
+"""Parity of what the benchmark ships, element by element, through the C ABI.
+
+* The production instance: CELL8 layout, FP32 grid, FP64 stages, the
+  per-lane register cell cache forced on, on a 20,000-nucleus sample of the
+  256^3 workload, against the oracle bit for bit.
+* Stored grid values (section 3.2, regular grids): the device's FP16, BF16,
+  FP32 and FP64 storage read back and compared bit for bit with the host
+  rounding of (value / value_scale), in both layouts, including the wrap
+  copies of LINEAR and the zero padding of CELL8 records.
+* value_scale: a power-of-two scale is exact, so results are bitwise equal
+  to the unscaled grid; a scale of 3.7 against the oracle on the grid of
+  stored values times 3.7 (within the stated gate: the two differ by the
+  rounding of the scaled values).
+* General FP64 division a/b on the device against the host, bit for bit (the
+  kernel divides for the direction norm, the error norm, the step ratio of
+  the event location and kappa = Z K / E).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_common import compare, require_gpu, run_oracle, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+def test_production_instance_with_register_cache(dev, oracle_mod):
+    torch, crp = dev
+    w, B, P = workload(1, n=20000)
+    _say("case: production instance (CELL8, FP32, register cell cache on), 20000 nuclei")
+    f = crp.make_field(B, w.spacing, dtype="f32", layout="cell8")
+    prm = crp.make_params(w.tol, w.h_min, w.h_max, obs_radius=w.obs_radius, l_max=w.max_length)
+    st = crp.particles_to_device(P["pos"], P["dir"], P["energy"], P["charge"])
+    cnt = torch.zeros(crp.NCOUNTERS, dtype=torch.int64, device="cuda")
+    crp.crp_propagate([f], [prm], st, tuning=crp.make_tuning(blocks_per_cu=2, cache_cells=1), counters=cnt)
+    torch.cuda.synchronize()
+    g = crp.particles_to_host(st)
+    c = cnt.cpu().numpy()
+    # the cache was in use: fewer than 6 cell loads per evaluation
+    assert c[6] < 0.6 * 6 * c[0], (c[6], c[0])
+    o = run_oracle(oracle_mod, B, w.spacing, w, P)
+    r = compare(g, o, "production instance")
+    assert c[1] == o["counters"]["accepted"] and c[2] == o["counters"]["rejected"]
+    _say(f"  {r}, cache hit rate {1 - c[6] / (6 * c[0]):.3f}")
+
+
+def _host_stored(B, dtype, scale):
+    """Host rounding of the stored values: value / scale in FP64, then to the
+    storage type by round to nearest even (16-bit types from the FP32 value).
+    Returns raw bits as an unsigned integer array of the storage width."""
+    v = np.asarray(B, np.float64) / scale
+    if dtype == "f64":
+        return v.view(np.uint64)
+    v32 = v.astype(np.float32)
+    if dtype == "f32":
+        return v32.view(np.uint32)
+    if dtype == "f16":
+        return v32.astype(np.float16).view(np.uint16)
+    b = v32.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) >> 16
+    return (b & 0xFFFF).astype(np.uint16)
+
+
+def _layout(raw, layout):
+    """The device layout of per-node raw values raw[n0][n1][n2][3]."""
+    n0, n1, n2, _ = raw.shape
+    if layout == "linear":
+        idx = [np.arange(m + 1) % m for m in (n0, n1, n2)]
+        return raw[idx[0]][:, idx[1]][:, :, idx[2]].reshape(-1)
+    rec = np.zeros((n0, n1, n2, 32), raw.dtype)
+    for dz in range(2):
+        for dy in range(2):
+            for dx in range(2):
+                corner = (dz * 2 + dy) * 2 + dx
+                sh = np.roll(np.roll(np.roll(raw, -dx, 0), -dy, 1), -dz, 2)
+                rec[..., 3 * corner:3 * corner + 3] = sh
+    return rec.reshape(-1)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16", "f32", "f64"])
+@pytest.mark.parametrize("layout", ["linear", "cell8"])
+@pytest.mark.parametrize("scale", [1.0, 0.125, 3.7])
+def test_stored_values_bitwise(dev, dtype, layout, scale):
+    torch, crp = dev
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((6, 5, 7, 3)) * np.array([1.0, 3e-3, 7e4])  # non-cubic, FP16 range edges
+    B[0, 0, 0] = [65504.0 * scale * 1.5, -1e-9, 0.0]  # beyond FP16's range; below its subnormals
+    if dtype in ("f64", "f32") and scale != 1.0:
+        pytest.skip("value_scale is meant for 16-bit storage")
+    for src in (B, B.astype(np.float32)):
+        f = crp.make_field(src, 0.1, dtype=dtype, layout=layout, value_scale=scale)
+        torch.cuda.synchronize()
+        want = _layout(_host_stored(src.astype(np.float64), dtype, scale), layout)
+        got = f.storage.cpu().numpy().view(want.dtype)
+        assert got.shape == want.shape
+        bad = np.count_nonzero(got != want)
+        assert bad == 0, f"{dtype} {layout} scale {scale} src {src.dtype}: {bad} stored values differ"
+
+
+def test_value_scale_power_of_two_bitwise(dev, oracle_mod):
+    torch, crp = dev
+    w, B, P = workload(0)
+    _say("case: value_scale 2^-4 (F32 storage of B * 16) against the unscaled grid")
+    sel = slice(0, 500)
+    prm = crp.make_params(w.tol, w.h_min, w.h_max, obs_radius=2.0, l_max=20.0)
+    out = []
+    for scale in (1.0, 0.0625):
+        f = crp.make_field(B, w.spacing, dtype="f32", value_scale=scale)
+        st = crp.particles_to_device(P["pos"][sel], P["dir"][sel], P["energy"][sel], P["charge"][sel])
+        crp.crp_propagate([f], [prm], st)
+        torch.cuda.synchronize()
+        out.append(crp.particles_to_host(st))
+    for k in ("pos", "dir", "length", "h_next", "status", "n_accepted", "n_rejected"):
+        assert np.array_equal(out[0][k], out[1][k]), k
+    o = run_oracle(oracle_mod, B.astype(np.float32), w.spacing, w, P, sel=sel, radius=2.0, l_max=20.0)
+    compare(out[1], o, "scaled 2^-4")
+
+
+def test_value_scale_non_power_of_two(dev, oracle_mod):
+    """Stored values v = f32(B / 3.7); the device interpolates v and multiplies
+    by 3.7, the oracle interpolates the FP64 products 3.7 v.  The two differ by
+    a rounding per node, so the comparison is over the first four accepted
+    steps, within the stated gate, with every step count equal."""
+    torch, crp = dev
+    w, B, P = workload(0)
+    _say("case: value_scale 3.7 against the oracle on the scaled stored grid")
+    scale = 3.7
+    sel = slice(0, 500)
+    f = crp.make_field(B, w.spacing, dtype="f32", value_scale=scale)
+    stored = (B / scale).astype(np.float32)
+    grid = stored.astype(np.float64) * scale
+    prm = crp.make_params(w.tol, w.h_min, w.h_max, l_max=50.0, max_steps=4)
+    st = crp.particles_to_device(P["pos"][sel], P["dir"][sel], P["energy"][sel], P["charge"][sel])
+    crp.crp_propagate([f], [prm], st)
+    torch.cuda.synchronize()
+    g = crp.particles_to_host(st)
+    o = run_oracle(oracle_mod, grid, w.spacing, w, P, sel=sel, l_max=50.0, max_steps=4)
+    assert np.all(g["status"] == 3)
+    # the stated gate (direction <= 1e-6 rad, position <= 1e-9 relative, equal
+    # step counts); the measured differences are ~1e-11
+    r = compare(g, o, "value_scale 3.7", require_bitwise=False)
+    _say(f"  {r}")
+    # and the scale is applied once: without it the deflections differ at first order
+    f1 = crp.make_field(stored, w.spacing, dtype="f32")
+    st1 = crp.particles_to_device(P["pos"][sel], P["dir"][sel], P["energy"][sel], P["charge"][sel])
+    crp.crp_propagate([f1], [prm], st1)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(crp.particles_to_host(st1)["dir"] - o["dir"])) > 1e-6
+
+
+def test_device_division_matches_host(dev):
+    torch, crp = dev
+    rng = np.random.default_rng(6)
+    n = 400000
+    a = np.concatenate([10.0 ** rng.uniform(-300, 300, n // 2) * rng.choice([-1, 1], n // 2),
+                        rng.uniform(-4, 4, n // 2)])
+    b = np.concatenate([10.0 ** rng.uniform(-300, 300, n // 2), rng.uniform(1e-3, 4, n // 2) * rng.choice([-1, 1], n // 2)])
+    extra = np.array([[1.0, 3.0], [2.0, 3.0], [5e-324, 2.0], [1.7e308, 0.5], [1.0, 1e-310], [-0.0, 1.0],
+                      [7.0, 7.0], [1e-300, 1e300]])
+    pairs = np.concatenate([np.stack([a, b], axis=1), extra])
+    inp = torch.from_numpy(pairs.reshape(-1).copy()).cuda()
+    out = torch.empty(len(pairs), dtype=torch.float64, device="cuda")
+    crp.crp_selftest_arith(inp, out, 6)
+    torch.cuda.synchronize()
+    ref = pairs[:, 0] / pairs[:, 1]
+    got = out.cpu().numpy()
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64)), np.count_nonzero(got != ref)
