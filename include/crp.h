@@ -239,6 +239,27 @@ crp_status crp_propagate(const crp_field *fields, int32_t n_fields, const crp_pa
                          int32_t precision, const crp_tuning *tuning, int64_t *counters, void *workspace,
                          size_t workspace_bytes, void *stream);
 
+/* crp_propagate for callers that cannot allocate device memory: code under
+ * hipGraph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, behaviour and results as crp_propagate, bit for bit, except
+ * that there is no workspace argument: the library keeps one fixed scratch
+ * array per GPU in its device image (crp_noalloc_scratch_bytes() bytes, about
+ * 17 MB, held until the process ends) and uses it as the workspace.  The
+ * call allocates nothing.  Limits: n <= CRP_NOALLOC_MAX_PARTICLES, n_fields
+ * <= CRP_NOALLOC_MAX_FIELDS, n_params <= CRP_NOALLOC_MAX_PARAMS (else
+ * CRP_ERR_INVALID before anything is enqueued).  Each call clears what must
+ * start at zero and rewrites the rest, so no call depends on an earlier one;
+ * but all calls on one GPU share its array, so calls that overlap on one GPU
+ * (different streams or host threads without ordering) race and must not be
+ * made. */
+#define CRP_NOALLOC_MAX_PARTICLES 4194304
+#define CRP_NOALLOC_MAX_FIELDS 64
+#define CRP_NOALLOC_MAX_PARAMS 64
+size_t crp_noalloc_scratch_bytes(void);
+crp_status crp_propagate_noalloc(const crp_field *fields, int32_t n_fields, const crp_params *params,
+                                 int32_t n_params, const crp_particles *p, int64_t n, const crp_tape *tape,
+                                 int32_t precision, const crp_tuning *tuning, int64_t *counters, void *stream);
+
 /* Workspace for crp_propagate_adjoint: n particles, checkpoint interval K. */
 size_t crp_adjoint_workspace_bytes(int64_t n, int32_t every_k);
 

@@ -96,6 +96,12 @@ def lib():
         L.crp_propagate.argtypes = [C.POINTER(crp_field), C.c_int32, C.POINTER(crp_params), C.c_int32,
                                     C.POINTER(crp_particles), C.c_int64, C.POINTER(crp_tape), C.c_int32,
                                     C.POINTER(crp_tuning), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.crp_propagate_noalloc.argtypes = [C.POINTER(crp_field), C.c_int32, C.POINTER(crp_params), C.c_int32,
+                                            C.POINTER(crp_particles), C.c_int64, C.POINTER(crp_tape), C.c_int32,
+                                            C.POINTER(crp_tuning), C.c_void_p, C.c_void_p]
+        L.crp_propagate_noalloc.restype = C.c_int
+        L.crp_noalloc_scratch_bytes.argtypes = []
+        L.crp_noalloc_scratch_bytes.restype = C.c_size_t
         L.crp_adjoint_workspace_bytes.argtypes = [C.c_int64, C.c_int32]
         L.crp_adjoint_workspace_bytes.restype = C.c_size_t
         L.crp_propagate_adjoint.argtypes = [C.POINTER(crp_field), C.POINTER(crp_params), C.POINTER(crp_particles),
@@ -242,6 +248,20 @@ def crp_propagate(fields, params, particles: dict, precision=CRP_PREC_FP64, tuni
                                int(precision), tun, _ptr(counters), _ptr(workspace), workspace.numel(),
                                _stream_handle(stream)))
     return particles
+
+
+def crp_propagate_noalloc(fields, params, particles: dict, precision=CRP_PREC_FP64, tuning=None,
+                          counters=None, stream=None, tape=None):
+    """crp_propagate without a workspace: the library's per-GPU scratch array
+    is used instead (for callers that cannot allocate device memory)."""
+    farr, nf, parr, np_, ps, n, tun = _marshal(fields, params, particles, tuning)
+    _check(lib().crp_propagate_noalloc(farr, nf, parr, np_, C.byref(ps), n, C.byref(tape.desc) if tape else None,
+                                       int(precision), tun, _ptr(counters), _stream_handle(stream)))
+    return particles
+
+
+def crp_noalloc_scratch_bytes() -> int:
+    return int(lib().crp_noalloc_scratch_bytes())
 
 
 def crp_adjoint_workspace_bytes(n: int, every_k: int) -> int:

@@ -319,3 +319,41 @@ def test_lens_entry_points_reject_bad_arguments(crp):
     assert L.crp_lens_apply(64, 0x1000, 0x2000, 0x3000, 10, 0x4000, 0x5000, 0, None) == crp.CRP_ERR_INVALID
     assert L.crp_lens_apply(64, 0x1000, 0x2000, 0x3000, 10, 0x4000, 0x5000, 5000, None) == crp.CRP_ERR_INVALID
     assert L.crp_lens_apply(64, 0x1000, None, 0x3000, 10, 0x4000, 0x5000, 1, None) == crp.CRP_ERR_INVALID
+
+
+def test_noalloc_entry_point_checks_without_device(crp):
+    """The allocation-free variant validates every argument before it touches
+    the device, and refuses sizes beyond its fixed scratch array."""
+    L = crp.lib()
+    assert crp.crp_noalloc_scratch_bytes() >= crp.crp_workspace_bytes(4194304, 64, 64)
+    f = _field(crp)
+    f.data = 0x1000
+    farr = (crp.crp_field * 1)(f)
+    parr = (crp.crp_params * 1)(crp.make_params(1e-4, 0.01, 1.0, l_max=10.0))
+    parts = crp.crp_particles(**{k: 0x2000 for k in crp._PARTICLE_FIELDS})
+
+    def call(fa, nf, pa, np_, n, prec=0):
+        return L.crp_propagate_noalloc(fa, nf, pa, np_, C.byref(parts), n, None, prec, None, None, None)
+
+    assert call(farr, 1, parr, 1, 4194305) == crp.CRP_ERR_INVALID
+    assert "CRP_NOALLOC_MAX_PARTICLES" in crp.crp_last_error()
+    many = (crp.crp_params * 65)(*([crp.make_params(1e-4, 0.01, 1.0, l_max=10.0)] * 65))
+    assert call(farr, 1, many, 65, 10) == crp.CRP_ERR_INVALID
+    assert call(farr, 1, parr, 1, -1) == crp.CRP_ERR_INVALID
+    bad = (crp.crp_params * 1)(crp.make_params(0.0, 0.01, 1.0, l_max=10.0))
+    assert call(farr, 1, bad, 1, 10) == crp.CRP_ERR_INVALID
+    assert call(farr, 1, parr, 1, 10, prec=9) == crp.CRP_ERR_INVALID
+    assert call(farr, 1, parr, 1, 0) == crp.CRP_OK
+
+
+def test_noalloc_valid_call_without_device_reports_device_error(crp):
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    f = _field(crp)
+    f.data = 0x1000
+    parts = crp.crp_particles(**{k: 0x2000 for k in crp._PARTICLE_FIELDS})
+    rc = crp.lib().crp_propagate_noalloc((crp.crp_field * 1)(f), 1,
+                                         (crp.crp_params * 1)(crp.make_params(1e-4, 0.01, 1.0, l_max=1.0)), 1,
+                                         C.byref(parts), 10, None, 0, None, None, None)
+    assert rc == crp.CRP_ERR_DEVICE
