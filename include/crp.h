@@ -68,7 +68,7 @@ enum {
     CRP_ST_MAX_LENGTH = 2,  /* trajectory length reached l_max exactly */
     CRP_ST_MAX_STEPS = 3,   /* accepted-step budget of this call used up */
     CRP_ST_NONFINITE = 4,   /* the error estimate or the event function was not finite */
-    CRP_ST_CANCELLED = 5,   /* stopped by the cancel flag */
+    CRP_ST_CANCELLED = 5,   /* stopped by the caller's cancel word (crp_tuning.cancel) */
     CRP_ST_BAD_INPUT = 6    /* E <= 0, zero or non-finite direction or position, bad h_next */
 };
 
@@ -168,10 +168,15 @@ typedef struct {
 } crp_tape;
 
 enum {
-    CRP_TAPE_EVENT = 1,       /* ended by a located sphere crossing */
-    CRP_TAPE_OVERFLOW = 2,    /* the record pool ran out: no adjoint */
-    CRP_TAPE_FRESH = 4,       /* started fresh (direction normalised on entry) */
-    CRP_TAPE_COMPLETE = 8     /* ended ARRIVED or MAX_LENGTH in this call */
+    CRP_TAPE_EVENT = 1,        /* ended by a located sphere crossing */
+    CRP_TAPE_OVERFLOW = 2,     /* the record pool ran out: no adjoint */
+    CRP_TAPE_FRESH = 4,        /* started fresh (direction normalised on entry) */
+    CRP_TAPE_COMPLETE = 8,     /* ended ARRIVED or MAX_LENGTH in this call */
+    CRP_TAPE_MIRRORED = 16,    /* was mirrored by a reflective box at least once (its derivative
+                                  is that of the replayed map; see crp_propagate_adjoint) */
+    CRP_TAPE_GRAD_OVERFLOW = 32 /* set by crp_propagate_adjoint: the particle's cotangent left the
+                                   FP64 range (a chaotic trajectory); its grid contributions from
+                                   that point on were left out of grad_field */
 };
 
 /* Launch configuration; NULL selects the defaults. */
@@ -184,7 +189,16 @@ typedef struct {
                                  per-particle groups) and skip repeated loads: 1 on, -1 off,
                                  0 automatic (default: on for LINEAR; for CELL8 on with more
                                  than 2048 particles per compute unit) */
-    int32_t reserved[3];
+    int32_t reserved;
+    const int32_t *cancel;    /* NULL, or a [dev] word the caller may set nonzero while the call
+                                 runs (from another stream, or mapped host memory) to stop it
+                                 early: read by every wavefront once every 64 loop iterations;
+                                 once seen, no further particle is started (those stay ACTIVE and
+                                 untouched), a particle between accepted steps stops after its
+                                 next accepted step with status CRP_ST_CANCELLED and its state
+                                 saved, and one locating its sphere crossing finishes it.  Set
+                                 CANCELLED back to ACTIVE (and the word to 0) to resume: the
+                                 result is bit-identical to an uninterrupted call. */
 } crp_tuning;
 
 /* Counters accumulated by crp_propagate into an optional [dev] int64 array. */
@@ -297,6 +311,13 @@ size_t crp_adjoint_workspace_bytes(int64_t n, int32_t every_k);
  * differentiated through both factors: grad_field is the gradient with
  * respect to the vector grid's values (its cotangent carries the factor m);
  * the modulation grid's own values get none.
+ * Chaotic trajectories amplify cotangents exponentially; a contribution to
+ * grad_field that is not finite is left out (so grad_field stays finite), and
+ * a particle with such a contribution or a non-finite gradient gets
+ * CRP_TAPE_GRAD_OVERFLOW in its tape flags (finals[4 i + 3], written by this
+ * call).  Its grid contributions are then incomplete: to obtain grad_field
+ * of the other particles exactly, zero the flagged particles' cotangents and
+ * call again (the autograd wrapper does this).
  * workspace: [dev] crp_adjoint_workspace_bytes(n, K) bytes, 256-aligned. */
 crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *params, const crp_particles *initial,
                                  int64_t n, const crp_tape *tape, const double *gbar_dir, const double *gbar_time,
@@ -338,6 +359,19 @@ crp_status crp_selftest_arith(const double *in, double *out, int64_t n, int32_t 
 crp_status crp_bench_gather(const crp_field *f, int64_t lanes, int64_t lookups_per_lane, double spread,
                             uint64_t seed, double *sink, void *stream);
 
+/* Replayed-lookup microbenchmark (measurement only): lanes threads each walk
+ * a recorded stream of steps rec ([dev] FP64, layout [step][7][lane]: x, y,
+ * z, ux, uy, uz of the state before the step and the step size h) and look
+ * the field up at the six Cash-Karp stage points x + c_i h u of every step
+ * (c = 0, 1/5, 3/10, 3/5, 1, 7/8), with the propagation kernel's lookup and,
+ * if cache_cells = 1, its per-lane cell cache (section 3.2: the lookup cost
+ * of regular grids).  The lookups do not depend on one another: the
+ * achievable lookup rate for the cell sequences of real trajectories.  sink:
+ * [dev] double[lanes] checksums; misses: [dev] int64[lanes] lookups that read
+ * grid memory, or NULL.  F64 or F32 grids. */
+crp_status crp_bench_gather_replay(const crp_field *f, const double *rec, int64_t lanes, int64_t steps,
+                                   int32_t cache_cells, double *sink, int64_t *misses, void *stream);
+
 /* Streaming microbenchmark (measurement only): reads bytes of src ([dev],
  * 16-byte aligned, bytes a multiple of 16) with blocks x 256 threads; copies
  * them to dst ([dev]) when dst is not NULL, else writes per-thread sums to
@@ -376,8 +410,9 @@ size_t crp_lens_workspace_bytes(int32_t nside, int64_t n);
  *        pixel col[e]) / (launches of row i), FP64 ratio rounded to FP32,
  *        columns ascending within a row;
  *   nnz: [host] out, the number of entries (the call waits for the stream).
- * 1 <= nside <= 1024; a row with more than 4096 launches gives
- * CRP_ERR_UNSUPPORTED, a row index out of range CRP_ERR_INVALID (both found
+ * 1 <= nside <= 1024; any number of launches per row; a row whose launches
+ * reach more than 4096 distinct border pixels gives CRP_ERR_UNSUPPORTED, a
+ * row index out of range CRP_ERR_INVALID (both found
  * on the device, reported after the wait). */
 crp_status crp_lens_build(int32_t nside, const int32_t *row, const double *ux, const double *uy, const double *uz,
                           const int32_t *status, int64_t n, int64_t *row_ptr, int32_t *col, float *val,

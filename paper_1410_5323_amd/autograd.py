@@ -10,7 +10,13 @@ the output energy equals the input one) and the grid values.
 
 The derivative is that of the replayed map: the accepted step sizes of the
 forward run are held fixed and the sphere crossing of the last step is
-differentiated through its defining equation.  The forward records a
+differentiated through its defining equation.  Chaotic trajectories can
+amplify a cotangent beyond the FP64 range: such particles keep their
+non-finite gradients, and the grid gradient is taken over the other
+particles (a second adjoint pass with the overflowed particles' cotangents
+zeroed).  The grid gradient is returned in the grid's dtype: for an FP32 grid
+the finite but huge gradients of long chaotic trajectories (1e38 and more)
+become infinite there.  The forward records a
 checkpoint every ``every_k`` accepted steps into a pool of records (run a
 second time only if the pool was too small).  The backward pass replays each
 segment from its checkpoint on the GPU and sweeps it in reverse.
@@ -77,6 +83,19 @@ class PropagateFunction(torch.autograd.Function):
         grad_field = torch.zeros(ctx.grid_shape, dtype=torch.float64, device=dev)
         crp.crp_propagate_adjoint(ctx.field, ctx.params, ctx.init, ctx.tape, gd, gt, grad_u0, grad_field,
                                   grad_x0=grad_x0, gbar_energy=ge, grad_energy=grad_e)
+        over = (ctx.tape.flags() & crp.CRP_TAPE_GRAD_OVERFLOW) != 0
+        if ctx.needs_input_grad[1] and bool(over.any()):
+            # chaotic particles whose cotangent left the FP64 range: the grid
+            # gradient is taken over the other particles only (their own
+            # gradients stay as computed, not finite)
+            keep = (~over).to(torch.float64)
+            grad_field.zero_()
+            crp.crp_propagate_adjoint(ctx.field, ctx.params, ctx.init, ctx.tape, gd * keep[:, None],
+                                      None if gt is None else gt * keep, torch.empty_like(grad_u0), grad_field,
+                                      grad_x0=torch.empty_like(grad_x0),
+                                      gbar_energy=None if ge is None else ge * keep,
+                                      grad_energy=torch.empty_like(grad_e))
+        ctx.overflowed = over
         gu = grad_u0 if ctx.needs_input_grad[0] else None
         gg = grad_field.to(ctx.grid_dtype) if ctx.needs_input_grad[1] else None
         gx = grad_x0 if ctx.needs_input_grad[2] else None

@@ -66,12 +66,13 @@ class crp_tape(C.Structure):
 
 
 CRP_TAPE_EVENT, CRP_TAPE_OVERFLOW, CRP_TAPE_FRESH, CRP_TAPE_COMPLETE = 1, 2, 4, 8
+CRP_TAPE_MIRRORED, CRP_TAPE_GRAD_OVERFLOW = 16, 32
 
 
 class crp_tuning(C.Structure):
     _fields_ = [("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("refill_threshold", C.c_int32), ("order_by_rigidity", C.c_int32),
-                ("cache_cells", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("cache_cells", C.c_int32), ("reserved", C.c_int32), ("cancel", C.c_void_p)]
 
 
 _lib = None
@@ -114,6 +115,9 @@ def lib():
                                        C.c_void_p, C.c_void_p]
         L.crp_bench_stream.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_int32, C.c_void_p]
         L.crp_bench_gather.restype = C.c_int
+        L.crp_bench_gather_replay.argtypes = [C.POINTER(crp_field), C.c_void_p, C.c_int64, C.c_int64, C.c_int32,
+                                              C.c_void_p, C.c_void_p, C.c_void_p]
+        L.crp_bench_gather_replay.restype = C.c_int
         L.crp_bench_stream.restype = C.c_int
         L.crp_graph_create.argtypes = [C.POINTER(crp_field), C.c_int32, C.POINTER(crp_params), C.c_int32,
                                        C.POINTER(crp_particles), C.c_int64, C.c_int32, C.POINTER(crp_tuning),
@@ -420,6 +424,11 @@ def crp_bench_gather(field, lanes: int, lookups_per_lane: int, spread: float, se
                                   int(seed), _ptr(sink), _stream_handle(stream)))
 
 
+def crp_bench_gather_replay(field, rec, lanes: int, steps: int, cache: bool, sink, misses=None, stream=None):
+    _check(lib().crp_bench_gather_replay(C.byref(field.desc), _ptr(rec), int(lanes), int(steps), 1 if cache else 0,
+                                         _ptr(sink), _ptr(misses), _stream_handle(stream)))
+
+
 def crp_bench_stream(src, dst, nbytes: int, sink, blocks: int, stream=None):
     _check(lib().crp_bench_stream(_ptr(src), _ptr(dst), int(nbytes), _ptr(sink), int(blocks),
                                   _stream_handle(stream)))
@@ -519,8 +528,11 @@ def make_params(tol, h_min, h_max, obs_radius=0.0, l_max=math.inf, obs_center=(0
 
 
 def make_tuning(block_size=256, blocks_per_cu=4, refill_threshold=32, order_by_rigidity=1,
-                cache_cells=0) -> crp_tuning:
-    return crp_tuning(block_size, blocks_per_cu, refill_threshold, order_by_rigidity, cache_cells)
+                cache_cells=0, cancel=None) -> crp_tuning:
+    """Launch configuration; ``cancel`` is an optional device int32 tensor (one
+    element) whose becoming nonzero stops the call early (resumable)."""
+    return crp_tuning(block_size, blocks_per_cu, refill_threshold, order_by_rigidity, cache_cells, 0,
+                      None if cancel is None else cancel.data_ptr())
 
 
 def particles_to_device(pos, dir, energy, charge, mass=None, param_index=None, device="cuda",

@@ -59,6 +59,39 @@ __global__ void __launch_bounds__(256) k_gather_bench(FieldDev F, int64_t lookup
     sink[tid] = acc;
 }
 
+// Replayed lookups: each lane walks a recorded stream of accepted steps
+// (state x, u and step size h, layout [step][7][lane]) and looks the field up
+// at the six Cash-Karp stage points of each step along the straight line,
+// x + c_i h u, with the propagation kernel's lookup and (CACHE) its per-lane
+// cell cache.  The lookups do not depend on one another, so many are in
+// flight: the achievable lookup rate for the cell sequences a real run
+// visits, including the locality the cell cache exploits.
+template <class T, int LAYOUT, bool CACHE>
+__global__ void __launch_bounds__(256) k_gather_replay(FieldDev F, const double *rec, int64_t lanes, int64_t steps,
+                                                       double *sink, int64_t *misses) {
+    const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (lane >= lanes) return;
+    constexpr double C[6] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 3.0 / 5.0, 1.0, 7.0 / 8.0};
+    dev::CellCache<T> cache;
+    dev::cache_reset(cache);
+    double acc = 0.0;
+    for (int64_t s = 0; s < steps; ++s) {
+        const double *r = rec + s * 7 * lanes + lane;
+        const double x[3] = {r[0], r[lanes], r[2 * lanes]};
+        const double u[3] = {r[3 * lanes], r[4 * lanes], r[5 * lanes]};
+        const double h = r[6 * lanes];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const double X[3] = {fma(C[i] * h, u[0], x[0]), fma(C[i] * h, u[1], x[1]), fma(C[i] * h, u[2], x[2])};
+            double B[3];
+            dev::lookup_cached<T, LAYOUT, CACHE>(F, 0, X, B, cache);
+            acc += B[0] + B[1] + B[2];
+        }
+    }
+    sink[lane] = acc;
+    if (misses) misses[lane] = cache.misses;
+}
+
 __global__ void __launch_bounds__(256) k_stream_read(const float4 *src, uint64_t n4, double *sink) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     float a = 0.f;
@@ -87,7 +120,38 @@ hipError_t gather_t(const FieldDev &F, int64_t lanes, int64_t lookups, double sp
     return hipGetLastError();
 }
 
+template <class T>
+hipError_t replay_t(const FieldDev &F, const double *rec, int64_t lanes, int64_t steps, bool cache, double *sink,
+                    int64_t *misses, hipStream_t s) {
+    const unsigned blocks = (unsigned)((lanes + 255) / 256);
+    if (F.layout == CRP_LAYOUT_CELL8) {
+        if (cache)
+            hipLaunchKernelGGL((k_gather_replay<T, CRP_LAYOUT_CELL8, true>), dim3(blocks), dim3(256), 0, s, F, rec,
+                               lanes, steps, sink, misses);
+        else
+            hipLaunchKernelGGL((k_gather_replay<T, CRP_LAYOUT_CELL8, false>), dim3(blocks), dim3(256), 0, s, F, rec,
+                               lanes, steps, sink, misses);
+    } else {
+        if (cache)
+            hipLaunchKernelGGL((k_gather_replay<T, CRP_LAYOUT_LINEAR, true>), dim3(blocks), dim3(256), 0, s, F, rec,
+                               lanes, steps, sink, misses);
+        else
+            hipLaunchKernelGGL((k_gather_replay<T, CRP_LAYOUT_LINEAR, false>), dim3(blocks), dim3(256), 0, s, F, rec,
+                               lanes, steps, sink, misses);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_gather_replay(const FieldDev &F, const double *rec, int64_t lanes, int64_t steps, bool cache,
+                                double *sink, int64_t *misses, hipStream_t s) {
+    switch (F.dtype) {
+        case CRP_F64: return replay_t<double>(F, rec, lanes, steps, cache, sink, misses, s);
+        case CRP_F32: return replay_t<float>(F, rec, lanes, steps, cache, sink, misses, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_gather_bench(const FieldDev &F, int64_t lanes, int64_t lookups, double spread, uint32_t seed,
                                double *sink, hipStream_t s) {

@@ -319,7 +319,7 @@ crp_status propagate_impl(const char *fn, const crp_field *fields, int32_t n_fie
         if (n > 0 && (!tape->head || !tape->finals || !tape->checkpoints || !tape->links))
             return fail(CRP_ERR_INVALID, "%s: tape arrays must not be null", fn);
     }
-    crp_tuning t = {256, 4, 32, 1, 0, 0, 0, 0};
+    crp_tuning t = {256, 4, 32, 1, 0, 0, nullptr};
     if (tuning) t = *tuning;
     if (t.block_size != 64 && t.block_size != 128 && t.block_size != 256)
         return fail(CRP_ERR_INVALID, "%s: block_size must be 64, 128 or 256", fn);
@@ -384,6 +384,7 @@ crp_status propagate_impl(const char *fn, const crp_field *fields, int32_t n_fie
     a.n_params = n_params;
     a.modulated = modulated ? 1 : 0;
     a.reflective = reflective ? 1 : 0;
+    a.cancel = t.cancel;
     a.tape_ckpt = tape ? tape->checkpoints : nullptr;
     a.tape_link = tape ? tape->links : nullptr;
     a.tape_head = tape ? tape->head : nullptr;
@@ -474,6 +475,7 @@ crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *param
     a.ckpt = tape->checkpoints;
     a.link = tape->links;
     a.fin = tape->finals;
+    a.fin_out = tape->finals;
     a.cap = tape->capacity;
     a.K = tape->every_k;
     a.gbar_dir = gbar_dir;
@@ -572,6 +574,20 @@ crp_status crp_bench_gather(const crp_field *f, int64_t lanes, int64_t lookups_p
     return ok();
 }
 
+crp_status crp_bench_gather_replay(const crp_field *f, const double *rec, int64_t lanes, int64_t steps,
+                                   int32_t cache_cells, double *sink, int64_t *misses, void *stream) {
+    crp_status st = check_field(f, true, "crp_bench_gather_replay");
+    if (st != CRP_OK) return st;
+    if (f->dtype != CRP_F64 && f->dtype != CRP_F32)
+        return fail(CRP_ERR_UNSUPPORTED, "crp_bench_gather_replay: F64 or F32 grids only");
+    if (lanes < 1 || lanes > (int64_t)1 << 30 || steps < 0 || !rec || !sink || (cache_cells != 0 && cache_cells != 1))
+        return fail(CRP_ERR_INVALID, "crp_bench_gather_replay: bad lanes, steps, records, cache flag or sink");
+    hipError_t e = crp::launch_gather_replay(make_field_dev(*f), rec, lanes, steps, cache_cells != 0, sink, misses,
+                                             static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_error(e, "crp_bench_gather_replay");
+    return ok();
+}
+
 crp_status crp_bench_stream(const void *src, void *dst, size_t bytes, double *sink, int32_t blocks, void *stream) {
     if (!src || bytes < 16 || (bytes & 15) || blocks < 1 || blocks > (1 << 20) || (!dst && !sink))
         return fail(CRP_ERR_INVALID, "crp_bench_stream: bad arguments");
@@ -624,7 +640,7 @@ crp_status crp_lens_build(int32_t nside, const int32_t *row, const double *ux, c
     if (e != hipSuccess) return device_error(e, fn);
     *nnz = total;
     if (flag & 1u) return fail(CRP_ERR_INVALID, "%s: a row index is outside [0, npix)", fn);
-    if (flag & 2u) return fail(CRP_ERR_UNSUPPORTED, "%s: a row holds more than 4096 launches", fn);
+    if (flag & 2u) return fail(CRP_ERR_UNSUPPORTED, "%s: a row reaches more than 4096 distinct border pixels", fn);
     return ok();
 }
 

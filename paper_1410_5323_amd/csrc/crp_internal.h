@@ -102,6 +102,7 @@ struct PropArgs {
     int32_t n_params;
     int32_t modulated;               // some field carries a modulation grid
     int32_t reflective;              // some parameter group has a reflective box
+    const int32_t *cancel;           // NULL, or the caller's cancel word (nonzero: stop)
     // The first field and parameter group by value: a launch with one of each
     // reads them from the kernel arguments with scalar loads, which never wait
     // behind the lanes' field gathers as vector loads of the tables would.
@@ -118,6 +119,7 @@ struct AdjArgs {
     const double *ckpt;
     const int64_t *link;
     const double *fin;
+    double *fin_out;                 // the same finals: flags written back (gradient overflow)
     int64_t cap;
     int32_t K;
     int32_t pad_;
@@ -175,6 +177,8 @@ hipError_t launch_upload(const FieldDev &f, const void *src, int src_dtype, void
 hipError_t launch_selftest(const double *in, double *out, int64_t n, int op, hipStream_t s);
 hipError_t launch_gather_bench(const FieldDev &F, int64_t lanes, int64_t lookups, double spread, uint32_t seed,
                                double *sink, hipStream_t s);
+hipError_t launch_gather_replay(const FieldDev &F, const double *rec, int64_t lanes, int64_t steps, bool cache,
+                                double *sink, int64_t *misses, hipStream_t s);
 // Lens construction workspace (byte offsets): device flag, launches per row,
 // cursors, row segment starts, the grouped border pixels and the run-length
 // encoded entries per row segment.

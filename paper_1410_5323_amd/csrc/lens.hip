@@ -9,8 +9,9 @@
 //
 // Construction: a counting sort of the launches by observed pixel (row),
 // then one block per row sorts its border pixels in LDS (bitonic), run-length
-// encodes them into (column, count) pairs and writes count / launches; a scan
-// of the per-row entry counts gives the CSR row pointers.  Application: one
+// encodes them into (column, count) pairs and writes count / launches (a row
+// of more than 4096 launches counts its columns in an LDS hash table
+// instead); a scan of the per-row entry counts gives the CSR row pointers.  Application: one
 // team of lanes per row, lanes split between the row's entries and the
 // vectors, FP64 sums, HBM-bound.
 #include <hip/hip_runtime.h>
@@ -152,12 +153,93 @@ __global__ void __launch_bounds__(256) k_lens_scatter(int32_t nside, const int32
     colbuf[starts[r] + k] = c;
 }
 
-constexpr int ROW_CAP = 4096;  // launches per row sorted in LDS
+constexpr int ROW_CAP = 4096;  // launches per row sorted in LDS; distinct columns of a larger row
+
+// In-place bitonic sort of P (a power of two, <= ROW_CAP) keys in LDS by the
+// block, carrying a value along when val is not null.
+__device__ __forceinline__ void lds_bitonic(int32_t *key, int32_t *val, int P) {
+    const int t = threadIdx.x;
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = t; i < P; i += 256) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int32_t a = key[i], b = key[l];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        key[i] = b;
+                        key[l] = a;
+                        if (val) {
+                            const int32_t va = val[i];
+                            val[i] = val[l];
+                            val[l] = va;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// A row with more than ROW_CAP launches: its border pixels are counted in an
+// LDS hash table of ROW_CAP slots (open addressing, linear probing), whose
+// (column, count) pairs are then sorted by column and written as
+// (column, count / launches).  More than ROW_CAP distinct columns raise flag
+// bit 2 and give the row no entries.
+__device__ void lens_row_counted(const int32_t *colbuf, int64_t s0, int64_t m, int64_t r, int32_t *scol, float *sval,
+                                 uint32_t *nnz_row, uint32_t *flag, int32_t *key, int32_t *cnt) {
+    __shared__ int full;
+    __shared__ int nvalid;
+    const int t = threadIdx.x;
+    for (int i = t; i < ROW_CAP; i += 256) {
+        key[i] = SENTINEL;
+        cnt[i] = 0;
+    }
+    if (t == 0) {
+        full = 0;
+        nvalid = ROW_CAP;
+    }
+    __syncthreads();
+    for (int64_t i = t; i < m; i += 256) {
+        const int32_t c = colbuf[s0 + i];
+        if (c == SENTINEL) continue;  // did not reach the border: denominator only
+        uint32_t slot = ((uint32_t)c * 2654435761u) >> 20;  // 12 bits: ROW_CAP slots
+        int probe = 0;
+        for (; probe < ROW_CAP; ++probe, slot = (slot + 1) & (ROW_CAP - 1)) {
+            const int32_t old = atomicCAS(&key[slot], SENTINEL, c);
+            if (old == SENTINEL || old == c) {
+                atomicAdd(&cnt[slot], 1);
+                break;
+            }
+        }
+        if (probe == ROW_CAP) full = 1;
+    }
+    __syncthreads();
+    if (full) {
+        if (t == 0) {
+            atomicOr(flag, 2u);
+            nnz_row[r] = 0;
+        }
+        return;
+    }
+    lds_bitonic(key, cnt, ROW_CAP);
+    // the occupied slots now lead, in ascending column order
+    for (int i = t; i < ROW_CAP; i += 256)
+        if (key[i] != SENTINEL && (i + 1 == ROW_CAP || key[i + 1] == SENTINEL)) nvalid = i + 1;
+    __syncthreads();
+    const int total = key[0] == SENTINEL ? 0 : nvalid;
+    for (int q = t; q < total; q += 256) {
+        scol[s0 + q] = key[q];
+        sval[s0 + q] = (float)((double)cnt[q] / (double)m);
+    }
+    if (t == 0) nnz_row[r] = (uint32_t)total;
+}
 
 // One block per row: bitonic sort of the row's border pixels in LDS, then
 // run-length encoding into (column, count / launches), written at the row's
 // segment start; the number of entries goes to nnz_row.  A row with more
-// than ROW_CAP launches raises flag bit 2 and gets no entries.
+// than ROW_CAP launches is counted in an LDS hash table instead.
 __global__ void __launch_bounds__(256) k_lens_rows(const int32_t *colbuf, const int64_t *starts, int64_t npix,
                                                    int32_t *scol, float *sval, uint32_t *nnz_row, uint32_t *flag) {
     __shared__ int32_t key[ROW_CAP];
@@ -168,10 +250,7 @@ __global__ void __launch_bounds__(256) k_lens_rows(const int32_t *colbuf, const 
     const int64_t s0 = starts[r];
     const int64_t m64 = starts[r + 1] - s0;
     if (m64 > ROW_CAP) {
-        if (t == 0) {
-            atomicOr(flag, 2u);
-            nnz_row[r] = 0;
-        }
+        lens_row_counted(colbuf, s0, m64, r, scol, sval, nnz_row, flag, key, pos);
         return;
     }
     const int m = (int)m64;
@@ -183,22 +262,7 @@ __global__ void __launch_bounds__(256) k_lens_rows(const int32_t *colbuf, const 
     while (P < m) P <<= 1;
     for (int i = t; i < P; i += 256) key[i] = i < m ? colbuf[s0 + i] : SENTINEL;
     __syncthreads();
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = t; i < P; i += 256) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const int32_t a = key[i], b = key[l];
-                    const bool up = (i & k) == 0;
-                    if ((a > b) == up) {
-                        key[i] = b;
-                        key[l] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
+    lds_bitonic(key, nullptr, P);
     // heads of runs among the valid keys; each thread owns a contiguous chunk
     const int chunk = (P + 255) / 256;
     const int b0 = t * chunk;

@@ -162,6 +162,9 @@ __device__ __forceinline__ void event_next(const ParamsDev &P, Lane &s, EventLDS
     }
 }
 
+// The cancel flag is read once every CANCEL_POLL loop iterations of a wavefront.
+constexpr unsigned int CANCEL_POLL = 64;
+
 // Per-iteration outcome bits of a lane; the wavefront sums them with ballots
 // into wave-uniform (scalar) counters.
 enum { F_EVAL = 1, F_ACC = 2, F_REJ = 4, F_EVENT = 8, F_FLOOR = 16 };
@@ -243,7 +246,7 @@ __device__ __forceinline__ bool start(const PropArgs &args, int64_t p, Lane &s) 
 // particle ended (its result already stored).
 template <class T, int LAYOUT, bool MULTI, bool CACHE, bool TAPE, bool MOD, bool RFL>
 __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, CellCache<T, MULTI> &cache, EventLDS &e,
-                                       int &flags) {
+                                       int &flags, bool cancel) {
     const int t = threadIdx.x;
     // per-particle groups: the lane's descriptors, read from the tables once
     // per iteration into registers (the lanes of a wavefront may differ)
@@ -318,7 +321,7 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
         s.y[3] = y5[3] / un;
         s.y[4] = y5[4] / un;
         s.y[5] = y5[5] / un;
-        if (RFL && P.reflect_on) reflect(P, s.y);
+        if (RFL && P.reflect_on && reflect(P, s.y) && TAPE) s.tflags |= CRP_TAPE_MIRRORED;
         s.L = Lnew;
         if (P.lmax_on && s.L >= P.l_max) {
             store(P, p, s, s.hctrl, CRP_ST_MAX_LENGTH);
@@ -329,6 +332,11 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane &s, Ce
             store(P, p, s, s.hctrl, CRP_ST_MAX_STEPS);
             if (TAPE) tape_final(a, p, s, 0.0, 0);
             return CRP_ST_MAX_STEPS;
+        }
+        if (cancel) {  // the caller's cancel flag: stop here, resumable like a used-up budget
+            store(P, p, s, s.hctrl, CRP_ST_CANCELLED);
+            if (TAPE) tape_final(a, p, s, 0.0, 0);
+            return CRP_ST_CANCELLED;
         }
         if (TAPE && s.dacc % a.tape_k == 0) tape_checkpoint(a, s);
         bid<RFL>(P, s);
@@ -397,8 +405,15 @@ k_propagate_fp64(PropArgs a) {
         cache_reset(cache);
     // wave-uniform counters, summed from ballots (scalar registers)
     unsigned long long n_eval = 0, n_acc = 0, n_rej = 0, n_ev = 0, n_fl = 0, n_taken = 0, n_iter = 0;
+    bool cancel = false;  // the caller's cancel flag was seen set
 
     for (;;) {
+        if ((n_iter & (CANCEL_POLL - 1)) == 0 && !cancel) {
+            // the pointer is read from the kernel-argument segment here, not held in
+            // registers across the loop
+            const int32_t *cw = kernel_args<PropArgs>().cancel;
+            if (cw) cancel = __hip_atomic_load(cw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
+        }
         // refill idle lanes from the work queue
         for (;;) {
             unsigned long long want = __ballot(pid == -1);
@@ -413,7 +428,7 @@ k_propagate_fp64(PropArgs a) {
             unsigned long long got = 0;
             if (pid == -1) {
                 unsigned long long q = base + (unsigned long long)__popcll(want & below);
-                if (q < (unsigned long long)a.n) {
+                if (q < (unsigned long long)a.n && !cancel) {
                     int64_t p = a.order ? (int64_t)a.order[q] : (int64_t)q;
                     got = 1;
                     pid = start<MULTI, TAPE, RFL>(a, p, s) ? p : -1;
@@ -430,7 +445,7 @@ k_propagate_fp64(PropArgs a) {
         n_iter++;
         int flags = 0;
         if (pid >= 0) {
-            int st = advance<T, LAYOUT, MULTI, CACHE, TAPE, MOD, RFL>(a, pid, s, cache, ev, flags);
+            int st = advance<T, LAYOUT, MULTI, CACHE, TAPE, MOD, RFL>(a, pid, s, cache, ev, flags, cancel);
             if (st != CRP_ST_ACTIVE) pid = -1;
         }
         n_eval += __popcll(__ballot(flags & F_EVAL));
@@ -795,6 +810,7 @@ struct GradAccum {
     int t;            // lane within the wavefront
     uint32_t key;     // cell (i n1 + j) n2 + k, 0xffffffff when empty
     int ci[3];
+    int dropped;      // a contribution of the lane's particle was not finite and was left out
 };
 
 __device__ __forceinline__ void grad_flush(const FieldDev &F, GradAccum &g, double *gbar) {
@@ -806,7 +822,15 @@ __device__ __forceinline__ void grad_flush(const FieldDev &F, GradAccum &g, doub
         int64_t node;
         corner_weight(F, g.ci, t0, q, dw, node);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) unsafeAtomicAdd(gbar + 3 * node + c, g.v[3 * q + c][g.t]);
+        for (int c = 0; c < 3; ++c) {
+            // a cotangent beyond the FP64 range (a chaotic trajectory) would
+            // poison every particle's sum: its contribution is left out
+            const double v = g.v[3 * q + c][g.t];
+            if (isfinite(v))
+                unsafeAtomicAdd(gbar + 3 * node + c, v);
+            else
+                g.dropped = 1;
+        }
     }
     g.key = 0xffffffffu;
 }
@@ -940,9 +964,13 @@ struct AdjLane {
 
 // Gradients of the lane's finished particle: the direction entering the map
 // is normalised on a fresh start.
-__device__ __forceinline__ void adj_finish(const AdjLane &L) {
+__device__ __forceinline__ void adj_finish(const AdjLane &L, int dropped) {
     KernArg<AdjArgs> &a = kernel_args<AdjArgs>();  // read here: once per particle
     const int64_t p = L.p;
+    // a cotangent that left the FP64 range is reported in the particle's tape flags
+    bool finite = isfinite(L.kbar);
+    for (int c = 0; c < 6; ++c) finite = finite && isfinite(L.lam[c]);
+    if (dropped || !finite) a.fin_out[4 * p + 3] = (double)(L.flags | CRP_TAPE_GRAD_OVERFLOW);
     // a backtracked run is the forward run of the antiparticle with the
     // direction reversed: its direction gradient is reversed back
     const double sg = a.P.backtrack_on ? -1.0 : 1.0;
@@ -984,7 +1012,7 @@ template <class T, int LAYOUT, bool RFL, bool MOD>
 __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
     const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     __shared__ double acc_lds[24][64];
-    GradAccum acc{acc_lds, (int)threadIdx.x, 0xffffffffu, {0, 0, 0}};
+    GradAccum acc{acc_lds, (int)threadIdx.x, 0xffffffffu, {0, 0, 0}, 0};
     double *col = a.segbuf + lane;
     double *kdcol = a.segbuf + (int64_t)a.K * REC_SIZE * a.lanes + lane;
     const int64_t rstride = (int64_t)REC_SIZE * a.lanes;  // doubles between consecutive records
@@ -1016,8 +1044,9 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
             }
             L.kap = ((double)(k.P.backtrack_on ? -k.charge[p] : k.charge[p]) * K_LORENTZ) / k.energy[p];
             L.kbar = 0.0;
+            acc.dropped = 0;
             if (L.N == 0) {
-                adj_finish(L);
+                adj_finish(L, 0);
                 L.p = -1;
                 continue;
             }
@@ -1095,7 +1124,7 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
         if (busy) {
             if (--L.seg < 0) {
                 grad_flush(a.F, acc, a.grad_field);
-                adj_finish(L);
+                adj_finish(L, acc.dropped);
                 L.p = -1;
             } else {
                 L.slot = a.link[L.slot];

@@ -385,7 +385,9 @@ __device__ __forceinline__ void bid(const ParamsDev &P, Lane<ACC> &s) {
     if (P.sphere_on) {
         const float z[3] = {0.f, 0.f, 0.f};
         double g = s.acc.sphere(P, z);  // |x - c|^2 - R^2
-        double r = sqrt(g + P.r2);
+        // g + R^2 is |x - c|^2 up to the rounding of R^2 inside g: at the
+        // centre it can come out a few ulp below zero, which is clamped
+        double r = sqrt(fmax(g + P.r2, 0.0));
         float dist = (float)(P.radius - r);
         if (dist < h) h = dist;
     }
@@ -509,7 +511,7 @@ __device__ __forceinline__ bool start(const PropArgs &args, int64_t p, Lane<ACC>
 
 template <class T, int LAYOUT, bool MULTI, int ACC, bool CACHE, bool RFL, bool MOD>
 __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &s, CellCache<T> &cache, EventLDS &e,
-                                       int &flags) {
+                                       int &flags, bool cancel) {
     const int t = threadIdx.x;
     // per-particle groups: the lane's descriptors, read from the tables once
     // per iteration into registers (the lanes of a wavefront may differ)
@@ -607,6 +609,10 @@ __device__ __forceinline__ int advance(const PropArgs &a, int64_t p, Lane<ACC> &
             store(P, p, s, (double)s.hctrl, CRP_ST_MAX_STEPS);
             return CRP_ST_MAX_STEPS;
         }
+        if (cancel) {  // the caller's cancel flag: stop here, resumable like a used-up budget
+            store(P, p, s, (double)s.hctrl, CRP_ST_CANCELLED);
+            return CRP_ST_CANCELLED;
+        }
         bid<ACC, RFL>(P, s);
         return CRP_ST_ACTIVE;
     }
@@ -656,8 +662,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CACHE 
     cache_reset(cache);
     Lane<ACC> s;
     unsigned long long n_eval = 0, n_acc = 0, n_rej = 0, n_ev = 0, n_fl = 0, n_taken = 0, n_iter = 0;
+    bool cancel = false;  // the caller's cancel flag was seen set (read every 64 iterations)
 
     for (;;) {
+        if ((n_iter & 63u) == 0 && !cancel) {
+            // the pointer is read from the kernel-argument segment here, not held in
+            // registers across the loop
+            const int32_t *cw = kernel_args<PropArgs>().cancel;
+            if (cw) cancel = __hip_atomic_load(cw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
+        }
         for (;;) {
             unsigned long long want = __ballot(pid == -1);
             if (want == 0ull) break;
@@ -671,7 +684,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CACHE 
             unsigned long long got = 0;
             if (pid == -1) {
                 unsigned long long q = base + (unsigned long long)__popcll(want & below);
-                if (q < (unsigned long long)a.n) {
+                if (q < (unsigned long long)a.n && !cancel) {
                     int64_t p = a.order ? (int64_t)a.order[q] : (int64_t)q;
                     got = 1;
                     pid = start<MULTI, ACC, RFL>(a, p, s) ? p : -1;
@@ -688,7 +701,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CACHE 
         n_iter++;
         int flags = 0;
         if (pid >= 0) {
-            int st = advance<T, LAYOUT, MULTI, ACC, CACHE, RFL, MOD>(a, pid, s, cache, ev, flags);
+            int st = advance<T, LAYOUT, MULTI, ACC, CACHE, RFL, MOD>(a, pid, s, cache, ev, flags, cancel);
             if (st != CRP_ST_ACTIVE) pid = -1;
         }
         n_eval += __popcll(__ballot(flags & F_EVAL));

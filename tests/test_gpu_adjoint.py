@@ -392,11 +392,18 @@ def test_full_adjoint_workload_sampled(dev, oracle_mod):
     steps = r["finals"][:, 0]
     _say(f"accepted steps: mean {steps.mean():.0f} max {steps.max():.0f}; sphere stops {np.mean(r['flags'] & 1):.3f}")
     assert np.all(r["flags"] & 8) and not np.any(r["flags"] & 2)
+    assert not np.any(r["flags"] & crp.CRP_TAPE_MIRRORED)  # no box
     # Deflected trajectories are chaotic: the derivative of the step map grows
     # exponentially with the number of gyrations, and for the longest ones it
     # leaves the FP64 range (inf), as the oracle's does.  Short ones stay small.
     gn = np.max(np.abs(r["gu"]), axis=1)
     fin = np.isfinite(gn)
+    # those particles are flagged, and their non-finite contributions are left
+    # out of the grid gradient, which stays finite
+    over = (r["flags"] & crp.CRP_TAPE_GRAD_OVERFLOW) != 0
+    assert np.all(over[~fin]) and over.any()
+    assert np.all(np.isfinite(r["gg"]))
+    _say(f"gradient overflow flagged for {np.mean(over):.4f} of the particles; grid gradient finite")
     _say("log10 max|grad_u0| percentiles 10/50/90/99: "
          + " ".join(f"{v:.1f}" for v in np.percentile(np.log10(gn[fin]), [10, 50, 90, 99]))
          + f"; non-finite {np.mean(~fin):.4f}")
@@ -459,6 +466,8 @@ def test_adjoint_in_reflective_box(dev, oracle_mod):
         r = _gpu_adjoint(crp, torch, B, w.spacing, prm, P["pos"], P["dir"], P["energy"], P["charge"], gdir, gtime,
                          every_k=k, layout=layout)
         assert np.all(r["flags"] & 8) and not np.any(r["flags"] & 2)
+        # the tape marks the particles the box mirrored (most of them here)
+        assert np.sum((r["flags"] & crp.CRP_TAPE_MIRRORED) != 0) >= n // 2
         if R > 0:
             assert np.sum(r["flags"] & 1) >= n // 2, "want arrivals"
         assert np.sum(r["finals"][:, 0] >= 64) >= n // 2, "want runs over several checkpoints"
@@ -591,3 +600,37 @@ def test_autograd_backtracking_central_differences(dev):
     e1 = (losses(P["dir"], P["energy"] * (1 + 1e-6)) - losses(P["dir"], P["energy"] * (1 - 1e-6))) / (
         2e-6 * P["energy"])
     assert np.max(np.abs(e1 - gE) / np.abs(e1)) <= 1e-5
+
+
+def test_autograd_excludes_overflowed_particles_from_the_grid_gradient(dev):
+    """Chaotic trajectories of the adjoint workload whose cotangent leaves the
+    FP64 range: autograd's grid gradient is the other particles' (finite),
+    equal to a direct adjoint with the overflowed particles' cotangents zeroed."""
+    torch, crp = dev
+    from paper_1410_5323_amd import autograd as AG
+    w, B, P = workload(4)
+    n = 4000
+    _say(f"case: autograd grid gradient with overflowing particles, {n} particles of the adjoint workload")
+    prm = crp.make_params(w.tol, w.h_min, w.h_max, obs_radius=w.obs_radius, l_max=w.max_length)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a[:n])).cuda()  # noqa: E731
+    u0 = t(P["dir"]).requires_grad_(True)
+    # an FP64 grid: its gradient is returned in the grid's dtype, and the
+    # finite gradients of long chaotic trajectories exceed FP32's range
+    B = B.astype(np.float64)
+    grid = torch.from_numpy(B).cuda().requires_grad_(True)
+    d, tm, e, st = AG.propagate(u0, grid, t(P["pos"]), t(P["energy"]), t(P["charge"]), w.spacing, prm,
+                                layout="cell8")
+    rng = np.random.default_rng(61)
+    wd = torch.from_numpy(rng.standard_normal((n, 3))).cuda()
+    loss = (d * wd).sum()
+    loss.backward()
+    gg = grid.grad.double()
+    fin = torch.isfinite(u0.grad).all(dim=1)
+    assert bool(torch.isfinite(gg).all())
+    assert int((~fin).sum()) > 0, "want overflowing particles in the sample"
+    # the same through the C ABI with the overflowed cotangents zeroed
+    r = _gpu_adjoint(crp, torch, B, w.spacing, prm, P["pos"][:n], P["dir"][:n], P["energy"][:n], P["charge"][:n],
+                     wd.cpu().numpy() * fin.cpu().numpy()[:, None], np.zeros(n), layout="cell8")
+    err = _rel_all(gg.cpu().numpy(), r["gg"])
+    _say(f"  {int((~fin).sum())} overflowed; grid gradient rel err against the direct adjoint {err:.2e}")
+    assert err <= GRAD_TOL

@@ -176,10 +176,37 @@ def test_build_reports_bad_rows(dev, small):
     with pytest.raises(crp.CRPError) as ei:
         crp.crp_lens_build(nside, _dev(torch, rows, np.int32), st)
     assert ei.value.status == crp.CRP_ERR_INVALID
-    full = np.zeros(n, np.int32)  # 5000 launches in one row: more than an LDS sort holds
+    # 30000 launches in one row towards random border pixels of nside 64:
+    # more distinct columns (about 26,000) than one row's LDS table holds
+    m = 30000
+    v = rng.standard_normal((m, 3))
+    sv = {"ux": _dev(torch, v[:, 0], np.float64), "uy": _dev(torch, v[:, 1], np.float64),
+          "uz": _dev(torch, v[:, 2], np.float64), "status": _dev(torch, np.ones(m), np.int32)}
     with pytest.raises(crp.CRPError) as ei:
-        crp.crp_lens_build(nside, _dev(torch, full, np.int32), st)
+        crp.crp_lens_build(64, _dev(torch, np.zeros(m, np.int32), np.int32), sv)
     assert ei.value.status == crp.CRP_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("nside, rows, per_row", [(4, 16, 25000), (16, 3, 70000)])
+def test_dense_rows_match_oracle(dev, LN, nside, rows, per_row):
+    """Rows with tens of thousands of launches (dense statistics): counted in
+    an LDS hash table instead of sorted, against the lens oracle bit for bit."""
+    torch, crp = dev
+    _say(f"case: dense lens rows, nside {nside}, {rows} rows of {per_row} launches")
+    rng = np.random.default_rng(nside)
+    n = rows * per_row
+    u = rng.standard_normal((n, 3))
+    u[:, 2] += 2.0  # concentrated towards +z, as deflected arrivals are
+    status = np.where(rng.random(n) < 0.9, 1, 2).astype(np.int32)  # a tenth trapped
+    row = np.repeat(rng.choice(LN.npix(nside), rows, replace=False), per_row).astype(np.int32)
+    st = {"ux": _dev(torch, u[:, 0], np.float64), "uy": _dev(torch, u[:, 1], np.float64),
+          "uz": _dev(torch, u[:, 2], np.float64), "status": _dev(torch, status, np.int32)}
+    lg = crp.crp_lens_build(nside, _dev(torch, row, np.int32), st)
+    row_ptr, col, val = LN.lens_matrix(nside, row, u[:, 0], u[:, 1], u[:, 2], status == 1)
+    assert np.array_equal(lg.row_ptr.cpu().numpy(), row_ptr)
+    assert np.array_equal(lg.col.cpu().numpy(), col)
+    assert np.array_equal(lg.val.cpu().numpy(), val)
+    assert np.max(np.diff(row_ptr)) > 20
 
 
 def test_lens_workload_matches_oracle(dev, oracle_mod, LN):
