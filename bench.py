@@ -44,8 +44,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # bid arithmetic of an accepted step about 74.
 FLOPS_PER_EVALUATION = 950
 BYTES_PER_VALUE = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
-# the kernels' sources and the host code that picks the instance a launch runs
-KERNEL_SOURCES = ["crp_device.h", "propagate_fp64.hip", "crp_internal.h", "crp_host.cpp"]
+# the propagation kernel's device sources (its profiles are tied to their hash)
+KERNEL_SOURCES = ["crp_device.h", "lane.h", "propagate_fp64.hip", "crp_internal.h"]
 PRECISIONS = {"fp64": 0, "mixed_f64acc": 1, "mixed_dfacc": 2}
 
 
@@ -558,21 +558,31 @@ def adjoint_leg(reps: int = 2):
     gt = torch.from_numpy(rng.standard_normal(n) * 1e-14).cuda()
     gu = torch.empty(n, 3, dtype=torch.float64, device="cuda")
     gg = torch.zeros(grids[0].shape, dtype=torch.float64, device="cuda")
-    aws = torch.empty(crp.crp_adjoint_workspace_bytes(n, w.checkpoint_every), dtype=torch.uint8, device="cuda")
+    # parallel replay of the particles with at least half the most steps
+    replay = tape.replay_steps(0.5)
+    aws = crp.adjoint_workspace(n, tape, replay_steps=replay)
+    aws0 = crp.adjoint_workspace(n, tape, replay_steps=0)
 
-    def adj():
+    def adj(ws):
         gg.zero_()
-        crp.crp_propagate_adjoint(f, prm, init, tape, gd, gt, gu, gg, workspace=aws)
+        crp.crp_propagate_adjoint(f, prm, init, tape, gd, gt, gu, gg, workspace=ws)
 
-    t_adj = ev_time(adj)
+    t_adj = ev_time(lambda: adj(aws))
+    gu_par = gu.clone()
+    t_adj0 = ev_time(lambda: adj(aws0))
+    same = bool(torch.equal(gu_par.view(torch.int64), gu.view(torch.int64)))
     fin = torch.isfinite(gu).all(dim=1)
     return {"workload": w.name, "particles": n, "layout": layout, "accepted_steps": steps,
             "forward_ms": t_fwd, "taped_forward_ms": t_tape, "adjoint_ms": t_adj,
             "adjoint_over_forward": t_adj / t_fwd,
             "gradient_over_forward": (t_tape + t_adj) / t_fwd,
+            "parallel_replay_steps": replay, "parallel_replay_bytes": aws.numel() - aws0.numel(),
+            "adjoint_ms_without_parallel_replay": t_adj0,
+            "parallel_replay_same_bits": same,
             "tape_records_used": tape.records_needed(), "tape_bytes_used": tape.records_needed() * 72 + n * 32,
             "finite_gradient_fraction": float(fin.float().mean()),
-            "note": "gradient = taped forward + adjoint (the autograd path)"}
+            "note": "gradient = taped forward + adjoint (the autograd path); the adjoint replays the checkpoint "
+                    "segments of the particles with at least half the most steps in parallel before its sweep"}
 
 
 def main():

@@ -274,8 +274,27 @@ crp_status crp_propagate_noalloc(const crp_field *fields, int32_t n_fields, cons
                                  int32_t n_params, const crp_particles *p, int64_t n, const crp_tape *tape,
                                  int32_t precision, const crp_tuning *tuning, int64_t *counters, void *stream);
 
-/* Workspace for crp_propagate_adjoint: n particles, checkpoint interval K. */
+/* Workspace for crp_propagate_adjoint: n particles, checkpoint interval K.
+ * The minimum: every particle's steps are replayed by the sweep itself. */
 size_t crp_adjoint_workspace_bytes(int64_t n, int32_t every_k);
+
+/* Workspace for crp_propagate_adjoint with room for the parallel replay of
+ * replay_steps step records (616 bytes each: the record and the stages'
+ * grid-value cotangents; plus about 8 bytes per checkpoint segment and 20 per
+ * particle).  Before the reverse sweep, the particles with the most accepted
+ * steps are replayed one checkpoint segment per thread (the segments are
+ * independent given their checkpoints; section 3.1's step logic taken exactly
+ * as the forward run took it), so the sweep of those particles, which sets
+ * the time of the whole adjoint, is the reverse pass alone; their
+ * grid-gradient contributions are added after the sweep, one thread per
+ * segment, off its critical path.  They are taken in groups of 64 consecutive
+ * particles of the adjoint's order (most steps first, sorted in buckets of 1/8
+ * in log2 of the steps), each group needing 64 records per step of its longest
+ * particle, for as many groups as fit.  The direction, position and energy
+ * gradients are the same bits with any replay_steps (the grid gradient equal
+ * to the order of its atomic sums).  Returns 0 for invalid arguments (n < 0,
+ * K outside [1, 4096], replay_steps < 0). */
+size_t crp_adjoint_replay_workspace_bytes(int64_t n, int32_t every_k, int64_t replay_steps);
 
 /* Reverse-mode derivatives of the taped forward run (FP64).  The map
  * differentiated replays the forward pass's accepted steps (their sizes held
@@ -318,7 +337,9 @@ size_t crp_adjoint_workspace_bytes(int64_t n, int32_t every_k);
  * call).  Its grid contributions are then incomplete: to obtain grad_field
  * of the other particles exactly, zero the flagged particles' cotangents and
  * call again (the autograd wrapper does this).
- * workspace: [dev] crp_adjoint_workspace_bytes(n, K) bytes, 256-aligned. */
+ * workspace: [dev] at least crp_adjoint_workspace_bytes(n, K) bytes, 256-aligned;
+ * what a larger workspace holds beyond that (see
+ * crp_adjoint_replay_workspace_bytes) is used for parallel replay. */
 crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *params, const crp_particles *initial,
                                  int64_t n, const crp_tape *tape, const double *gbar_dir, const double *gbar_time,
                                  const double *gbar_energy, double *grad_u0, double *grad_x0,

@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcrp.so")
-SOURCES = ["crp_host.cpp", "support.hip", "upload.hip", "propagate_fp64.hip", "propagate_mixed.hip", "bench_kernels.hip",
-           "lens.hip", "noalloc.hip"]
+SOURCES = ["crp_host.cpp", "support.hip", "upload.hip", "propagate_fp64.hip", "adjoint_fp64.hip", "propagate_mixed.hip",
+           "bench_kernels.hip", "lens.hip", "noalloc.hip"]
 ARCH = os.environ.get("CRP_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -105,6 +105,8 @@ def lib():
         L.crp_noalloc_scratch_bytes.restype = C.c_size_t
         L.crp_adjoint_workspace_bytes.argtypes = [C.c_int64, C.c_int32]
         L.crp_adjoint_workspace_bytes.restype = C.c_size_t
+        L.crp_adjoint_replay_workspace_bytes.argtypes = [C.c_int64, C.c_int32, C.c_int64]
+        L.crp_adjoint_replay_workspace_bytes.restype = C.c_size_t
         L.crp_propagate_adjoint.argtypes = [C.POINTER(crp_field), C.POINTER(crp_params), C.POINTER(crp_particles),
                                             C.c_int64, C.POINTER(crp_tape), C.c_void_p, C.c_void_p, C.c_void_p,
                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -234,6 +236,25 @@ class Tape:
     def steps(self):
         return self.finals.view(-1, 4)[:, 0].to(_torch().int64)
 
+    def replay_steps(self, fraction: float = 0.5) -> int:
+        """Parallel-replay room (in records) for the particles that took at
+        least `fraction` of the most steps any particle took, which takes their
+        replay off the adjoint's critical path.  The adjoint replays groups of
+        64 consecutive particles of its order, each group padded to its most
+        steps; the order sorts by steps only within buckets of 1/8 in log2, so
+        the padded size is estimated on the sorted steps with a 10% margin."""
+        torch = _torch()
+        N = self.steps()
+        if N.numel() == 0:
+            return 0
+        top = int(N.max().item())
+        if top <= 0:
+            return 0
+        keep = torch.sort(N[N >= max(1, int(fraction * top))], descending=True).values
+        pad = (-keep.numel()) % 64
+        keep = torch.cat([keep, keep.new_zeros(pad)]).view(-1, 64)
+        return int(1.1 * 64 * int(keep.max(dim=1).values.sum().item())) + 64
+
     @property
     def nbytes(self) -> int:
         return self.capacity * 72 + self.finals.numel() * 8 + 8
@@ -272,16 +293,37 @@ def crp_adjoint_workspace_bytes(n: int, every_k: int) -> int:
     return int(lib().crp_adjoint_workspace_bytes(int(n), int(every_k)))
 
 
-def crp_propagate_adjoint(field, params, initial: dict, tape: Tape, gbar_dir, gbar_time, grad_u0, grad_field,
-                          grad_x0=None, gbar_energy=None, workspace=None, stream=None, grad_energy=None):
-    """Reverse-mode derivatives of a taped forward run (see crp.h)."""
+def crp_adjoint_replay_workspace_bytes(n: int, every_k: int, replay_steps: int) -> int:
+    return int(lib().crp_adjoint_replay_workspace_bytes(int(n), int(every_k), int(replay_steps)))
+
+
+def adjoint_workspace(n: int, tape: Tape, replay_steps="auto", device="cuda"):
+    """Workspace for crp_propagate_adjoint.  replay_steps: room for parallel
+    replay, in accepted steps; "auto" sizes it with tape.replay_steps() (after
+    the taped run) within a quarter of the free device memory; 0: none."""
     torch = _torch()
+    if replay_steps == "auto":
+        replay_steps = tape.replay_steps()
+        free = torch.cuda.mem_get_info(torch.device(device))[0]
+        base = crp_adjoint_workspace_bytes(n, tape.every_k)
+        while replay_steps > 0 and crp_adjoint_replay_workspace_bytes(n, tape.every_k, replay_steps) - base > free // 4:
+            replay_steps //= 2
+    nbytes = crp_adjoint_replay_workspace_bytes(n, tape.every_k, int(replay_steps))
+    if nbytes == 0:
+        raise ValueError("invalid adjoint workspace arguments")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def crp_propagate_adjoint(field, params, initial: dict, tape: Tape, gbar_dir, gbar_time, grad_u0, grad_field,
+                          grad_x0=None, gbar_energy=None, workspace=None, stream=None, grad_energy=None,
+                          replay_steps="auto"):
+    """Reverse-mode derivatives of a taped forward run (see crp.h).  Without a
+    workspace, one is allocated with adjoint_workspace(n, tape, replay_steps)."""
     n = int(initial["energy"].numel())
     ps = crp_particles(**{k: (initial[k].data_ptr() if initial.get(k) is not None else None)
                           for k in _PARTICLE_FIELDS})
     if workspace is None:
-        workspace = torch.empty(crp_adjoint_workspace_bytes(n, tape.every_k), dtype=torch.uint8,
-                                device=initial["energy"].device)
+        workspace = adjoint_workspace(n, tape, replay_steps, device=initial["energy"].device)
     _check(lib().crp_propagate_adjoint(C.byref(field.desc), C.byref(params), C.byref(ps), n, C.byref(tape.desc),
                                        _ptr(gbar_dir), _ptr(gbar_time), _ptr(gbar_energy), _ptr(grad_u0),
                                        _ptr(grad_x0), _ptr(grad_energy), _ptr(grad_field), _ptr(workspace),

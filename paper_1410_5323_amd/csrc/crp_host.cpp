@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.h"
 #include "crp_internal.h"
 
 namespace {
@@ -421,12 +422,22 @@ crp_status propagate_impl(const char *fn, const crp_field *fields, int32_t n_fie
 
 extern "C" {
 
-// Threads of an adjoint launch (each keeps a column of replay records).
-static int64_t adjoint_lanes(int64_t n) { return n < 65536 ? ((n + 63) / 64) * 64 : 65536; }
+// Threads of the adjoint's sweep launch (each keeps a column of replay
+// records): at most 16384, one wavefront per compute unit of an MI355X.  The
+// sweep runs one wavefront per SIMD at most (it takes all 512 registers), and
+// wavefronts sharing a compute unit slow each other down more than they add:
+// on a 1e5-particle workload with parallel replay the sweep took 1333 ms with
+// 65536 threads, 992 with 32768, 907 with 24576, 852 with 16384, 899 with
+// 12288 and 1051 with 8192.
+static int64_t adjoint_lanes(int64_t n) { return n < 16384 ? ((n + 63) / 64) * 64 : 16384; }
+
+size_t crp_adjoint_replay_workspace_bytes(int64_t n, int32_t every_k, int64_t replay_steps) {
+    if (n < 0 || every_k < 1 || every_k > 4096 || replay_steps < 0) return 0;
+    return crp::adjoint_ws_layout(n, every_k, adjoint_lanes(n), replay_steps).total;
+}
 
 size_t crp_adjoint_workspace_bytes(int64_t n, int32_t every_k) {
-    if (n < 0 || every_k < 1 || every_k > 4096) return 0;
-    return crp::adjoint_ws_bytes(n, every_k, adjoint_lanes(n));
+    return crp_adjoint_replay_workspace_bytes(n, every_k, 0);
 }
 
 crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *params, const crp_particles *initial,
@@ -451,15 +462,23 @@ crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *param
         !tape->checkpoints || !tape->links || !gbar_dir || !grad_u0 || !grad_field)
         return fail(CRP_ERR_INVALID, "%s: a required array is null", fn);
     int64_t lanes = adjoint_lanes(n);
-    size_t need = crp::adjoint_ws_bytes(n, tape->every_k, lanes);
+    size_t need = crp::adjoint_ws_layout(n, tape->every_k, lanes, 0).total;
     if (!workspace || workspace_bytes < need)
         return fail(CRP_ERR_WORKSPACE, "%s: workspace of %zu bytes needed", fn, need);
+    // the parallel-replay space: the most records the rest of the workspace holds
+    int64_t lo = 0, hi = (int64_t)(workspace_bytes / (8 * crp::ADJ_RECORD_DOUBLES));
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (crp::adjoint_ws_layout(n, tape->every_k, lanes, mid).total <= workspace_bytes)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const crp::AdjWs L = crp::adjoint_ws_layout(n, tape->every_k, lanes, lo);
     if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(CRP_ERR_WORKSPACE, "%s: workspace alignment", fn);
     if (cu_count() <= 0) return fail(CRP_ERR_DEVICE, "%s: no HIP device available", fn);
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
-    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
-    size_t off_order = 256, off_buckets = up(off_order + 4 * size_t(n)), off_seg = up(off_buckets + 8 * size_t(crp::NBUCKET + 1));
     crp::AdjArgs a;
     std::memset(&a, 0, sizeof a);
     a.F = make_field_dev(*field);
@@ -485,15 +504,26 @@ crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *param
     a.grad_x0 = grad_x0;
     a.grad_energy = grad_energy;
     a.grad_field = grad_field;
-    a.segbuf = reinterpret_cast<double *>(ws + off_seg);
+    a.segbuf = reinterpret_cast<double *>(ws + L.seg);
     a.lanes = lanes;
     a.queue = reinterpret_cast<unsigned long long *>(ws);
-    a.order = reinterpret_cast<const int32_t *>(ws + off_order);
+    a.order = reinterpret_cast<const int32_t *>(ws + L.order);
     a.n = n;
-    hipError_t e = crp::launch_fill_u64(a.queue, 0ull, 1, s);
+    a.R = L.R;
+    a.rows = L.rows;
+    if (L.R > 0) {
+        a.grp_rec = reinterpret_cast<int64_t *>(ws + L.grp_rec);
+        a.grp_row = reinterpret_cast<int64_t *>(ws + L.grp_row);
+        a.pre_ok = reinterpret_cast<int32_t *>(ws + L.pre_ok);
+        a.seg_slot = reinterpret_cast<int64_t *>(ws + L.seg_slot);
+        a.prerec = reinterpret_cast<double *>(ws + L.prerec);
+        a.prebar = reinterpret_cast<double *>(ws + L.prebar);
+    }
+    // queue head and parallel-replay cuts (0: none) cleared by a fill kernel
+    hipError_t e = crp::launch_fill_u64(a.queue, 0ull, 3, s);
     if (e == hipSuccess)
-        e = crp::launch_order_by_steps(tape->finals, n, reinterpret_cast<int32_t *>(ws + off_order),
-                                       reinterpret_cast<unsigned int *>(ws + off_buckets), s);
+        e = crp::launch_order_by_steps(tape->finals, n, reinterpret_cast<int32_t *>(ws + L.order),
+                                       reinterpret_cast<unsigned int *>(ws + L.buckets), s);
     if (e == hipSuccess) e = crp::launch_adjoint_fp64(a, (int)(lanes / 64), s);
     if (e != hipSuccess) return device_error(e, fn);
     return ok();

@@ -110,44 +110,6 @@ struct PropArgs {
     ParamsDev P0;
 };
 
-// Kernel arguments of the adjoint kernel.
-struct AdjArgs {
-    FieldDev F;
-    ParamsDev P;
-    const double *x0, *y0, *z0, *ux0, *uy0, *uz0, *energy;
-    const int32_t *charge;
-    const double *ckpt;
-    const int64_t *link;
-    const double *fin;
-    double *fin_out;                 // the same finals: flags written back (gradient overflow)
-    int64_t cap;
-    int32_t K;
-    int32_t pad_;
-    const double *gbar_dir, *gbar_time, *gbar_energy;
-    double *grad_u0, *grad_x0, *grad_energy, *grad_field;
-    double *segbuf;                  // [step j][58][lane] replay records, then [36][lane] scratch
-    int64_t lanes;                   // threads launched (segbuf stride)
-    unsigned long long *queue;
-    const int32_t *order;            // NULL: index order
-    int64_t n;
-};
-
-// Adjoint replay record: doubles per accepted step (pre-step state 6, step 1,
-// stage states 30, stage fields 18, output direction 3, mirrored axes 1), and
-// the crossing-derivative scratch.
-constexpr int ADJ_RECORD_DOUBLES = 59;
-constexpr int ADJ_SCRATCH_DOUBLES = 36;
-
-inline size_t adjoint_ws_bytes(int64_t n, int32_t K, int64_t lanes) {
-    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
-    size_t b = 256;                                  // queue head
-    b = up(b + 4 * size_t(n > 0 ? n : 0));           // order
-    b = up(b + 8 * size_t(NBUCKET + 1));             // bucket counters
-    b = up(b + 8 * ADJ_RECORD_DOUBLES * size_t(K) * size_t(lanes));  // replay records
-    b = up(b + 8 * ADJ_SCRATCH_DOUBLES * size_t(lanes));             // crossing-derivative scratch
-    return b;
-}
-
 // crp_propagate's checks and launches (crp_host.cpp), given host staging
 // arrays fd and pd of at least n_fields and n_params descriptors.  fn names
 // the entry point in error messages.  check_only: validate the arguments
@@ -170,7 +132,6 @@ hipError_t launch_propagate_fp64(const PropArgs &a, int dtype, int layout, bool 
                                  int block_size, hipStream_t s);
 hipError_t launch_propagate_mixed(const PropArgs &a, int dtype, int layout, bool multi, int precision, bool cache,
                                   int blocks, int block_size, hipStream_t s);
-hipError_t launch_adjoint_fp64(const AdjArgs &a, int blocks, hipStream_t s);
 hipError_t launch_order_by_steps(const double *fin, int64_t n, int32_t *order, unsigned int *buckets, hipStream_t s);
 hipError_t launch_upload_modulation(const FieldDev &f, const void *src, int src_dtype, hipStream_t s);
 hipError_t launch_upload(const FieldDev &f, const void *src, int src_dtype, void *dst, hipStream_t s);

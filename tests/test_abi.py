@@ -169,6 +169,16 @@ def test_tape_and_adjoint_reject_bad_arguments_without_device(crp):
     assert crp.crp_adjoint_workspace_bytes(-1, 64) == 0
     assert crp.crp_adjoint_workspace_bytes(100, 0) == 0
     assert crp.crp_adjoint_workspace_bytes(1000, 64) > crp.crp_adjoint_workspace_bytes(1000, 8) > 0
+    # parallel-replay room: none below one block of 64 records, then growing with it
+    base = crp.crp_adjoint_workspace_bytes(1000, 64)
+    assert crp.crp_adjoint_replay_workspace_bytes(1000, 64, 0) == base
+    assert crp.crp_adjoint_replay_workspace_bytes(1000, 64, 63) == base
+    sizes = [crp.crp_adjoint_replay_workspace_bytes(1000, 64, r) for r in (64, 6400, 640000, 64000000)]
+    assert base < sizes[0] < sizes[1] < sizes[2] < sizes[3]
+    # 472 bytes of record and 144 of grid-value cotangents per step, and the tables
+    assert 616 * 64000000 < sizes[3] - base < 640 * 64000000
+    assert crp.crp_adjoint_replay_workspace_bytes(1000, 64, -1) == 0
+    assert crp.crp_adjoint_replay_workspace_bytes(1000, 0, 64) == 0
 
     def adj(field=f, params=p, t=tape, n=10, g=0x6000, gu=0x7000, gf=0x8000, ws=None, wsb=0):
         return L.crp_propagate_adjoint(C.byref(field), C.byref(params), C.byref(parts), n, C.byref(t), g, None, None,

@@ -37,7 +37,7 @@ def dev():
 
 
 def _gpu_adjoint(crp, torch, B, spacing, prm, pos, dirs, energy, charge, gdir, gtime, every_k=64,
-                 layout="linear", capacity=None, genergy=None, modulation=None):
+                 layout="linear", capacity=None, genergy=None, modulation=None, replay_steps="auto"):
     dt = "f64" if B.dtype == np.float64 else "f32"
     f = crp.make_field(B, spacing, dtype=dt, layout=layout, modulation=modulation)
     init = crp.particles_to_device(pos, dirs, energy, charge)
@@ -56,7 +56,8 @@ def _gpu_adjoint(crp, torch, B, spacing, prm, pos, dirs, energy, charge, gdir, g
     gd = torch.from_numpy(np.ascontiguousarray(gdir, dtype=np.float64)).cuda()
     gt = torch.from_numpy(np.ascontiguousarray(gtime, dtype=np.float64)).cuda()
     gbe = None if genergy is None else torch.from_numpy(np.ascontiguousarray(genergy, dtype=np.float64)).cuda()
-    crp.crp_propagate_adjoint(f, prm, init, tape, gd, gt, gu, gg, grad_x0=gx, gbar_energy=gbe, grad_energy=ge)
+    crp.crp_propagate_adjoint(f, prm, init, tape, gd, gt, gu, gg, grad_x0=gx, gbar_energy=gbe, grad_energy=ge,
+                              replay_steps=replay_steps)
     torch.cuda.synchronize()
     return {"state": crp.particles_to_host(st), "gu": gu.cpu().numpy(), "gx": gx.cpu().numpy(),
             "ge": ge.cpu().numpy(),
@@ -156,6 +157,50 @@ def test_checkpoint_interval_does_not_change_gradients(dev):
         assert np.array_equal(out[k]["gx"], out[64]["gx"]), k
         eg = _rel_all(out[k]["gg"], out[64]["gg"])
         assert eg <= 1e-12, (k, eg)
+
+
+def test_parallel_replay_gives_the_same_bits(dev):
+    """Records replayed in parallel before the sweep (one thread per
+    checkpoint segment) are the bits the sweep's own replay writes: with no
+    parallel-replay room, with room for some of the longest particles (the cut
+    inside the order), for all of them and with the automatic size, the
+    direction, position and energy gradients are identical and the grid
+    gradient equal to the atomics' order.  Sphere arrivals, length stops,
+    both layouts, two intervals, a reflective box with a modulated field, and
+    a backtracked run."""
+    torch, crp = dev
+    w, B, P = workload(0, n=200, grid_dtype="f64")
+    rng = np.random.default_rng(23)
+    gdir = rng.standard_normal((200, 3))
+    gtime = rng.standard_normal(200) * 1e-14
+    M = ci.lognormal_modulation(8, 0.4, 0.8, 0.6, 78)
+    box = ((-1.0, -1.0, -1.0), (1.0, 1.0, 1.0))
+    cases = (("linear", 16, dict(obs_radius=2.0, l_max=20.0), None),
+             ("cell8", 5, dict(obs_radius=2.0, l_max=20.0), None),
+             ("cell8", 7, dict(obs_radius=1.3, l_max=20.0, box=box), M),
+             ("linear", 16, dict(obs_radius=2.0, l_max=20.0, backtrack=True), None))
+    for layout, k, kw, Mv in cases:
+        prm = crp.make_params(1e-6, 1e-7, 0.2, **kw)
+        mod = None if Mv is None else crp.make_modulation(Mv, 0.4, origin=(-0.13, 0.07, 0.21))
+        pos = P["pos"] if "box" not in kw else np.random.default_rng(55).uniform(-0.05, 0.05, (200, 3))
+
+        def run(budget):
+            return _gpu_adjoint(crp, torch, B, w.spacing, prm, pos, P["dir"], P["energy"], P["charge"], gdir, gtime,
+                                every_k=k, layout=layout, modulation=mod, replay_steps=budget)
+
+        ref = run(0)
+        N = ref["finals"][:, 0].astype(np.int64)
+        assert np.any(ref["flags"] & 1) and N.max() > 2 * k, "want arrivals and several segments"
+        total = int(N.sum())
+        for budget in (int(N.max()), total // 3, total, "auto"):
+            _say(f"case: parallel replay, {layout} K={k} {sorted(kw)} modulated {Mv is not None}, room {budget} "
+                 f"of {total} steps")
+            r = run(budget)
+            # steps, crossing and flags (the pool slots depend on the atomics' order)
+            assert np.array_equal(r["finals"][:, [0, 1, 3]], ref["finals"][:, [0, 1, 3]])
+            assert np.array_equal(r["gu"], ref["gu"]) and np.array_equal(r["gx"], ref["gx"])
+            assert np.array_equal(r["ge"], ref["ge"])
+            assert _rel_all(r["gg"], ref["gg"]) <= 1e-12
 
 
 def test_uniform_field_rotation(dev):
