@@ -18,9 +18,13 @@
  * Conventions
  *   - [dev] marks device pointers; every buffer is owned by the caller (for
  *     example allocated through PyTorch).  The library never allocates device
- *     memory and keeps no global state other than a thread-local error string.
+ *     memory and keeps no global state other than a thread-local error string;
+ *     the one exception is crp_propagate_noalloc's scratch array, a fixed
+ *     array in the library's device image whose per-device address it keeps.
  *   - All work is enqueued on the caller's stream and is asynchronous; the
- *     call returns after enqueueing.  No call throws across the ABI.
+ *     call returns after enqueueing.  The exception is crp_lens_build, which
+ *     waits for its stream to return the entry count and the row checks to
+ *     the host.  No call throws across the ABI.
  *   - Units: positions and lengths in Mpc, energies in eV, fields in nG,
  *     times in seconds.  Status values are the CRP_ST_* codes below.
  *   - Argument errors are reported synchronously, before anything is
@@ -235,7 +239,9 @@ size_t crp_modulation_bytes(const crp_modulation *m);
 crp_status crp_modulation_upload(const crp_modulation *m, const void *src, int32_t src_dtype, void *stream);
 
 /* Device workspace needed by crp_propagate for n particles and the given
- * table sizes (field and parameter descriptors, work queue, ordering keys). */
+ * table sizes (field and parameter descriptors, work queue, ordering keys).
+ * It is the same for every precision: no precision keeps per-particle
+ * scratch in the workspace. */
 size_t crp_workspace_bytes(int64_t n, int32_t n_fields, int32_t n_params);
 
 /* Propagate n particles in place (sections 2, 3.1, 3.2): each ACTIVE particle
@@ -311,9 +317,11 @@ size_t crp_adjoint_replay_workspace_bytes(int64_t n, int32_t every_k, int64_t re
  * may be NULL) with respect to the initial energy in eV: the rigidity
  * derivative (section 3.3: rigidity sets the deflection), kappa-bar * (-kappa /
  * E) with kappa = Z K / E and kappa-bar the cotangent of kappa summed over
- * every stage of the replay, plus gbar_energy; and grad_field ([dev] FP64
- * [n0][n1][n2][3], accumulated: the caller zeroes it) with respect to the
- * grid values in nG.  Particles without a complete tape get zero gradients.
+ * every stage of the replay, plus gbar_energy; and grad_field ([dev]
+ * [n0][n1][n2][3] of grad_dtype, CRP_F64 or CRP_F32, accumulated: the caller
+ * zeroes it) with respect to the grid values in nG.  The contributions are
+ * summed in FP64 per cell and added to grad_field with atomics of its type;
+ * an FP32 gradient halves its memory and its atomic traffic.  Particles without a complete tape get zero gradients.
  * A backtracked run (params->backtrack = 1) is differentiated as the forward
  * run of the antiparticle it is: gradients and cotangents refer to the
  * physical directions of the input and output, as crp_propagate reads and
@@ -331,7 +339,8 @@ size_t crp_adjoint_replay_workspace_bytes(int64_t n, int32_t every_k, int64_t re
  * respect to the vector grid's values (its cotangent carries the factor m);
  * the modulation grid's own values get none.
  * Chaotic trajectories amplify cotangents exponentially; a contribution to
- * grad_field that is not finite is left out (so grad_field stays finite), and
+ * grad_field that is not finite in grad_dtype is left out (so grad_field
+ * stays finite), and
  * a particle with such a contribution or a non-finite gradient gets
  * CRP_TAPE_GRAD_OVERFLOW in its tape flags (finals[4 i + 3], written by this
  * call).  Its grid contributions are then incomplete: to obtain grad_field
@@ -343,8 +352,8 @@ size_t crp_adjoint_replay_workspace_bytes(int64_t n, int32_t every_k, int64_t re
 crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *params, const crp_particles *initial,
                                  int64_t n, const crp_tape *tape, const double *gbar_dir, const double *gbar_time,
                                  const double *gbar_energy, double *grad_u0, double *grad_x0,
-                                 double *grad_energy, double *grad_field, void *workspace, size_t workspace_bytes,
-                                 void *stream);
+                                 double *grad_energy, void *grad_field, int32_t grad_dtype, void *workspace,
+                                 size_t workspace_bytes, void *stream);
 
 /* A captured propagation (hipGraph): the whole sequence of crp_propagate for
  * these exact arguments (descriptor tables, queue reset, longest-first order,

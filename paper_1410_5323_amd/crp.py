@@ -109,8 +109,8 @@ def lib():
         L.crp_adjoint_replay_workspace_bytes.restype = C.c_size_t
         L.crp_propagate_adjoint.argtypes = [C.POINTER(crp_field), C.POINTER(crp_params), C.POINTER(crp_particles),
                                             C.c_int64, C.POINTER(crp_tape), C.c_void_p, C.c_void_p, C.c_void_p,
-                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                            C.c_size_t, C.c_void_p]
+                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                            C.c_void_p, C.c_size_t, C.c_void_p]
         L.crp_propagate_adjoint.restype = C.c_int
         L.crp_selftest_arith.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
         L.crp_bench_gather.argtypes = [C.POINTER(crp_field), C.c_int64, C.c_int64, C.c_double, C.c_uint64,
@@ -318,7 +318,12 @@ def crp_propagate_adjoint(field, params, initial: dict, tape: Tape, gbar_dir, gb
                           grad_x0=None, gbar_energy=None, workspace=None, stream=None, grad_energy=None,
                           replay_steps="auto"):
     """Reverse-mode derivatives of a taped forward run (see crp.h).  Without a
-    workspace, one is allocated with adjoint_workspace(n, tape, replay_steps)."""
+    workspace, one is allocated with adjoint_workspace(n, tape, replay_steps).
+    grad_field: a float64 or float32 tensor (the grid gradient's dtype)."""
+    torch = _torch()
+    if grad_field.dtype not in (torch.float64, torch.float32):
+        raise TypeError("grad_field must be float64 or float32")
+    gdt = CRP_F64 if grad_field.dtype == torch.float64 else CRP_F32
     n = int(initial["energy"].numel())
     ps = crp_particles(**{k: (initial[k].data_ptr() if initial.get(k) is not None else None)
                           for k in _PARTICLE_FIELDS})
@@ -326,7 +331,7 @@ def crp_propagate_adjoint(field, params, initial: dict, tape: Tape, gbar_dir, gb
         workspace = adjoint_workspace(n, tape, replay_steps, device=initial["energy"].device)
     _check(lib().crp_propagate_adjoint(C.byref(field.desc), C.byref(params), C.byref(ps), n, C.byref(tape.desc),
                                        _ptr(gbar_dir), _ptr(gbar_time), _ptr(gbar_energy), _ptr(grad_u0),
-                                       _ptr(grad_x0), _ptr(grad_energy), _ptr(grad_field), _ptr(workspace),
+                                       _ptr(grad_x0), _ptr(grad_energy), _ptr(grad_field), gdt, _ptr(workspace),
                                        workspace.numel(),
                                        _stream_handle(stream)))
 

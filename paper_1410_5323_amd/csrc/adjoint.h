@@ -83,9 +83,10 @@ struct AdjArgs {
     double *fin_out;                 // the same finals: flags written back (gradient overflow)
     int64_t cap;
     int32_t K;
-    int32_t pad_;
+    int32_t grad_f32;                // grad_field holds FP32 values (else FP64)
     const double *gbar_dir, *gbar_time, *gbar_energy;
-    double *grad_u0, *grad_x0, *grad_energy, *grad_field;
+    double *grad_u0, *grad_x0, *grad_energy;
+    void *grad_field;
     double *segbuf;                  // [wave][step j][59][64] replay records, then [36][lane] scratch
     int64_t lanes;                   // threads of the sweep launch
     unsigned long long *queue;       // queue head; the parallel-replay cut follows it

@@ -300,7 +300,13 @@ struct GradAccum {
     int dropped;      // a contribution of the lane's particle was not finite and was left out
 };
 
-__device__ __forceinline__ void grad_flush(const FieldDev &F, GradAccum &g, double *gbar) {
+// The grid gradient: FP64 or FP32 values in the natural [n0][n1][n2][3] layout.
+struct GradOut {
+    void *p;
+    int f32;
+};
+
+__device__ __forceinline__ void grad_flush(const FieldDev &F, GradAccum &g, GradOut gbar) {
     if (g.key == 0xffffffffu) return;
     const double t0[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -313,10 +319,17 @@ __device__ __forceinline__ void grad_flush(const FieldDev &F, GradAccum &g, doub
             // a cotangent beyond the FP64 range (a chaotic trajectory) would
             // poison every particle's sum: its contribution is left out
             const double v = g.v[3 * q + c][g.t];
-            if (isfinite(v))
-                unsafeAtomicAdd(gbar + 3 * node + c, v);
-            else
+            if (gbar.f32) {
+                const float v32 = (float)v;
+                if (isfinite(v32))
+                    unsafeAtomicAdd(static_cast<float *>(gbar.p) + 3 * node + c, v32);
+                else
+                    g.dropped = 1;
+            } else if (isfinite(v)) {
+                unsafeAtomicAdd(static_cast<double *>(gbar.p) + 3 * node + c, v);
+            } else {
                 g.dropped = 1;
+            }
         }
     }
     g.key = 0xffffffffu;
@@ -324,7 +337,7 @@ __device__ __forceinline__ void grad_flush(const FieldDev &F, GradAccum &g, doub
 
 // Make ci the accumulator's cell, flushing and clearing the slots when it
 // changes.
-__device__ __forceinline__ void grad_select(const FieldDev &F, GradAccum &g, const int ci[3], double *gbar) {
+__device__ __forceinline__ void grad_select(const FieldDev &F, GradAccum &g, const int ci[3], GradOut gbar) {
     const uint32_t key = ((uint32_t)ci[0] * (uint32_t)F.n[1] + (uint32_t)ci[1]) * (uint32_t)F.n[2] + (uint32_t)ci[2];
     if (key == g.key) return;
     grad_flush(F, g, gbar);
@@ -347,7 +360,7 @@ __device__ __forceinline__ void grad_select(const FieldDev &F, GradAccum &g, con
 // (b . B-bar) dm/dX.
 template <class T, int LAYOUT, bool MOD>
 __device__ __forceinline__ void reverse_step(const FieldDev &F, double kap, const double *r, int64_t stride, double lam[6],
-                             const double *comb, GradAccum &acc, double *gbar, double &kbar, double *bbar) {
+                             const double *comb, GradAccum &acc, GradOut gbar, double &kbar, double *bbar) {
     const double s = r[REC_H * stride];
     double z[6];
 #pragma unroll
@@ -704,6 +717,7 @@ __global__ void __launch_bounds__(64) k_adj_scatter(AdjArgs a) {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     __shared__ double acc_lds[24][64];
     GradAccum acc{acc_lds, (int)threadIdx.x, 0xffffffffu, {0, 0, 0}, 0};
+    const GradOut gout{a.grad_field, a.grad_f32};
     int64_t G, q, sg;
     if (!replay_slot(a, g, G, q, sg)) return;
     const Eligible e = eligible(a, q);
@@ -720,7 +734,7 @@ __global__ void __launch_bounds__(64) k_adj_scatter(AdjArgs a) {
             double t[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) ci[c] = cell_axis(Y[c], a.F.origin[c], a.F.inv_spacing, a.F.n[c], a.F.pow2, t[c]);
-            grad_select(a.F, acc, ci, a.grad_field);
+            grad_select(a.F, acc, ci, gout);
             const double b[3] = {bb[(3 * i) * ADJ_GROUP], bb[(3 * i + 1) * ADJ_GROUP], bb[(3 * i + 2) * ADJ_GROUP]};
 #pragma unroll
             for (int qq = 0; qq < 8; ++qq) {
@@ -734,7 +748,7 @@ __global__ void __launch_bounds__(64) k_adj_scatter(AdjArgs a) {
             }
         }
     }
-    grad_flush(a.F, acc, a.grad_field);
+    grad_flush(a.F, acc, gout);
     if (acc.dropped) a.fin_out[4 * e.p + 3] = (double)(e.flags | CRP_TAPE_GRAD_OVERFLOW);
 }
 
@@ -752,6 +766,7 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
     const int64_t lane = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     __shared__ double acc_lds[24][64];
     GradAccum acc{acc_lds, (int)threadIdx.x, 0xffffffffu, {0, 0, 0}, 0};
+    const GradOut gout{a.grad_field, a.grad_f32};
     // this wavefront's block of segment records, the lane's column in it
     double *col = a.segbuf + (lane / ADJ_GROUP) * (int64_t)a.K * ADJ_BLOCK_DOUBLES + lane % ADJ_GROUP;
     double *kdcol = a.segbuf + (int64_t)a.K * REC_SIZE * a.lanes + lane;
@@ -850,7 +865,7 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
                 gs += dg[c] * zs[c];
             }
             double comb[3] = {-(psi / gs) * dg[0], -(psi / gs) * dg[1], -(psi / gs) * dg[2]};
-            reverse_step<T, LAYOUT, MOD>(a.F, L.kap, r, fs, L.lam, comb, acc, a.grad_field, L.kbar,
+            reverse_step<T, LAYOUT, MOD>(a.F, L.kap, r, fs, L.lam, comb, acc, gout, L.kbar,
                                          bb0 ? bb0 + (int64_t)(m - 1) * ADJ_BAR_BLOCK : nullptr);
         }
         // reverse sweep (the crossing step, if any, is done above; it ends on
@@ -860,18 +875,18 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
             if (j < mrev) {
                 const double *r = rb + (int64_t)j * ss;
                 if (RFL) mirror_cotangent(r, fs, L.lam);
-                reverse_step<T, LAYOUT, MOD>(a.F, L.kap, r, fs, L.lam, nullptr, acc, a.grad_field, L.kbar,
+                reverse_step<T, LAYOUT, MOD>(a.F, L.kap, r, fs, L.lam, nullptr, acc, gout, L.kbar,
                                              bb0 ? bb0 + (int64_t)j * ADJ_BAR_BLOCK : nullptr);
             }
         if (busy) {
             if (--L.seg < 0) {
-                grad_flush(a.F, acc, a.grad_field);
+                grad_flush(a.F, acc, gout);
                 adj_finish(L, acc.dropped);
                 L.p = -1;
             } else if (!pre) {
                 L.slot = a.link[L.slot];
                 if (L.slot < 0 || L.slot >= a.cap) {  // a broken chain: no adjoint for this particle
-                    grad_flush(a.F, acc, a.grad_field);
+                    grad_flush(a.F, acc, gout);
                     adj_zero(L.p);
                     L.p = -1;
                 }

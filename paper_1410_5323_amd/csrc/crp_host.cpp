@@ -443,7 +443,7 @@ size_t crp_adjoint_workspace_bytes(int64_t n, int32_t every_k) {
 crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *params, const crp_particles *initial,
                                  int64_t n, const crp_tape *tape, const double *gbar_dir, const double *gbar_time,
                                  const double *gbar_energy, double *grad_u0, double *grad_x0, double *grad_energy,
-                                 double *grad_field,
+                                 void *grad_field, int32_t grad_dtype,
                                  void *workspace, size_t workspace_bytes, void *stream) {
     const char *fn = "crp_propagate_adjoint";
     crp_status st = check_field(field, true, fn);
@@ -455,6 +455,8 @@ crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *param
     if (st != CRP_OK) return st;
     if (!initial || !tape) return fail(CRP_ERR_INVALID, "%s: null particles or tape", fn);
     if (n < 0 || n > (int64_t)0x7fffffff) return fail(CRP_ERR_INVALID, "%s: n out of range", fn);
+    if (grad_dtype != CRP_F64 && grad_dtype != CRP_F32)
+        return fail(CRP_ERR_INVALID, "%s: grad_dtype must be CRP_F64 or CRP_F32", fn);
     if (tape->every_k < 1 || tape->every_k > 4096) return fail(CRP_ERR_INVALID, "%s: bad tape interval", fn);
     if (n == 0) return ok();
     if (tape->capacity < 1) return fail(CRP_ERR_INVALID, "%s: the tape needs at least one record", fn);
@@ -504,6 +506,7 @@ crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *param
     a.grad_x0 = grad_x0;
     a.grad_energy = grad_energy;
     a.grad_field = grad_field;
+    a.grad_f32 = grad_dtype == CRP_F32;
     a.segbuf = reinterpret_cast<double *>(ws + L.seg);
     a.lanes = lanes;
     a.queue = reinterpret_cast<unsigned long long *>(ws);

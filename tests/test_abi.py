@@ -180,14 +180,16 @@ def test_tape_and_adjoint_reject_bad_arguments_without_device(crp):
     assert crp.crp_adjoint_replay_workspace_bytes(1000, 64, -1) == 0
     assert crp.crp_adjoint_replay_workspace_bytes(1000, 0, 64) == 0
 
-    def adj(field=f, params=p, t=tape, n=10, g=0x6000, gu=0x7000, gf=0x8000, ws=None, wsb=0):
+    def adj(field=f, params=p, t=tape, n=10, g=0x6000, gu=0x7000, gf=0x8000, ws=None, wsb=0, gdt=crp.CRP_F64):
         return L.crp_propagate_adjoint(C.byref(field), C.byref(params), C.byref(parts), n, C.byref(t), g, None, None,
-                                       gu, None, None, gf, ws, wsb, None)
+                                       gu, None, None, gf, gdt, ws, wsb, None)
 
     assert adj(n=-1) == crp.CRP_ERR_INVALID
     assert adj(t=crp.crp_tape(0x3000, 0x4000, 0x5000, 0x5800, 100, 0, 0)) == crp.CRP_ERR_INVALID
     assert adj(t=crp.crp_tape(0x3000, None, 0x5000, 0x5800, 100, 64, 0)) == crp.CRP_ERR_INVALID
     assert adj(g=None) == crp.CRP_ERR_INVALID
+    assert adj(gdt=crp.CRP_F16) == crp.CRP_ERR_INVALID  # the grid gradient is FP64 or FP32
+    assert adj(gdt=crp.CRP_F32) == crp.CRP_ERR_WORKSPACE  # arguments fine, no workspace
     assert adj(gu=None) == crp.CRP_ERR_INVALID
     assert adj(gf=None) == crp.CRP_ERR_INVALID
     assert adj(field=half) == crp.CRP_ERR_UNSUPPORTED
@@ -229,7 +231,7 @@ def test_modulation_descriptor_checks(crp):
     assert L.crp_propagate(farr, 1, parr, 1, C.byref(parts), 10, C.byref(tape), crp.CRP_PREC_MIXED_F64ACC, None,
                            None, None, 0, None) == crp.CRP_ERR_UNSUPPORTED  # a tape needs FP64 precision
     assert L.crp_propagate_adjoint(C.byref(f), C.byref(parr[0]), C.byref(parts), 10, C.byref(tape), 0x6000, None,
-                                   None, 0x7000, None, None, 0x8000, None, 0, None) == crp.CRP_ERR_WORKSPACE
+                                   None, 0x7000, None, None, 0x8000, crp.CRP_F64, None, 0, None) == crp.CRP_ERR_WORKSPACE
     assert L.crp_propagate(farr, 1, parr, 1, C.byref(parts), 10, None, 0, None, None, None, 0,
                            None) == crp.CRP_ERR_WORKSPACE
     m.data = None
@@ -267,11 +269,11 @@ def test_reflective_box_checks(crp):
     tape = crp.crp_tape(0x3000, 0x4000, 0x5000, 0x5800, 100, 64, 0)
     assert call(good, tape=tape) == crp.CRP_ERR_WORKSPACE  # arguments fine, no workspace
     assert L.crp_propagate_adjoint(C.byref(f), C.byref(good), C.byref(parts), 10, C.byref(tape), 0x6000, None, None,
-                                   0x7000, None, None, 0x8000, None, 0, None) == crp.CRP_ERR_WORKSPACE
+                                   0x7000, None, None, 0x8000, crp.CRP_F64, None, 0, None) == crp.CRP_ERR_WORKSPACE
     bad_box = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0, box=((0.0, 0.0, 0.0), (10.0, 0.0, 10.0)))
     assert call(bad_box, tape=tape) == crp.CRP_ERR_INVALID
     assert L.crp_propagate_adjoint(C.byref(f), C.byref(bad_box), C.byref(parts), 10, C.byref(tape), 0x6000, None,
-                                   None, 0x7000, None, None, 0x8000, None, 0, None) == crp.CRP_ERR_INVALID
+                                   None, 0x7000, None, None, 0x8000, crp.CRP_F64, None, 0, None) == crp.CRP_ERR_INVALID
     # a box that is off (reflect = 0) is not checked
     off = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0)
     off.box_lo[0] = 5.0
@@ -299,7 +301,7 @@ def test_backtrack_checks(crp):
     assert call(bt, prec=crp.CRP_PREC_MIXED_F64ACC) == crp.CRP_ERR_WORKSPACE  # the mixed kernel backtracks too
     assert call(bt, t=tape) == crp.CRP_ERR_WORKSPACE  # arguments fine, no workspace
     assert L.crp_propagate_adjoint(C.byref(f), C.byref(bt), C.byref(parts), 10, C.byref(tape), 0x6000, None, None,
-                                   0x7000, None, None, 0x8000, None, 0, None) == crp.CRP_ERR_WORKSPACE
+                                   0x7000, None, None, 0x8000, crp.CRP_F64, None, 0, None) == crp.CRP_ERR_WORKSPACE
     bad = crp.make_params(1e-4, 0.01, 1.0, l_max=10.0)
     bad.backtrack = -1
     assert call(bad) == crp.CRP_ERR_INVALID
