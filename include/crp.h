@@ -91,7 +91,10 @@ typedef struct {
 
 /* One periodic vector grid (section 3.2: regular grids; section 4: a vector
  * grid with a random Kolmogorov realisation).  Node (i,j,k) sits at
- * origin + spacing*(i,j,k); the field repeats with period n*spacing. */
+ * origin + spacing*(i,j,k); the field repeats with period n*spacing.
+ * Domain: cell indices are 32-bit integers, so positions must stay within
+ * 2^31 spacings of the origin along each axis (1.07e8 Mpc at 50 kpc); beyond
+ * it the index saturates instead of wrapping, and results are not defined. */
 typedef struct {
     int32_t n[3];          /* nodes per axis, each >= 2 */
     int32_t dtype;         /* crp_dtype of the stored values */
