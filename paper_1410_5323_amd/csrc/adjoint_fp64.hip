@@ -36,16 +36,36 @@ constexpr int REC_Y = 0, REC_H = 6, REC_STAGE = 7, REC_FIELD = 37, REC_ZU = 55, 
               REC_SIZE = ADJ_RECORD_DOUBLES;
 static_assert(REC_MIR + 1 == REC_SIZE, "record layout");
 
+// Stage recorder of a replayed step.  Vector-memory loads and stores retire
+// through one in-order counter, so a store issued before a field gather would
+// hold up the wait for that gather: the stage fields are kept in registers
+// and every record store is issued after the step's last gather, the stage
+// states recomputed from the stage derivatives with the step's own formulas
+// (the same bits).
 struct RecordWriter {
+    static constexpr bool deferred = true;
     double *r;       // field 0 of the record
     int64_t stride;  // doubles between its fields
-    __device__ __forceinline__ void stage(int i, const double *Y) const {
+    mutable double B[6][3];
+    __device__ __forceinline__ void stage(int, const double *) const {}
+    __device__ __forceinline__ void field(int i, const double *b) const {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) r[(REC_STAGE + 6 * (i - 1) + c) * stride] = Y[c];
+        for (int c = 0; c < 3; ++c) B[i][c] = b[c];
     }
-    __device__ __forceinline__ void field(int i, const double *B) const {
+    __device__ __forceinline__ void flush(const double *y, double h, const double *k1, const double *k2,
+                                          const double *k3, const double *k4, const double *k5) const {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) r[(REC_FIELD + 3 * i + c) * stride] = B[c];
+        for (int c = 0; c < 6; ++c) {
+            r[(REC_STAGE + c) * stride] = ck_y1(y, h, k1, c);
+            r[(REC_STAGE + 6 + c) * stride] = ck_y2(y, h, k1, k2, c);
+            r[(REC_STAGE + 12 + c) * stride] = ck_y3(y, h, k1, k2, k3, c);
+            r[(REC_STAGE + 18 + c) * stride] = ck_y4(y, h, k1, k2, k3, k4, c);
+            r[(REC_STAGE + 24 + c) * stride] = ck_y5(y, h, k1, k2, k3, k4, k5, c);
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) r[(REC_FIELD + 3 * i + c) * stride] = B[i][c];
     }
 };
 

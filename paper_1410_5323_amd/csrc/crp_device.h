@@ -401,11 +401,37 @@ __device__ __forceinline__ double norm3(double a, double b, double c) { return s
 
 // Stage recorder of ck_eval: receives each stage state Y_i (i = 1..5; Y_0 is
 // y itself) and each stage's field value B_i (i = 0..5).  The default records
-// nothing and compiles away.
+// nothing and compiles away.  A recorder with deferred = true is instead
+// handed the step's inputs and stage derivatives once, after the last stage
+// (flush), so that its stores come after every field gather of the step.
 struct NoStageRecord {
+    static constexpr bool deferred = false;
     __device__ __forceinline__ void stage(int, const double *) const {}
     __device__ __forceinline__ void field(int, const double *) const {}
+    __device__ __forceinline__ void flush(const double *, double, const double *, const double *, const double *,
+                                          const double *, const double *) const {}
 };
+
+// Component c of the Cash-Karp stage states Y_1..Y_5 from the stage
+// derivatives k_1..k_i: sums over j in increasing order with fma from zero.
+__device__ __forceinline__ double ck_y1(const double *y, double h, const double *k1, int c) {
+    return fma(h, fma(A21, k1[c], 0.0), y[c]);
+}
+__device__ __forceinline__ double ck_y2(const double *y, double h, const double *k1, const double *k2, int c) {
+    return fma(h, fma(A32, k2[c], fma(A31, k1[c], 0.0)), y[c]);
+}
+__device__ __forceinline__ double ck_y3(const double *y, double h, const double *k1, const double *k2,
+                                        const double *k3, int c) {
+    return fma(h, fma(A43, k3[c], fma(A42, k2[c], fma(A41, k1[c], 0.0))), y[c]);
+}
+__device__ __forceinline__ double ck_y4(const double *y, double h, const double *k1, const double *k2,
+                                        const double *k3, const double *k4, int c) {
+    return fma(h, fma(A54, k4[c], fma(A53, k3[c], fma(A52, k2[c], fma(A51, k1[c], 0.0)))), y[c]);
+}
+__device__ __forceinline__ double ck_y5(const double *y, double h, const double *k1, const double *k2,
+                                        const double *k3, const double *k4, const double *k5, int c) {
+    return fma(h, fma(A65, k5[c], fma(A64, k4[c], fma(A63, k3[c], fma(A62, k2[c], fma(A61, k1[c], 0.0))))), y[c]);
+}
 
 // One Cash-Karp evaluation of step h from y: fifth-order solution y5 and the
 // norms of the embedded error vector delta = h * sum_i e_i k_i split into
@@ -420,34 +446,31 @@ __device__ __forceinline__ void ck_eval(const FieldDev &F, int fid, CellCache<T,
     rhs<T, LAYOUT, CACHE, MOD>(F, fid, cache, kap, y, k1, B);
     rec.field(0, B);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) Y[c] = fma(h, fma(A21, k1[c], 0.0), y[c]);
+    for (int c = 0; c < 6; ++c) Y[c] = ck_y1(y, h, k1, c);
     rec.stage(1, Y);
     rhs<T, LAYOUT, CACHE, MOD>(F, fid, cache, kap, Y, k2, B);
     rec.field(1, B);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) Y[c] = fma(h, fma(A32, k2[c], fma(A31, k1[c], 0.0)), y[c]);
+    for (int c = 0; c < 6; ++c) Y[c] = ck_y2(y, h, k1, k2, c);
     rec.stage(2, Y);
     rhs<T, LAYOUT, CACHE, MOD>(F, fid, cache, kap, Y, k3, B);
     rec.field(2, B);
 #pragma unroll
-    for (int c = 0; c < 6; ++c)
-        Y[c] = fma(h, fma(A43, k3[c], fma(A42, k2[c], fma(A41, k1[c], 0.0))), y[c]);
+    for (int c = 0; c < 6; ++c) Y[c] = ck_y3(y, h, k1, k2, k3, c);
     rec.stage(3, Y);
     rhs<T, LAYOUT, CACHE, MOD>(F, fid, cache, kap, Y, k4, B);
     rec.field(3, B);
 #pragma unroll
-    for (int c = 0; c < 6; ++c)
-        Y[c] = fma(h, fma(A54, k4[c], fma(A53, k3[c], fma(A52, k2[c], fma(A51, k1[c], 0.0)))), y[c]);
+    for (int c = 0; c < 6; ++c) Y[c] = ck_y4(y, h, k1, k2, k3, k4, c);
     rec.stage(4, Y);
     rhs<T, LAYOUT, CACHE, MOD>(F, fid, cache, kap, Y, k5, B);
     rec.field(4, B);
 #pragma unroll
-    for (int c = 0; c < 6; ++c)
-        Y[c] = fma(h, fma(A65, k5[c], fma(A64, k4[c], fma(A63, k3[c], fma(A62, k2[c], fma(A61, k1[c], 0.0))))),
-                   y[c]);
+    for (int c = 0; c < 6; ++c) Y[c] = ck_y5(y, h, k1, k2, k3, k4, k5, c);
     rec.stage(5, Y);
     rhs<T, LAYOUT, CACHE, MOD>(F, fid, cache, kap, Y, k6, B);
     rec.field(5, B);
+    if constexpr (Rec::deferred) rec.flush(y, h, k1, k2, k3, k4, k5);
     double d[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
