@@ -393,6 +393,7 @@ __device__ __forceinline__ void reverse_step(const FieldDev &F, double kap, cons
     if (comb)
         for (int c = 0; c < 3; ++c) zb[c] += comb[c];
     double Yb[6][6];
+    double bbs[6][3];  // the stages' b-bar, stored after the step's last gather
     double yb[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) yb[c] = zb[c];
@@ -452,9 +453,8 @@ __device__ __forceinline__ void reverse_step(const FieldDev &F, double kap, cons
                     __hip_atomic_fetch_add(&acc.v[3 * q + c][acc.t], w * bb[c], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        if (bbar)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) bbar[(3 * i + c) * stride] = bb[c];
+        for (int c = 0; c < 3; ++c) bbs[i][c] = bb[c];
         if constexpr (MOD) {
             // X-bar += (b . B-bar) dm/dX
 #pragma unroll
@@ -465,6 +465,13 @@ __device__ __forceinline__ void reverse_step(const FieldDev &F, double kap, cons
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) lam[c] = yb[c];
+    // stores retire through the same in-order counter as the gathers: issued
+    // here, none of this step's gathers waits for them
+    if (bbar)
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) bbar[(3 * i + c) * stride] = bbs[i][c];
 }
 
 // Wavefront-wide maximum of a lane value (inactive lanes contribute 0).
