@@ -9,26 +9,28 @@
 // recording every accepted step's stage states and stage field values; the
 // records are then swept in reverse.  The reverse sweep reads the recorded
 // stages instead of recomputing them, so it gathers each stage's cell once
-// (for the field gradient) and scatters the grid-gradient contributions to a
-// natural-layout FP64 array with atomics.
+// (for the field gradient) and adds the grid-gradient contributions to a
+// natural-layout FP64 or FP32 array with atomics.
 //
 // Where the replay happens:
-//  * in the sweep kernel, one checkpoint segment at a time, into the lane's
-//    own column of records (every particle, when no parallel-replay space is
-//    given);
+//  * in the sweep kernel, one checkpoint segment at a time, into its
+//    wavefront's block of records (every particle, when no parallel-replay
+//    space is given);
 //  * before the sweep, for the particles with the most accepted steps that
 //    fit in the workspace's parallel-replay space: every checkpoint segment
 //    of theirs is replayed by a thread of its own (segments are independent
 //    given their checkpoints), so the sweep of those particles is only the
-//    reverse pass.  Their records are the same bits either way.
+//    reverse pass, and their grid contributions are added after it.  Their
+//    records are the same bits either way.
 #include "adjoint.h"
 #include "lane.h"
 
 namespace crp {
 namespace {
 
-// Record of one accepted step, its fields `stride` doubles apart (a lane's
-// column: stride = lanes; a parallel-replayed record: stride 1): the
+// Record of one accepted step, its fields `stride` doubles apart (64: the
+// records of a wavefront's lanes interleave, so that a field's loads and
+// stores are contiguous across the wavefront): the
 // pre-step state y (6), the step size (1), the stage states Y_1..Y_5 (30),
 // the stage field values B_0..B_5 (18), the unnormalised output direction
 // (3) and, in a reflective box, the axes mirrored after the step (1).
@@ -94,7 +96,7 @@ __device__ __forceinline__ double stage_k(double kap, const double Y[6], const d
 
 // One attempt of the replay of a step from lane state s, exactly as advance()
 // takes it (the caller bids before a step's first attempt): one Cash-Karp
-// evaluation recorded at r (this thread's column), then either a rejection
+// evaluation recorded at r (this lane's record), then either a rejection
 // (smaller step, returns false) or the acceptance (controller, normalisation,
 // the mirror in a reflective box, the pre-step state, step size and mirrored
 // axes recorded; returns true).
@@ -605,7 +607,11 @@ __global__ void __launch_bounds__(PREFIX_THREADS) k_adj_prefix(AdjArgs a) {
     __shared__ int64_t sr[PREFIX_THREADS], ss[PREFIX_THREADS];
     __shared__ unsigned long long cut;
     const int t = threadIdx.x;
-    const int64_t ng = (a.n + ADJ_GROUP - 1) / ADJ_GROUP;
+    // the scan covers the first R / 64 + 1 groups: a group with steps takes at
+    // least one block, so a later group can fit only after empty ones (then
+    // it is left to the sweep)
+    const int64_t ng_all = (a.n + ADJ_GROUP - 1) / ADJ_GROUP, blocks = a.R / ADJ_GROUP;
+    const int64_t ng = ng_all < blocks + 1 ? ng_all : blocks + 1;
     const int64_t chunk = (ng + PREFIX_THREADS - 1) / PREFIX_THREADS;
     const int64_t g0 = (int64_t)t * chunk < ng ? (int64_t)t * chunk : ng;
     const int64_t g1 = g0 + chunk < ng ? g0 + chunk : ng;
@@ -628,7 +634,6 @@ __global__ void __launch_bounds__(PREFIX_THREADS) k_adj_prefix(AdjArgs a) {
     }
     r = sr[t] - r;  // exclusive
     w = ss[t] - w;
-    const int64_t blocks = a.R / ADJ_GROUP;
     for (int64_t G = g0; G < g1; ++G) {
         const int64_t m = group_steps(a, G);
         a.grp_rec[G] = r;
@@ -794,7 +799,7 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
     __shared__ double acc_lds[24][64];
     GradAccum acc{acc_lds, (int)threadIdx.x, 0xffffffffu, {0, 0, 0}, 0};
     const GradOut gout{a.grad_field, a.grad_f32};
-    // this wavefront's block of segment records, the lane's column in it
+    // this wavefront's block of segment records, the lane's records in it
     double *col = a.segbuf + (lane / ADJ_GROUP) * (int64_t)a.K * ADJ_BLOCK_DOUBLES + lane % ADJ_GROUP;
     double *kdcol = a.segbuf + (int64_t)a.K * REC_SIZE * a.lanes + lane;
     AdjLane L;
@@ -847,7 +852,7 @@ __global__ void __launch_bounds__(64) k_adjoint_fp64(AdjArgs a) {
         const bool busy = L.p >= 0;
         if (__ballot(busy) == 0ull) break;
 
-        // this segment's records: the lane's column, replayed here, or the
+        // this segment's records: the wavefront's block, replayed here, or the
         // parallel-replayed ones (the same layout: fields 64 apart)
         const bool pre = busy && L.pre != nullptr;
         const int64_t nseg = busy ? (L.N + a.K - 1) / a.K : 0;
