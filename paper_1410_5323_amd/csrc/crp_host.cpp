@@ -467,8 +467,11 @@ crp_status crp_propagate_adjoint(const crp_field *field, const crp_params *param
     size_t need = crp::adjoint_ws_layout(n, tape->every_k, lanes, 0).total;
     if (!workspace || workspace_bytes < need)
         return fail(CRP_ERR_WORKSPACE, "%s: workspace of %zu bytes needed", fn, need);
-    // the parallel-replay space: the most records the rest of the workspace holds
+    // the parallel-replay space: the most records the rest of the workspace
+    // holds (at most 2^36, 40 TB of records, which keeps every size and grid
+    // dimension derived from it in range)
     int64_t lo = 0, hi = (int64_t)(workspace_bytes / (8 * crp::ADJ_RECORD_DOUBLES));
+    if (hi > ((int64_t)1 << 36)) hi = (int64_t)1 << 36;
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo + 1) / 2;
         if (crp::adjoint_ws_layout(n, tape->every_k, lanes, mid).total <= workspace_bytes)
