@@ -45,6 +45,7 @@ static_assert(REC_MIR + 1 == REC_SIZE, "record layout");
 // states recomputed from the stage derivatives with the step's own formulas
 // (the same bits).
 struct RecordWriter {
+    static constexpr bool records = true;
     static constexpr bool deferred = true;
     double *r;       // field 0 of the record
     int64_t stride;  // doubles between its fields

@@ -162,6 +162,50 @@ __device__ __forceinline__ void interp_corners(const FieldDev &F, const T (&v)[2
     }
 }
 
+// fma(t, d, a) into a register of its own.  The compiler's two-address form
+// of fma overwrites its addend, which for the cached edges would cost a copy
+// of every cached value at every lookup; this form leaves them in place.  The
+// same rounding as fma().
+__device__ __forceinline__ double fma_keep(double t, double d, double a) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(t), "v"(d), "v"(a));
+    return r;
+}
+
+// The cached form of a cell: edge e = (dz*2 + dy)*3 + c runs along x from
+// corner (0, dy, dz) to (1, dy, dz) of component c; a holds its lower value,
+// d the upper minus the lower, both as interp_corners forms them.
+template <class T>
+__device__ __forceinline__ void edges_of_corners(const T (&v)[24], double (&a)[12], double (&d)[12]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            a[3 * e + c] = to_f64<T>(v[6 * e + c]);
+            d[3 * e + c] = to_f64<T>(v[6 * e + 3 + c]) - a[3 * e + c];
+        }
+}
+
+// interp_corners on the cached edges: the same operations in the same order.
+__device__ __forceinline__ void interp_edges(const FieldDev &F, const double (&a)[12], const double (&d)[12],
+                                             double tx, double ty, double tz, double B[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double c00 = fma_keep(tx, d[0 + c], a[0 + c]);
+        double c10 = fma_keep(tx, d[3 + c], a[3 + c]);
+        double c01 = fma_keep(tx, d[6 + c], a[6 + c]);
+        double c11 = fma_keep(tx, d[9 + c], a[9 + c]);
+        double c0 = lerp(c00, c10, ty);
+        double c1 = lerp(c01, c11, ty);
+        B[c] = lerp(c0, c1, tz);
+    }
+    if (F.value_scale != 1.0) {
+        B[0] = B[0] * F.value_scale;
+        B[1] = B[1] * F.value_scale;
+        B[2] = B[2] * F.value_scale;
+    }
+}
+
 // Field lookup at X (Mpc) -> B (nG), reading the corners from memory.
 template <class T, int LAYOUT>
 __device__ __forceinline__ void lookup(const FieldDev &F, const double X[3], double B[3]) {
@@ -189,6 +233,8 @@ struct CellCache {
     uint32_t key;   // cell index (i*n1 + j)*n2 + k, 0xffffffff = empty
     int32_t field;  // field the cell belongs to
     T v[24];        // the cell's stored corner values
+    double a[12];   // or, for paired lookups (lookup_pair), the cell's x-edges: lower corner
+    double d[12];   // values converted exactly, and upper minus lower
     uint32_t mkey;  // FP32 modulation grid: its last cell, 0xffffffff = empty
     float mv[8];    // that cell's 8 stored values
     int misses;     // lookups that read global memory (diagnostic)
@@ -381,14 +427,8 @@ __device__ __forceinline__ void lookup_cached(const FieldDev &F, int fid, const 
     }
 }
 
-// Right-hand side in path length: k = (U, kappa * U x B(X)) for Y = (X, U).
-template <class T, int LAYOUT, bool CACHE, bool MOD = false, bool L = false>
-__device__ __forceinline__ void rhs(const FieldDev &F, int fid, CellCache<T, L> &cache, double kap, const double Y[6],
-                                    double k[6], double B[3]) {
-    lookup_cached<T, LAYOUT, CACHE, MOD>(F, fid, Y, B, cache);
-    k[0] = Y[3];
-    k[1] = Y[4];
-    k[2] = Y[5];
+// Direction part of the right-hand side: k[3..5] = kappa * U x B for Y = (X, U).
+__device__ __forceinline__ void lorentz(double kap, const double Y[6], const double B[3], double k[6]) {
     double cx = Y[4] * B[2] - Y[5] * B[1];
     double cy = Y[5] * B[0] - Y[3] * B[2];
     double cz = Y[3] * B[1] - Y[4] * B[0];
@@ -397,14 +437,26 @@ __device__ __forceinline__ void rhs(const FieldDev &F, int fid, CellCache<T, L> 
     k[5] = kap * cz;
 }
 
+// Right-hand side in path length: k = (U, kappa * U x B(X)) for Y = (X, U).
+template <class T, int LAYOUT, bool CACHE, bool MOD = false, bool L = false>
+__device__ __forceinline__ void rhs(const FieldDev &F, int fid, CellCache<T, L> &cache, double kap, const double Y[6],
+                                    double k[6], double B[3]) {
+    lookup_cached<T, LAYOUT, CACHE, MOD>(F, fid, Y, B, cache);
+    k[0] = Y[3];
+    k[1] = Y[4];
+    k[2] = Y[5];
+    lorentz(kap, Y, B, k);
+}
+
 __device__ __forceinline__ double norm3(double a, double b, double c) { return sqrt(a * a + b * b + c * c); }
 
 // Stage recorder of ck_eval: receives each stage state Y_i (i = 1..5; Y_0 is
 // y itself) and each stage's field value B_i (i = 0..5).  The default records
-// nothing and compiles away.  A recorder with deferred = true is instead
+// nothing (records = false) and compiles away.  A recorder with deferred = true is instead
 // handed the step's inputs and stage derivatives once, after the last stage
 // (flush), so that its stores come after every field gather of the step.
 struct NoStageRecord {
+    static constexpr bool records = false;
     static constexpr bool deferred = false;
     __device__ __forceinline__ void stage(int, const double *) const {}
     __device__ __forceinline__ void field(int, const double *) const {}
@@ -433,6 +485,118 @@ __device__ __forceinline__ double ck_y5(const double *y, double h, const double 
     return fma(h, fma(A65, k5[c], fma(A64, k4[c], fma(A63, k3[c], fma(A62, k2[c], fma(A61, k1[c], 0.0))))), y[c]);
 }
 
+// The cell of the grid holding X and the fractions within it, as
+// lookup_cached finds them.
+struct CellAt {
+    uint32_t key;
+    int i, j, k;
+    double tx, ty, tz;
+};
+
+__device__ __forceinline__ void cell_at(const FieldDev &F, const double X[3], CellAt &c) {
+    c.i = cell_axis(X[0], F.origin[0], F.inv_spacing, F.n[0], F.pow2, c.tx);
+    c.j = cell_axis(X[1], F.origin[1], F.inv_spacing, F.n[1], F.pow2, c.ty);
+    c.k = cell_axis(X[2], F.origin[2], F.inv_spacing, F.n[2], F.pow2, c.tz);
+    c.key = ((uint32_t)c.i * (uint32_t)F.n[1] + (uint32_t)c.j) * (uint32_t)F.n[2] + (uint32_t)c.k;
+}
+
+// Two lookups whose positions are both known, through the register cell
+// cache: the corner loads of both cells are issued before the first is
+// waited for, so the two gathers' latencies overlap.  Every lane issues both
+// loads; a lane whose cell is already held reads the grid's first record
+// instead (the same line for the whole wavefront, so one cache access), which
+// keeps the loads out of branches: the wait for the first cell then does not
+// also wait for the second.  The cache holds A's cell after A and B's after
+// B, as two calls of lookup_cached would leave it; the values, and so B, are
+// the same.
+template <class T, int LAYOUT>
+__device__ __forceinline__ void lookup_pair(const FieldDev &F, int fid, const double XA[3], const double XB[3],
+                                            double BA[3], double BB[3], CellCache<T, false> &cache) {
+    CellAt a, b;
+    cell_at(F, XA, a);
+    cell_at(F, XB, b);
+    const bool missA = a.key != cache.key || fid != cache.field;
+    const bool missB = b.key != a.key;
+    T va[24], vb[24];
+    load_corners<T, LAYOUT>(F, missA ? a.i : 0, missA ? a.j : 0, missA ? a.k : 0, va);
+    load_corners<T, LAYOUT>(F, missB ? b.i : 0, missB ? b.j : 0, missB ? b.k : 0, vb);
+    // keeps both loads here: without it the compiler moves each into the
+    // branch that uses it, where it is waited for at once
+    asm volatile("" ::: "memory");
+    if (missA) {
+        edges_of_corners<T>(va, cache.a, cache.d);
+        cache.key = a.key;
+        cache.field = fid;
+        cache.misses++;
+    }
+    interp_edges(F, cache.a, cache.d, a.tx, a.ty, a.tz, BA);
+    if (missB) {
+        edges_of_corners<T>(vb, cache.a, cache.d);
+        cache.key = b.key;
+        cache.misses++;
+    }
+    interp_edges(F, cache.a, cache.d, b.tx, b.ty, b.tz, BB);
+}
+
+// ck_eval's six stages in three levels of two lookups (register cell cache,
+// no modulation, nothing recorded).  The position of stage i+1 needs only the
+// stage directions up to stage i, that is the fields up to stage i-1, so
+// stages (1, 2), (3, 4) and (5, 6) can look up their fields together.  Every
+// component is computed by the same expression as in ck_eval; only the order
+// in which components are formed differs, so the results are the same bits.
+template <class T, int LAYOUT>
+__device__ __forceinline__ void ck_stages_paired(const FieldDev &F, int fid, CellCache<T, false> &cache, double kap,
+                                                 const double y[6], double h, double k1[6], double k2[6],
+                                                 double k3[6], double k4[6], double k5[6], double k6[6]) {
+    double Ya[6], Yb[6], BA[3], BB[3];
+    // stages 1 and 2: X_1 = x; X_2 needs k1[0..2] = u only
+    k1[0] = y[3];
+    k1[1] = y[4];
+    k1[2] = y[5];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Yb[c] = ck_y1(y, h, k1, c);
+    lookup_pair<T, LAYOUT>(F, fid, y, Yb, BA, BB, cache);
+    lorentz(kap, y, BA, k1);
+#pragma unroll
+    for (int c = 3; c < 6; ++c) Yb[c] = ck_y1(y, h, k1, c);
+    k2[0] = Yb[3];
+    k2[1] = Yb[4];
+    k2[2] = Yb[5];
+    lorentz(kap, Yb, BB, k2);
+    // stages 3 and 4: X_3 needs k1, k2; X_4 needs k3[0..2] = U_3, which needs k1, k2
+#pragma unroll
+    for (int c = 0; c < 6; ++c) Ya[c] = ck_y2(y, h, k1, k2, c);
+    k3[0] = Ya[3];
+    k3[1] = Ya[4];
+    k3[2] = Ya[5];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Yb[c] = ck_y3(y, h, k1, k2, k3, c);
+    lookup_pair<T, LAYOUT>(F, fid, Ya, Yb, BA, BB, cache);
+    lorentz(kap, Ya, BA, k3);
+#pragma unroll
+    for (int c = 3; c < 6; ++c) Yb[c] = ck_y3(y, h, k1, k2, k3, c);
+    k4[0] = Yb[3];
+    k4[1] = Yb[4];
+    k4[2] = Yb[5];
+    lorentz(kap, Yb, BB, k4);
+    // stages 5 and 6
+#pragma unroll
+    for (int c = 0; c < 6; ++c) Ya[c] = ck_y4(y, h, k1, k2, k3, k4, c);
+    k5[0] = Ya[3];
+    k5[1] = Ya[4];
+    k5[2] = Ya[5];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Yb[c] = ck_y5(y, h, k1, k2, k3, k4, k5, c);
+    lookup_pair<T, LAYOUT>(F, fid, Ya, Yb, BA, BB, cache);
+    lorentz(kap, Ya, BA, k5);
+#pragma unroll
+    for (int c = 3; c < 6; ++c) Yb[c] = ck_y5(y, h, k1, k2, k3, k4, k5, c);
+    k6[0] = Yb[3];
+    k6[1] = Yb[4];
+    k6[2] = Yb[5];
+    lorentz(kap, Yb, BB, k6);
+}
+
 // One Cash-Karp evaluation of step h from y: fifth-order solution y5 and the
 // norms of the embedded error vector delta = h * sum_i e_i k_i split into
 // position (ex) and direction (eu) parts.  Stage sums accumulate over j in
@@ -442,7 +606,11 @@ template <class T, int LAYOUT, bool CACHE, class Rec = NoStageRecord, bool MOD =
 __device__ __forceinline__ void ck_eval(const FieldDev &F, int fid, CellCache<T, L> &cache, double kap,
                                         const double y[6], double h, double y5[6], double &ex, double &eu,
                                         const Rec &rec = Rec()) {
-    double k1[6], k2[6], k3[6], k4[6], k5[6], k6[6], Y[6], B[3];
+    double k1[6], k2[6], k3[6], k4[6], k5[6], k6[6];
+    if constexpr (CACHE && !MOD && !L && !Rec::records) {
+        ck_stages_paired<T, LAYOUT>(F, fid, cache, kap, y, h, k1, k2, k3, k4, k5, k6);
+    } else {
+    double Y[6], B[3];
     rhs<T, LAYOUT, CACHE, MOD>(F, fid, cache, kap, y, k1, B);
     rec.field(0, B);
 #pragma unroll
@@ -471,6 +639,7 @@ __device__ __forceinline__ void ck_eval(const FieldDev &F, int fid, CellCache<T,
     rhs<T, LAYOUT, CACHE, MOD>(F, fid, cache, kap, Y, k6, B);
     rec.field(5, B);
     if constexpr (Rec::deferred) rec.flush(y, h, k1, k2, k3, k4, k5);
+    }
     double d[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
