@@ -201,6 +201,23 @@ template <> struct Acc<ACC_DF> {
     }
 };
 
+// FP32 trilinear interpolation of a cell's stored corner values at
+// fractions t (along x, then y, then z), times the grid's value scale.
+template <class T>
+__device__ __forceinline__ void interp_rel(const T (&v)[24], const float t[3], float sc, float B[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float c00 = lerpf(to_f32<T>(v[0 + c]), to_f32<T>(v[3 + c]), t[0]);
+        float c10 = lerpf(to_f32<T>(v[6 + c]), to_f32<T>(v[9 + c]), t[0]);
+        float c01 = lerpf(to_f32<T>(v[12 + c]), to_f32<T>(v[15 + c]), t[0]);
+        float c11 = lerpf(to_f32<T>(v[18 + c]), to_f32<T>(v[21 + c]), t[0]);
+        B[c] = lerpf(lerpf(c00, c10, t[1]), lerpf(c01, c11, t[1]), t[2]);
+    }
+    B[0] *= sc;
+    B[1] *= sc;
+    B[2] *= sc;
+}
+
 // Cell-relative FP32 lookup: base cell ib, fraction tb, stage offset d (Mpc).
 // With CACHE, the last cell's corner values are kept in the lane's registers
 // and a repeated lookup of that cell reads no global memory; those instances
@@ -273,18 +290,7 @@ __device__ __forceinline__ void lookup_rel(const FieldDev &F, int fid, const int
         load_corners<T, LAYOUT>(F, ci[0], ci[1], ci[2], v);
         cache.misses++;
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        float c00 = lerpf(to_f32<T>(v[0 + c]), to_f32<T>(v[3 + c]), t[0]);
-        float c10 = lerpf(to_f32<T>(v[6 + c]), to_f32<T>(v[9 + c]), t[0]);
-        float c01 = lerpf(to_f32<T>(v[12 + c]), to_f32<T>(v[15 + c]), t[0]);
-        float c11 = lerpf(to_f32<T>(v[18 + c]), to_f32<T>(v[21 + c]), t[0]);
-        B[c] = lerpf(lerpf(c00, c10, t[1]), lerpf(c01, c11, t[1]), t[2]);
-    }
-    const float sc = (float)F.value_scale;
-    B[0] *= sc;
-    B[1] *= sc;
-    B[2] *= sc;
+    interp_rel<T>(v, t, (float)F.value_scale, B);
     if (mod) {
         // trilinear as the FP64 path: along x, then y, then z
         const float c00 = lerpf(mv[0], mv[2], mt[0]);  // (y, z) = (0, 0)
@@ -296,6 +302,58 @@ __device__ __forceinline__ void lookup_rel(const FieldDev &F, int fid, const int
         B[1] *= m;
         B[2] *= m;
     }
+}
+
+// Two cell-relative lookups whose offsets are both known (register cell
+// cache, no modulation): the corner loads of both cells are issued before
+// the first is waited for.  Every lane issues both loads, a lane whose cell
+// is already cached reading the grid's first record instead (one line for
+// the whole wavefront), so that the wait for the first cell is not also a
+// wait for the second; the empty asm keeps the compiler from moving each load
+// into the branch that uses it.  Cells, fractions and interpolation are those
+// of lookup_rel, and the cache is left as two calls of it would leave it.
+template <class T, int LAYOUT>
+__device__ __forceinline__ void lookup_pair_rel(const FieldDev &F, int fid, const int ib[3], const float tb[3],
+                                                const float dA[3], const float dB[3], float BA[3], float BB[3],
+                                                CellCache<T> &cache) {
+    const float inv = (float)F.inv_spacing;
+    int ca[3], cb[3];
+    float ta[3], tbb[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float f = fmaf(dA[a], inv, tb[a]);
+        float fl = floorf(f);
+        ta[a] = f - fl;
+        ca[a] = wrap(ib[a] + (int)fl, F.n[a], F.pow2);
+        float g = fmaf(dB[a], inv, tb[a]);
+        float gl = floorf(g);
+        tbb[a] = g - gl;
+        cb[a] = wrap(ib[a] + (int)gl, F.n[a], F.pow2);
+    }
+    const uint32_t ka = ((uint32_t)ca[0] * (uint32_t)F.n[1] + (uint32_t)ca[1]) * (uint32_t)F.n[2] + (uint32_t)ca[2];
+    const uint32_t kb = ((uint32_t)cb[0] * (uint32_t)F.n[1] + (uint32_t)cb[1]) * (uint32_t)F.n[2] + (uint32_t)cb[2];
+    const bool missA = ka != cache.key || fid != cache.field;
+    const bool missB = kb != ka;
+    T va[24], vb[24];
+    load_corners<T, LAYOUT>(F, missA ? ca[0] : 0, missA ? ca[1] : 0, missA ? ca[2] : 0, va);
+    load_corners<T, LAYOUT>(F, missB ? cb[0] : 0, missB ? cb[1] : 0, missB ? cb[2] : 0, vb);
+    asm volatile("" ::: "memory");
+    const float sc = (float)F.value_scale;
+    if (missA) {
+#pragma unroll
+        for (int w = 0; w < 24; ++w) cache.v[w] = va[w];
+        cache.key = ka;
+        cache.field = fid;
+        cache.misses++;
+    }
+    interp_rel<T>(cache.v, ta, sc, BA);
+    if (missB) {
+#pragma unroll
+        for (int w = 0; w < 24; ++w) cache.v[w] = vb[w];
+        cache.key = kb;
+        cache.misses++;
+    }
+    interp_rel<T>(cache.v, tbb, sc, BB);
 }
 
 __device__ __forceinline__ void lorentz(float kap, const float U[3], const float B[3], float F[3]) {
@@ -314,6 +372,45 @@ __device__ __forceinline__ void ck_eval_f32(const FieldDev &F, int fid, CellCach
     float F1[3], F2[3], F3[3], F4[3], F5[3], F6[3];
     float d[3], B[3];
     const float z[3] = {0.f, 0.f, 0.f};
+    if constexpr (CACHE && !MOD) {
+        // stages (1, 2), (3, 4), (5, 6) in pairs: the offset of stage i+1
+        // needs the directions up to stage i, so the fields only up to i-1;
+        // each quantity is the same expression as below
+        float e[3], B2[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) e[c] = h * (a21 * u[c]);
+        lookup_pair_rel<T, LAYOUT>(F, fid, ib, tb, z, e, B, B2, cache);
+        lorentz(kap, u, B, F1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) U2[c] = fmaf(h, a21 * F1[c], u[c]);
+        lorentz(kap, U2, B2, F2);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            d[c] = h * fmaf(a32, U2[c], a31 * u[c]);
+            U3[c] = fmaf(h, fmaf(a32, F2[c], a31 * F1[c]), u[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) e[c] = h * fmaf(a43, U3[c], fmaf(a42, U2[c], a41 * u[c]));
+        lookup_pair_rel<T, LAYOUT>(F, fid, ib, tb, d, e, B, B2, cache);
+        lorentz(kap, U3, B, F3);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) U4[c] = fmaf(h, fmaf(a43, F3[c], fmaf(a42, F2[c], a41 * F1[c])), u[c]);
+        lorentz(kap, U4, B2, F4);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            d[c] = h * fmaf(a54, U4[c], fmaf(a53, U3[c], fmaf(a52, U2[c], a51 * u[c])));
+            U5[c] = fmaf(h, fmaf(a54, F4[c], fmaf(a53, F3[c], fmaf(a52, F2[c], a51 * F1[c]))), u[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            e[c] = h * fmaf(a65, U5[c], fmaf(a64, U4[c], fmaf(a63, U3[c], fmaf(a62, U2[c], a61 * u[c]))));
+        lookup_pair_rel<T, LAYOUT>(F, fid, ib, tb, d, e, B, B2, cache);
+        lorentz(kap, U5, B, F5);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            U6[c] = fmaf(h, fmaf(a65, F5[c], fmaf(a64, F4[c], fmaf(a63, F3[c], fmaf(a62, F2[c], a61 * F1[c])))), u[c]);
+        lorentz(kap, U6, B2, F6);
+    } else {
     lookup_rel<T, LAYOUT, CACHE, MOD>(F, fid, ib, tb, mr, z, B, cache);
     lorentz(kap, u, B, F1);
 #pragma unroll
@@ -351,6 +448,7 @@ __device__ __forceinline__ void ck_eval_f32(const FieldDev &F, int fid, CellCach
     }
     lookup_rel<T, LAYOUT, CACHE, MOD>(F, fid, ib, tb, mr, d, B, cache);
     lorentz(kap, U6, B, F6);
+    }
     float exx[3], euu[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
