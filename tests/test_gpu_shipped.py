@@ -20,6 +20,8 @@ import sys
 import numpy as np
 import pytest
 
+import crp_inputs as ci
+
 from gpu_common import compare, require_gpu, run_oracle, workload
 
 pytestmark = pytest.mark.gpu
@@ -53,6 +55,52 @@ def test_production_instance_with_register_cache(dev, oracle_mod):
     r = compare(g, o, "production instance")
     assert c[1] == o["counters"]["accepted"] and c[2] == o["counters"]["rejected"]
     _say(f"  {r}, cache hit rate {1 - c[6] / (6 * c[0]):.3f}")
+
+
+@pytest.mark.parametrize("layout,dtype,mixed", [("cell8", "f32", False), ("linear", "f64", False),
+                                                ("cell8", "f16", True), ("linear", "bf16", True)])
+def test_paired_lookups_leave_the_cache_as_sequential_ones(dev, oracle_mod, layout, dtype, mixed):
+    """Register-cache instances without modulation look up the stage fields
+    in pairs, both cells' loads in flight together; modulated instances look
+    them up one at a time.  With a modulation of ones the two give the same
+    bits and the same number of cell loads: the pairs leave the cell cache as
+    sequential lookups do, in the FP64 kernel (also bitwise equal to the
+    oracle) and in the mixed one.  Steps of up to five cells (h_max 0.5 Mpc
+    on a 0.1 Mpc grid) put the two stages of a pair in different cells often."""
+    torch, crp = dev
+    w = ci.get_config(0)
+    fs, ps, _ = ci.config_seeds(0)
+    B = ci.kolmogorov_field(w.grid_n, w.spacing, w.l_min, w.l_max, w.b_rms, fs)
+    B = B.astype(np.float32) if dtype == "f32" else B
+    prec = crp.CRP_PREC_MIXED_F64ACC if mixed else crp.CRP_PREC_FP64
+    P = ci.isotropic_particles(3000, 1e18, 3e19, (1, 2, 7, 26), ps)
+    prm_kw = dict(tol=1e-4, h_min=1e-4, h_max=0.5, obs_radius=2.5, l_max=30.0)
+    _say(f"case: paired against sequential cached lookups, {layout} {dtype}, mixed {mixed}, 3000 nuclei")
+    ones = crp.make_modulation(np.ones((7, 9, 11)), 0.31, origin=(-1.0, 0.2, 0.4))
+    runs = []
+    for mod in (None, ones):
+        f = crp.make_field(B, w.spacing, dtype=dtype, layout=layout, modulation=mod)
+        st = crp.particles_to_device(P["pos"], P["dir"], P["energy"], P["charge"])
+        cnt = torch.zeros(crp.NCOUNTERS, dtype=torch.int64, device="cuda")
+        crp.crp_propagate([f], [crp.make_params(**prm_kw)], st, precision=prec, tuning=crp.make_tuning(cache_cells=1),
+                          counters=cnt)
+        torch.cuda.synchronize()
+        runs.append((crp.particles_to_host(st), cnt.cpu().numpy()))
+    (g, c), (gm, cm) = runs
+    for k in ("pos", "dir", "length", "status", "n_accepted", "n_rejected", "h_next"):
+        assert np.array_equal(g[k], gm[k]), k
+    assert c[6] == cm[6], (c[6], cm[6])
+    # both hits and misses are frequent
+    assert 0.1 * 6 * c[0] < c[6] < 0.9 * 6 * c[0], (c[6], c[0])
+    if mixed:
+        _say(f"  same bits, cell loads per lookup {c[6] / (6 * c[0]):.3f}")
+        return
+    O = oracle_mod
+    prm = O.params_array(prm_kw["tol"], prm_kw["h_min"], prm_kw["h_max"], radius=prm_kw["obs_radius"],
+                         l_max=prm_kw["l_max"])
+    o = O.propagate(O.Grid(B, w.spacing), prm, P["pos"], P["dir"], P["energy"], P["charge"])
+    r = compare(g, o, "paired lookups")
+    _say(f"  {r}, cell loads per lookup {c[6] / (6 * c[0]):.3f}")
 
 
 def _host_stored(B, dtype, scale):
