@@ -500,6 +500,20 @@ __device__ __forceinline__ void cell_at(const FieldDev &F, const double X[3], Ce
     c.key = ((uint32_t)c.i * (uint32_t)F.n[1] + (uint32_t)c.j) * (uint32_t)F.n[2] + (uint32_t)c.k;
 }
 
+// The corner values of cell (i, j, k) with key (i*n1 + j)*n2 + k (use), or
+// of the grid's first cell.  In CELL8 storage the key is the record index.
+template <class T, int LAYOUT>
+__device__ __forceinline__ void load_cell(const FieldDev &F, uint32_t key, int i, int j, int k, bool use,
+                                          T (&v)[24]) {
+    if (LAYOUT == CRP_LAYOUT_CELL8) {
+        const global_ptr<raw_t<T>> p = as_global<raw_t<T>>(F.data) + 32ull * (uint64_t)(use ? key : 0u);
+#pragma unroll
+        for (int w = 0; w < 24; ++w) v[w] = from_raw<T>(p[w]);
+    } else {
+        load_corners<T, LAYOUT>(F, use ? i : 0, use ? j : 0, use ? k : 0, v);
+    }
+}
+
 // Two lookups whose positions are both known, through the register cell
 // cache: the corner loads of both cells are issued before the first is
 // waited for, so the two gathers' latencies overlap.  Every lane issues both
@@ -518,8 +532,8 @@ __device__ __forceinline__ void lookup_pair(const FieldDev &F, int fid, const do
     const bool missA = a.key != cache.key || fid != cache.field;
     const bool missB = b.key != a.key;
     T va[24], vb[24];
-    load_corners<T, LAYOUT>(F, missA ? a.i : 0, missA ? a.j : 0, missA ? a.k : 0, va);
-    load_corners<T, LAYOUT>(F, missB ? b.i : 0, missB ? b.j : 0, missB ? b.k : 0, vb);
+    load_cell<T, LAYOUT>(F, a.key, a.i, a.j, a.k, missA, va);
+    load_cell<T, LAYOUT>(F, b.key, b.i, b.j, b.k, missB, vb);
     // keeps both loads here: without it the compiler moves each into the
     // branch that uses it, where it is waited for at once
     asm volatile("" ::: "memory");

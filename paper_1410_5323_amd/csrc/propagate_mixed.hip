@@ -335,8 +335,8 @@ __device__ __forceinline__ void lookup_pair_rel(const FieldDev &F, int fid, cons
     const bool missA = ka != cache.key || fid != cache.field;
     const bool missB = kb != ka;
     T va[24], vb[24];
-    load_corners<T, LAYOUT>(F, missA ? ca[0] : 0, missA ? ca[1] : 0, missA ? ca[2] : 0, va);
-    load_corners<T, LAYOUT>(F, missB ? cb[0] : 0, missB ? cb[1] : 0, missB ? cb[2] : 0, vb);
+    load_cell<T, LAYOUT>(F, ka, ca[0], ca[1], ca[2], missA, va);
+    load_cell<T, LAYOUT>(F, kb, cb[0], cb[1], cb[2], missB, vb);
     asm volatile("" ::: "memory");
     const float sc = (float)F.value_scale;
     if (missA) {
