@@ -235,6 +235,8 @@ struct CellCache {
     T v[24];        // the cell's stored corner values
     double a[12];   // or, for paired lookups (lookup_pair), the cell's x-edges: lower corner
     double d[12];   // values converted exactly, and upper minus lower
+    float fa[12];   // the same in FP32 for the mixed kernel's paired lookups
+    float fd[12];
     uint32_t mkey;  // FP32 modulation grid: its last cell, 0xffffffff = empty
     float mv[8];    // that cell's 8 stored values
     int misses;     // lookups that read global memory (diagnostic)

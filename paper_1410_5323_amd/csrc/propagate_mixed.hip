@@ -304,6 +304,42 @@ __device__ __forceinline__ void lookup_rel(const FieldDev &F, int fid, const int
     }
 }
 
+// fmaf(t, d, a) into a register of its own (the two-address fma would
+// overwrite the cached addend a; same rounding as fmaf).
+__device__ __forceinline__ float fmaf_keep(float t, float d, float a) {
+    float r;
+    asm("v_fma_f32 %0, %1, %2, %3" : "=v"(r) : "v"(t), "v"(d), "v"(a));
+    return r;
+}
+
+// interp_rel on a cell held as FP32 x-edges: edge e = (dz*2 + dy)*3 + c has
+// lower value fa[e] and upper minus lower fd[e], as interp_rel forms them.
+__device__ __forceinline__ void interp_rel_edges(const float (&fa)[12], const float (&fd)[12], const float t[3],
+                                                 float sc, float B[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float c00 = fmaf_keep(t[0], fd[0 + c], fa[0 + c]);
+        float c10 = fmaf_keep(t[0], fd[3 + c], fa[3 + c]);
+        float c01 = fmaf_keep(t[0], fd[6 + c], fa[6 + c]);
+        float c11 = fmaf_keep(t[0], fd[9 + c], fa[9 + c]);
+        B[c] = lerpf(lerpf(c00, c10, t[1]), lerpf(c01, c11, t[1]), t[2]);
+    }
+    B[0] *= sc;
+    B[1] *= sc;
+    B[2] *= sc;
+}
+
+template <class T>
+__device__ __forceinline__ void edges_rel(const T (&v)[24], float (&fa)[12], float (&fd)[12]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            fa[3 * e + c] = to_f32<T>(v[6 * e + c]);
+            fd[3 * e + c] = to_f32<T>(v[6 * e + 3 + c]) - fa[3 * e + c];
+        }
+}
+
 // Two cell-relative lookups whose offsets are both known (register cell
 // cache, no modulation): the corner loads of both cells are issued before
 // the first is waited for.  Every lane issues both loads, a lane whose cell
@@ -311,7 +347,8 @@ __device__ __forceinline__ void lookup_rel(const FieldDev &F, int fid, const int
 // the whole wavefront), so that the wait for the first cell is not also a
 // wait for the second; the empty asm keeps the compiler from moving each load
 // into the branch that uses it.  Cells, fractions and interpolation are those
-// of lookup_rel, and the cache is left as two calls of it would leave it.
+// of lookup_rel (the cell cached as its FP32 x-edges), and the cache holds
+// the cell two calls of it would leave it holding.
 template <class T, int LAYOUT>
 __device__ __forceinline__ void lookup_pair_rel(const FieldDev &F, int fid, const int ib[3], const float tb[3],
                                                 const float dA[3], const float dB[3], float BA[3], float BB[3],
@@ -340,20 +377,18 @@ __device__ __forceinline__ void lookup_pair_rel(const FieldDev &F, int fid, cons
     asm volatile("" ::: "memory");
     const float sc = (float)F.value_scale;
     if (missA) {
-#pragma unroll
-        for (int w = 0; w < 24; ++w) cache.v[w] = va[w];
+        edges_rel<T>(va, cache.fa, cache.fd);
         cache.key = ka;
         cache.field = fid;
         cache.misses++;
     }
-    interp_rel<T>(cache.v, ta, sc, BA);
+    interp_rel_edges(cache.fa, cache.fd, ta, sc, BA);
     if (missB) {
-#pragma unroll
-        for (int w = 0; w < 24; ++w) cache.v[w] = vb[w];
+        edges_rel<T>(vb, cache.fa, cache.fd);
         cache.key = kb;
         cache.misses++;
     }
-    interp_rel<T>(cache.v, tbb, sc, BB);
+    interp_rel_edges(cache.fa, cache.fd, tbb, sc, BB);
 }
 
 __device__ __forceinline__ void lorentz(float kap, const float U[3], const float B[3], float F[3]) {
