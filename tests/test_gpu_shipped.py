@@ -57,25 +57,33 @@ def test_production_instance_with_register_cache(dev, oracle_mod):
     _say(f"  {r}, cache hit rate {1 - c[6] / (6 * c[0]):.3f}")
 
 
-@pytest.mark.parametrize("layout,dtype,mixed", [("cell8", "f32", False), ("linear", "f64", False),
-                                                ("cell8", "f16", True), ("linear", "bf16", True)])
-def test_paired_lookups_leave_the_cache_as_sequential_ones(dev, oracle_mod, layout, dtype, mixed):
+@pytest.mark.parametrize("layout,dtype,mixed,shape", [("cell8", "f32", False, None), ("linear", "f64", False, None),
+                                                      ("cell8", "f16", True, None), ("linear", "bf16", True, None),
+                                                      ("cell8", "f32", False, (24, 20, 28)),
+                                                      ("linear", "f32", False, (24, 20, 28))])
+def test_paired_lookups_leave_the_cache_as_sequential_ones(dev, oracle_mod, layout, dtype, mixed, shape):
     """Register-cache instances without modulation look up the stage fields
     in pairs, both cells' loads in flight together; modulated instances look
     them up one at a time.  With a modulation of ones the two give the same
     bits and the same number of cell loads: the pairs leave the cell cache as
     sequential lookups do, in the FP64 kernel (also bitwise equal to the
     oracle) and in the mixed one.  Steps of up to five cells (h_max 0.5 Mpc
-    on a 0.1 Mpc grid) put the two stages of a pair in different cells often."""
+    on a 0.1 Mpc grid) put the two stages of a pair in different cells often.
+    A shape takes a non-cubic block of the grid with sides that are not
+    powers of two, as a periodic grid of its own (cell indices wrap by
+    remainder there, not by mask)."""
     torch, crp = dev
     w = ci.get_config(0)
     fs, ps, _ = ci.config_seeds(0)
     B = ci.kolmogorov_field(w.grid_n, w.spacing, w.l_min, w.l_max, w.b_rms, fs)
+    if shape is not None:
+        B = np.ascontiguousarray(B[:shape[0], :shape[1], :shape[2]])
     B = B.astype(np.float32) if dtype == "f32" else B
     prec = crp.CRP_PREC_MIXED_F64ACC if mixed else crp.CRP_PREC_FP64
     P = ci.isotropic_particles(3000, 1e18, 3e19, (1, 2, 7, 26), ps)
     prm_kw = dict(tol=1e-4, h_min=1e-4, h_max=0.5, obs_radius=2.5, l_max=30.0)
-    _say(f"case: paired against sequential cached lookups, {layout} {dtype}, mixed {mixed}, 3000 nuclei")
+    _say(f"case: paired against sequential cached lookups, {layout} {dtype}, mixed {mixed}, grid {shape or 'cubic'}, "
+         "3000 nuclei")
     ones = crp.make_modulation(np.ones((7, 9, 11)), 0.31, origin=(-1.0, 0.2, 0.4))
     runs = []
     for mod in (None, ones):
